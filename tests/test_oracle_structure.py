@@ -1,0 +1,170 @@
+"""Pins for the oracle's structure analysis (Section 3).
+
+* Definition 1 on hand-built graphs whose leaf sets are worked out by hand.
+* Equation 2 / Theorem 2: the bound never exceeds the true minimum number of
+  groups found by brute force over all set partitions of small item lists.
+* Algorithm 3 on a hand-traced example; Algorithm 4 meets its bound.
+* Combined functions: selection probabilities of the combined functions sum to
+  one (Section 3.3), a one-node group reproduces the node's truth tables, and
+  each output bit depends only on its own member's chosen function.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import pbn_synth as ps
+from oracle import structure as so
+
+
+def graph(n, edges, self_loops=()):
+    """Single-predictor network where node v reads the listed parents."""
+    par = {v: [] for v in range(n)}
+    for a, b in edges:            # a is a parent of b
+        par[b].append(a)
+    for v in self_loops:
+        par[v].append(v)
+    fns = []
+    for v in range(n):
+        k = len(par[v])
+        fns.append([(1.0, par[v], [0] * (1 << k))])
+    return ps.assemble(n, 0.1, fns)
+
+
+def test_leaf_chain_collapses_to_interest():
+    net = graph(4, [(0, 1), (1, 2), (2, 3)])
+    assert so.leaf_nodes(net, [0]) == {1, 2, 3}
+    assert so.leaf_nodes(net, [2]) == {3}
+    assert so.leaf_nodes(net, [3]) == set()
+
+
+def test_leaf_self_loop_and_cycle_are_kept():
+    net = graph(5, [(0, 1), (1, 0), (0, 2), (3, 4)], self_loops=[3])
+    # 2 and 4 are sinks; 0-1 is a cycle; 3 reads itself
+    assert so.leaf_nodes(net, []) == {2, 4}
+
+
+def test_leaf_interest_sink_is_kept():
+    net = graph(3, [(0, 1), (0, 2)])
+    assert so.leaf_nodes(net, [2]) == {1}
+    assert so.leaf_nodes(net, []) == {0, 1, 2}
+
+
+def set_partitions(items):
+    if not items:
+        yield []
+        return
+    first, rest = items[0], items[1:]
+    for part in set_partitions(rest):
+        for k in range(len(part)):
+            yield part[:k] + [[first] + part[k]] + part[k + 1:]
+        yield [[first]] + part
+
+
+def true_min_groups(weights, theta):
+    best = None
+    for part in set_partitions(list(range(len(weights)))):
+        total = sum(int(np.prod([weights[i] for i in g])) for g in part)
+        if total <= theta and (best is None or len(part) < best):
+            best = len(part)
+    return best
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_eq2_is_a_lower_bound(seed):
+    rng = np.random.default_rng(seed)
+    k = int(rng.integers(1, 7))
+    w = [int(x) for x in rng.integers(2, 6, size=k)]
+    theta = int(rng.integers(2, 200))
+    mhat = so.eq2_lower_bound(w, theta)
+    m_true = true_min_groups(w, theta)
+    if m_true is not None:
+        assert mhat is not None and mhat <= m_true
+    if mhat is not None:
+        # by definition m-hat satisfies Eq. 2 and m-hat - 1 does not
+        W = int(np.prod(w))
+        assert W * mhat ** mhat <= theta ** mhat
+        if mhat > 1:
+            assert W * (mhat - 1) ** (mhat - 1) > theta ** (mhat - 1)
+
+
+def test_eq2_worked_values():
+    # four nodes with 2 predictors each: W = 16.  theta = 8: m = 2 gives 2*4 = 8.
+    assert so.eq2_lower_bound([2, 2, 2, 2], 8) == 2
+    # min over m of m * 16^(1/m) is about 7.54 (m = 3): theta = 7 admits no m
+    assert so.eq2_lower_bound([2, 2, 2, 2], 7) is None
+    # eight nodes: W = 256; m = 4 gives 4 * 4 = 16, m = 3 gives 19.05
+    assert so.eq2_lower_bound([2] * 8, 16) == 4
+    assert so.eq2_lower_bound([2] * 8, 15) is None
+    assert so.eq2_lower_bound([2, 2, 2, 2], 16) == 1
+
+
+def test_find_partitions_hand_trace():
+    items = [(10, 3), (11, 2), (12, 4), (13, 2), (14, 3)]
+    # sorted: 12(4) 10(3) 14(3) 11(2) 13(2); groups start empty (weight 0)
+    # 12 -> g0 [4]; 10 -> g1 [3]; 14 -> g1? no: g1=3 < g0=4 -> g1 [9];
+    # 11 -> g0 [8]; 13 -> g0 (8 < 9) [16]
+    assert so.find_partitions(items, 2) == [[12, 11, 13], [10, 14]]
+
+
+def test_partition_multi_meets_theta_or_stops_at_singletons():
+    rng = np.random.default_rng(2)
+    for _ in range(50):
+        k = int(rng.integers(1, 12))
+        items = [(i, int(rng.integers(2, 5))) for i in range(k)]
+        theta = int(rng.integers(4, 300))
+        groups = so.partition_multi(items, theta)
+        assert sorted(v for g in groups for v in g) == list(range(k))
+        w = dict(items)
+        total = sum(int(np.prod([w[v] for v in g])) for g in groups)
+        assert total <= theta or len(groups) == k
+        mhat = so.eq2_lower_bound([x for _, x in items], theta)
+        if mhat is not None:
+            assert len(groups) >= min(mhat, k)
+
+
+def test_group_single_respects_caps_and_prefers_shared_parents():
+    parents = {0: [5, 6], 1: [7, 8], 2: [5, 6, 9], 3: [7], 4: [1, 2, 3, 4]}
+    groups = so.group_single([0, 1, 2, 3, 4], parents, max_nodes=2, max_bits=3)
+    assert groups[0] == [0, 2]          # shares {5, 6}
+    assert groups[1] == [1, 3]          # shares {7}
+    assert groups[2] == [4]             # union cap
+    for g in groups:
+        assert len(g) <= 2
+        assert len(set().union(*[parents[v] for v in g])) <= 3 or len(g) == 1
+
+
+def test_combined_table_probabilities_and_members():
+    net = ps.random_pbn(6, 0.1, 5, nfn=lambda r: int(r.integers(1, 4)),
+                        nparents=lambda r: int(r.integers(1, 4)))
+    members = [1, 3, 4]
+    union, table = so.combined_table(net, members)
+    fns = [so.node_functions(net, v) for v in members]
+    probs = [net["sel_prob"][net["fn_off"][v]:net["fn_off"][v + 1]] for v in members]
+    total = sum(np.prod(c) for c in itertools.product(*probs))
+    assert abs(total - 1.0) < 1e-12
+    radix = [len(f) for f in fns]
+    assert table.shape == (int(np.prod(radix)), 1 << len(union))
+    rng = np.random.default_rng(0)
+    for _ in range(200):
+        digits = [int(rng.integers(0, r)) for r in radix]
+        c = 0
+        for d, r in zip(digits, radix):
+            c = c * r + d
+        x = int(rng.integers(0, 1 << len(union)))
+        vals = {p: (x >> b) & 1 for b, p in enumerate(union)}
+        for k, (fl, j) in enumerate(zip(fns, digits)):
+            pa, bits = fl[j]
+            idx = sum(vals[p] << b for b, p in enumerate(pa))
+            assert (int(table[c, x]) >> k) & 1 == bits[idx]
+
+
+def test_combined_table_of_one_node_is_its_truth_tables():
+    net = ps.assemble(3, 0.1, [[(0.5, [2, 0], [0, 1, 1, 0]), (0.5, [1], [1, 0])],
+                               [(1.0, [0], [0, 1])], [(1.0, [1], [1, 1])]])
+    union, table = so.combined_table(net, [0])
+    assert union == [0, 1, 2]
+    for x in range(8):
+        s0, s1, s2 = x & 1, (x >> 1) & 1, (x >> 2) & 1
+        assert table[0, x] == [0, 1, 1, 0][s2 | (s0 << 1)]
+        assert table[1, x] == [1, 0][s1]
