@@ -1,0 +1,282 @@
+/*
+ * pbn.h -- C ABI of the MI355X probabilistic Boolean network (PBN) simulator.
+ *
+ * Method: Mizera, Pang, Yuan, "Fast Simulation of Probabilistic Boolean
+ * Networks" (arXiv:1605.00854).  The library simulates long trajectories of an
+ * independent-synchronous PBN with perturbations (Section 2.1, Eq. 1) after the
+ * paper's structure-based preparation: leaf-node reduction (Section 3.1,
+ * Definition 1) and node grouping into combined predictor functions
+ * (Section 3.3, Algorithms 3-4), assembled as in Algorithm 5.  Hit counters of
+ * queried state sets feed the steady-state estimate (Section 4.2).
+ *
+ * Conventions
+ *   - Every call returns pbn_status: PBN_OK (0) or a negative error code.
+ *     pbn_last_error() returns a thread-local message for the last failure.
+ *     No C++ exception or abort crosses this boundary.
+ *   - Host arrays passed in are owned by the caller and copied; the library
+ *     keeps no pointer to them after the call returns.
+ *   - Opaque objects (pbn_net, pbn_plan) are owned by the library and freed by
+ *     the matching *_destroy call (destroying NULL is a no-op).
+ *   - Device buffers (d_*) are allocated by the caller on the current HIP
+ *     device and passed as raw device pointers.  `stream` is a hipStream_t
+ *     (NULL = legacy default stream).  Device calls only enqueue work; they do
+ *     not synchronise.  Launch errors are reported through the return code.
+ *
+ * Random-number contract (the paper leaves the generator unspecified; this
+ * fixed reading makes every trajectory a pure function of (seed, trajectory)):
+ *   Philox4x32-10 with key = seed and counter (trajectory, step, index, stream),
+ *   streams INIT = 1, PERT = 2, SEL = 3.  Perturbations of all n original nodes
+ *   are drawn by a geometric skip chain over the integer table
+ *   Q[h] = floor(v_h 2^64), v_h = fl(v_{h-1} fl(1 - p)); predictor selection of a
+ *   node with l >= 2 predictors uses word (r & 3) of the SEL call with index
+ *   r >> 2 (r = its rank among multi-predictor nodes of the full network)
+ *   against thresholds CUM[m] = min(2^32 - 1, floor(S_m 2^32 + 1/2)).
+ *   Reduction and grouping never change a kept node's trajectory.
+ */
+#ifndef PBN_H
+#define PBN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pbn_status;
+
+#define PBN_OK        0
+#define PBN_EINVAL   -1   /* bad argument or malformed network                  */
+#define PBN_ENOMEM   -2   /* host allocation failed                             */
+#define PBN_ELIMIT   -3   /* input exceeds a documented limit of this library   */
+#define PBN_ELDS     -4   /* plan cannot be laid out within the device limits   */
+#define PBN_EHIP     -5   /* a HIP runtime call or kernel launch failed         */
+#define PBN_ERANGE   -6   /* step or trajectory counter would overflow 32 bits  */
+#define PBN_ENODEV   -7   /* no HIP device                                      */
+
+/* Library limits. */
+#define PBN_MAX_NODES          16000   /* nodes per network                      */
+#define PBN_MAX_PREDICTORS         4   /* predictor functions per node, l(i)     */
+#define PBN_MAX_FN_PARENTS        16   /* parents of one predictor function      */
+#define PBN_MAX_GROUP_NODES        4   /* nodes per combined group               */
+#define PBN_MAX_GROUP_PARENTS     16   /* parent bits indexing one group table   */
+#define PBN_MAX_PAIRS             64   /* (node, value) pairs over all targets   */
+
+/* Last error message of the calling thread ("" if none). */
+const char* pbn_last_error(void);
+
+/* ------------------------------------------------------------------ network
+ * A PBN G(X, F) (Section 2.1): n binary nodes; node i has l(i) >= 1 predictor
+ * functions with selection probabilities summing to 1; each predictor reads
+ * its own ordered parent list; every node flips with probability p per step.
+ *
+ *   n          number of nodes, 1 .. PBN_MAX_NODES
+ *   p          perturbation rate, 0 < p < 1 with 1 - p < 1 in double
+ *   fn_off     [n+1]  predictors of node i are fn_off[i] .. fn_off[i+1]-1;
+ *                     fn_off[0] = 0, 1 <= l(i) <= PBN_MAX_PREDICTORS
+ *   sel_prob   [NF]   selection probabilities, finite, >= 0, per-node sum
+ *                     within 1e-9 of 1 (NF = fn_off[n])
+ *   par_off    [NF+1] parents of predictor f are parents[par_off[f] .. par_off[f+1]-1]
+ *                     (0 .. PBN_MAX_FN_PARENTS of them)
+ *   parents    node ids < n; parent k is bit k of the truth-table index
+ *   tt_off     [NF+1] truth table of f is tt[tt_off[f] .. tt_off[f+1]-1], exactly
+ *                     max(1, 2^phi / 64) 64-bit words for phi parents
+ *   tt         LSB-first: the output for index j is bit (j % 64) of word j / 64;
+ *                     bits at or above 2^phi must be zero
+ * Errors: PBN_EINVAL (any rule above), PBN_ELIMIT (a limit), PBN_ENOMEM.
+ * The integer quantisation of p and of the selection probabilities is done
+ * here, once.
+ */
+typedef struct pbn_desc {
+  uint32_t n;
+  double p;
+  const uint32_t* fn_off;
+  const double* sel_prob;
+  const uint32_t* par_off;
+  const uint32_t* parents;
+  const uint32_t* tt_off;
+  const uint64_t* tt;
+} pbn_desc;
+
+typedef struct pbn_net pbn_net;
+typedef struct pbn_plan pbn_plan;
+
+pbn_status pbn_net_create(const pbn_desc* desc, pbn_net** out);
+pbn_status pbn_net_destroy(pbn_net* net);
+
+/* Integer tables of the random-number contract, for inspection and tests.
+ *   q      [n+1] Q[h] for h = 0..n (Q[0] = 0: the certain event, never compared)
+ *   cum    [3 n] thresholds of node i at cum[3 i + m], m < l(i) - 1; the unused
+ *                entries are 0xFFFFFFFF
+ *   rank   [n]   rank among nodes with >= 2 predictors, or -1                  */
+pbn_status pbn_net_tables(const pbn_net* net, uint64_t* q, uint32_t* cum, int32_t* rank);
+
+/* --------------------------------------------------------------------- plan
+ * Preparation (Algorithm 5): leaf-node reduction (Definition 1), node grouping
+ * (Equation 2, Algorithm 3, Algorithm 4, and grouping of single-predictor
+ * nodes by shared parents, Section 3.3), combined predictor tables, and the
+ * device layout.  `interest` lists the nodes of interest (every node a query
+ * will read); they are never removed.
+ *
+ * Options:
+ *   reduce             1: remove leaf nodes (their perturbations still force a
+ *                      perturbation-only step, as Algorithm 1 requires)
+ *   group              1: group nodes into combined tables; 0: one predictor
+ *                      evaluation per node
+ *   weight_mode        weight of a multi-predictor node in Algorithms 3-4:
+ *                      0 = l(i) (number of predictor functions, as in the paper),
+ *                      1 = l(i) * 2^|P_i| (entries of its table over the union
+ *                      P_i of its parents), so theta bounds table entries
+ *   theta              Algorithm 4 limit on the sum over groups of the product
+ *                      of member weights
+ *   lds_budget_bytes   bytes of plan image (records + tables) that may be
+ *                      staged in LDS; larger images stay in global memory
+ *   max_table_entries  cap on (product of l) * 2^|union parents| per group
+ *   max_parent_bits    cap on |union parents| per group (<= PBN_MAX_GROUP_PARENTS)
+ *   max_group_nodes    cap on nodes per group (<= PBN_MAX_GROUP_NODES)
+ * Errors: PBN_EINVAL (bad node id, bad option), PBN_ELIMIT (a node needs a
+ * table larger than max_table_entries), PBN_ELDS (layout exceeds device
+ * limits), PBN_ENOMEM.
+ */
+typedef struct pbn_plan_opts {
+  uint32_t reduce;
+  uint32_t group;
+  uint32_t weight_mode;
+  uint32_t lds_budget_bytes;
+  uint64_t theta;
+  uint32_t max_table_entries;
+  uint32_t max_parent_bits;
+  uint32_t max_group_nodes;
+  uint32_t reserved;
+} pbn_plan_opts;
+
+/* Defaults: reduce = 1, group = 1, weight_mode = 1, theta = 65536,
+ * lds_budget_bytes = 65536, max_table_entries = 4096, max_parent_bits = 12,
+ * max_group_nodes = 4. */
+void pbn_plan_opts_default(pbn_plan_opts* opts);
+
+pbn_status pbn_plan_build(const pbn_net* net, const uint32_t* interest, uint32_t n_interest,
+                          const pbn_plan_opts* opts, pbn_plan** out);
+pbn_status pbn_plan_destroy(pbn_plan* plan);
+
+typedef struct pbn_plan_info {
+  uint32_t n;               /* nodes of the original network                    */
+  uint32_t n_kept;          /* nodes after reduction (n')                        */
+  uint32_t n_slots;         /* evaluation slots: groups + single-node slots      */
+  uint32_t n_table_slots;   /* slots evaluated through a combined table          */
+  uint32_t n_passes;        /* ceil(n_slots / 64): lane passes per step          */
+  uint32_t state_words;     /* 32-bit words of one packed trajectory state       */
+  uint32_t n_jobs;          /* Philox calls per unperturbed step (1 + SEL blocks)*/
+  uint32_t image_bytes;     /* records + tables read by the step kernel          */
+  uint32_t table_bytes;     /* combined tables within the image                  */
+  uint32_t image_in_lds;    /* 1 if the image is staged in LDS                   */
+  uint32_t blob_bytes;      /* size of the exported device blob                  */
+  uint32_t max_fn_parents;  /* largest parent count of a predictor in FN slots   */
+  uint32_t max_union_bits;  /* largest |union parents| of a table slot           */
+  uint32_t n_multi_groups;  /* groups holding >= 2 multi-predictor nodes         */
+  uint32_t reserved[6];
+} pbn_plan_info;
+
+pbn_status pbn_plan_info_get(const pbn_plan* plan, pbn_plan_info* info);
+
+/* Bit position of every original node in the packed plan state, or
+ * 0xFFFFFFFF for a removed leaf.  pos: [n]. */
+pbn_status pbn_plan_node_pos(const pbn_plan* plan, uint32_t* pos);
+
+/* Slot of every original node (0xFFFFFFFF for leaves) and whether the slot is
+ * evaluated through a combined table.  slot: [n], is_table: [n_slots]. */
+pbn_status pbn_plan_slots(const pbn_plan* plan, uint32_t* slot, uint32_t* is_table);
+
+/* Groups found by Algorithm 4 on the multi-predictor kept nodes, before any
+ * device-limit split: flat member list and offsets (ngroups + 1 entries).
+ * Call with NULL buffers to query the sizes. */
+pbn_status pbn_plan_alg4_groups(const pbn_plan* plan, uint32_t* members, uint32_t* n_members,
+                                uint32_t* offsets, uint32_t* n_groups);
+
+/* Same for the grouping of single-predictor kept nodes by shared parents. */
+pbn_status pbn_plan_single_groups(const pbn_plan* plan, uint32_t* members, uint32_t* n_members,
+                                  uint32_t* offsets, uint32_t* n_groups);
+
+/* Equation 2: smallest m >= 1 with m * (prod w)^(1/m) <= theta, or 0 when no m
+ * satisfies it.  weights: [count] positive integers. */
+pbn_status pbn_eq2_lower_bound(const uint64_t* weights, uint32_t count, uint64_t theta,
+                               uint32_t* m_out);
+
+/* Copy the device blob of the plan into host_buf.  *bytes: in = capacity,
+ * out = size written (call with host_buf = NULL to query the size).  The
+ * caller uploads the blob into device memory it owns and passes that pointer
+ * as d_plan to the device calls below, together with the host plan. */
+pbn_status pbn_plan_export(const pbn_plan* plan, void* host_buf, size_t* bytes);
+
+/* ------------------------------------------------------------------ targets
+ * Target state sets (queried steady-state events): target t is the
+ * conjunction "node_k == value_k" over its pairs.  Built from original node
+ * ids; every node must be kept by the plan (list it as of interest).
+ *   node, value, target_of   [npairs] pair k belongs to target target_of[k]
+ *   ntargets                 1 .. 64; npairs <= PBN_MAX_PAIRS
+ * Errors: PBN_EINVAL (removed node, value not 0/1, empty target, bad counts). */
+typedef struct pbn_targets {
+  uint32_t ntargets;
+  uint32_t npairs;
+  uint32_t pos[PBN_MAX_PAIRS];    /* byte position of the pair's node in the step state */
+  uint32_t val[PBN_MAX_PAIRS];
+  uint64_t mask[64];              /* pairs of target t */
+} pbn_targets;
+
+pbn_status pbn_targets_build(const pbn_plan* plan, const uint32_t* node, const uint32_t* value,
+                             const uint32_t* target_of, uint32_t npairs, uint32_t ntargets,
+                             pbn_targets* out);
+
+/* ----------------------------------------------------------- device calls
+ * d_plan    device copy of pbn_plan_export(plan); must stay alive until the
+ *           enqueued work completes
+ * seed      64-bit Philox key
+ * traj0     id of the first trajectory; trajectories traj0 .. traj0+ntraj-1
+ * d_state   [ntraj][state_words] packed states in plan layout (bit = node at
+ *           pbn_plan_node_pos), read and written in place
+ *
+ * pbn_state_init: s(0) of every trajectory from the INIT stream.
+ * Errors: PBN_EINVAL, PBN_ERANGE (traj0 + ntraj > 2^32), PBN_EHIP.
+ */
+pbn_status pbn_state_init(const pbn_plan* plan, const void* d_plan, uint64_t seed, uint32_t traj0,
+                          uint32_t ntraj, uint32_t* d_state, void* stream);
+
+/* Launch tunables (0 = library choice). */
+typedef struct pbn_launch_opts {
+  uint32_t waves_per_block;       /* trajectories per workgroup, 1 .. 16      */
+  uint32_t reserved[3];
+} pbn_launch_opts;
+
+/* pbn_simulate: advance every trajectory by nsteps transitions of Eq. 1,
+ * global steps step0 .. step0+nsteps-1 (Algorithm 5's ParallelSimulation per
+ * step), and accumulate per-target counters of the states reached:
+ *   d_counts [ntargets][ntraj][3] uint64, added to (not overwritten):
+ *     [0] hits: transitions t >= count_from whose result s(t+1) is in the target
+ *     [1] 0->1 and [2] 1->0 changes of the hit indicator between consecutive
+ *         counted states (t >= count_from + 1), for the two-state chain estimate.
+ * Chunked calls (step0 advancing) give the same bits as one call.
+ * Errors: PBN_EINVAL, PBN_ERANGE (step0 + nsteps >= 2^32), PBN_EHIP. */
+pbn_status pbn_simulate(const pbn_plan* plan, const void* d_plan, uint64_t seed, uint32_t traj0,
+                        uint32_t ntraj, uint32_t step0, uint32_t nsteps, uint32_t count_from,
+                        const pbn_targets* targets, uint32_t* d_state, uint64_t* d_counts,
+                        const pbn_launch_opts* launch, void* stream);
+
+/* The plain per-node kernel (the paper's Method_old when the plan was built
+ * with reduce = 0 and group = 0; Method_reduction with reduce = 1): same
+ * contract, a step kernel compiled without combined-table evaluation.
+ * Errors as pbn_simulate, and PBN_EINVAL if the plan holds table slots. */
+pbn_status pbn_simulate_plain(const pbn_plan* plan, const void* d_plan, uint64_t seed,
+                              uint32_t traj0, uint32_t ntraj, uint32_t step0, uint32_t nsteps,
+                              uint32_t count_from, const pbn_targets* targets, uint32_t* d_state,
+                              uint64_t* d_counts, const pbn_launch_opts* launch, void* stream);
+
+/* Unpack plan-layout states to original node order: d_out [ntraj][ceil(n/32)]
+ * words, bit i = node i; removed leaves read 0. */
+pbn_status pbn_state_to_original(const pbn_plan* plan, const void* d_plan, const uint32_t* d_state,
+                                 uint32_t ntraj, uint32_t* d_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PBN_H */

@@ -112,6 +112,10 @@ def partition_multi(items, theta):
     if not items:
         return []
     weight = dict(items)
+    if sum(w for _, w in items) > theta:
+        # weights are >= 2, so a * b >= a + b: merging never lowers the sum and
+        # no m below one group per item can meet theta
+        return find_partitions(items, len(items))
     m0 = eq2_lower_bound([w for _, w in items], theta)
     m = len(items) if m0 is None else min(max(1, m0), len(items))
     while True:

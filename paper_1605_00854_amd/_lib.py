@@ -1,0 +1,103 @@
+"""ctypes declarations of the C ABI in include/pbn.h (argument marshalling only)."""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpbn_amd.so")
+
+MAX_PAIRS = 64
+
+OK, EINVAL, ENOMEM, ELIMIT, ELDS, EHIP, ERANGE, ENODEV = 0, -1, -2, -3, -4, -5, -6, -7
+_NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", ELIMIT: "ELIMIT", ELDS: "ELDS", EHIP: "EHIP",
+          ERANGE: "ERANGE", ENODEV: "ENODEV"}
+
+
+class PbnError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class pbn_desc(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("p", C.c_double),
+                ("fn_off", C.POINTER(C.c_uint32)), ("sel_prob", C.POINTER(C.c_double)),
+                ("par_off", C.POINTER(C.c_uint32)), ("parents", C.POINTER(C.c_uint32)),
+                ("tt_off", C.POINTER(C.c_uint32)), ("tt", C.POINTER(C.c_uint64))]
+
+
+class pbn_plan_opts(C.Structure):
+    _fields_ = [("reduce", C.c_uint32), ("group", C.c_uint32), ("weight_mode", C.c_uint32),
+                ("lds_budget_bytes", C.c_uint32), ("theta", C.c_uint64),
+                ("max_table_entries", C.c_uint32), ("max_parent_bits", C.c_uint32),
+                ("max_group_nodes", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class pbn_plan_info(C.Structure):
+    _fields_ = [(name, C.c_uint32) for name in (
+        "n", "n_kept", "n_slots", "n_table_slots", "n_passes", "state_words", "n_jobs",
+        "image_bytes", "table_bytes", "image_in_lds", "blob_bytes", "max_fn_parents",
+        "max_union_bits", "n_multi_groups")] + [("reserved", C.c_uint32 * 6)]
+
+
+class pbn_targets(C.Structure):
+    _fields_ = [("ntargets", C.c_uint32), ("npairs", C.c_uint32),
+                ("pos", C.c_uint32 * MAX_PAIRS), ("val", C.c_uint32 * MAX_PAIRS),
+                ("mask", C.c_uint64 * 64)]
+
+
+class pbn_launch_opts(C.Structure):
+    _fields_ = [("waves_per_block", C.c_uint32), ("reserved", C.c_uint32 * 3)]
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_P = C.c_void_p
+_U32, _U64, _SZ = C.c_uint32, C.c_uint64, C.c_size_t
+_pU32, _pU64, _pI32 = C.POINTER(C.c_uint32), C.POINTER(C.c_uint64), C.POINTER(C.c_int32)
+SIGNATURES = {
+    "pbn_last_error": (C.c_char_p, []),
+    "pbn_net_create": (C.c_int32, [C.POINTER(pbn_desc), C.POINTER(_P)]),
+    "pbn_net_destroy": (C.c_int32, [_P]),
+    "pbn_net_tables": (C.c_int32, [_P, _pU64, _pU32, _pI32]),
+    "pbn_plan_opts_default": (None, [C.POINTER(pbn_plan_opts)]),
+    "pbn_plan_build": (C.c_int32, [_P, _pU32, _U32, C.POINTER(pbn_plan_opts), C.POINTER(_P)]),
+    "pbn_plan_destroy": (C.c_int32, [_P]),
+    "pbn_plan_info_get": (C.c_int32, [_P, C.POINTER(pbn_plan_info)]),
+    "pbn_plan_node_pos": (C.c_int32, [_P, _pU32]),
+    "pbn_plan_slots": (C.c_int32, [_P, _pU32, _pU32]),
+    "pbn_plan_alg4_groups": (C.c_int32, [_P, _pU32, _pU32, _pU32, _pU32]),
+    "pbn_plan_single_groups": (C.c_int32, [_P, _pU32, _pU32, _pU32, _pU32]),
+    "pbn_eq2_lower_bound": (C.c_int32, [_pU64, _U32, _U64, _pU32]),
+    "pbn_plan_export": (C.c_int32, [_P, _P, C.POINTER(_SZ)]),
+    "pbn_targets_build": (C.c_int32, [_P, _pU32, _pU32, _pU32, _U32, _U32, C.POINTER(pbn_targets)]),
+    "pbn_state_init": (C.c_int32, [_P, _P, _U64, _U32, _U32, _P, _P]),
+    "pbn_simulate": (C.c_int32, [_P, _P, _U64, _U32, _U32, _U32, _U32, _U32,
+                                 C.POINTER(pbn_targets), _P, _P, C.POINTER(pbn_launch_opts), _P]),
+    "pbn_simulate_plain": (C.c_int32, [_P, _P, _U64, _U32, _U32, _U32, _U32, _U32,
+                                       C.POINTER(pbn_targets), _P, _P, C.POINTER(pbn_launch_opts), _P]),
+    "pbn_state_to_original": (C.c_int32, [_P, _P, _P, _U32, _P, _P]),
+}
+
+
+def lib():
+    """The loaded library.  Raises if it was not built: there is no fallback."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
+                              "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(code):
+    if code != OK:
+        msg = lib().pbn_last_error().decode(errors="replace")
+        raise PbnError(code, msg)
+    return code

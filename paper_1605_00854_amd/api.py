@@ -1,0 +1,221 @@
+"""Python binding of the PBN simulator (marshalling only: every step of the
+simulation runs in the library's HIP kernels).
+
+Device memory and streams come from PyTorch: buffers are torch tensors on the
+current HIP device and launches go to torch's current stream.
+"""
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import check, lib
+
+
+def _ptr(arr, ctype):
+    return arr.ctypes.data_as(C.POINTER(ctype))
+
+
+class Net:
+    """A validated, quantised PBN (pbn_net_create)."""
+
+    def __init__(self, net):
+        self.desc_dict = net
+        self.n = int(net["n"])
+        arrs = {
+            "fn_off": np.ascontiguousarray(net["fn_off"], dtype=np.uint32),
+            "sel_prob": np.ascontiguousarray(net["sel_prob"], dtype=np.float64),
+            "par_off": np.ascontiguousarray(net["par_off"], dtype=np.uint32),
+            "parents": np.ascontiguousarray(net["parents"], dtype=np.uint32),
+            "tt_off": np.ascontiguousarray(net["tt_off"], dtype=np.uint32),
+            "tt": np.ascontiguousarray(net["tt"], dtype=np.uint64),
+        }
+        if arrs["parents"].size == 0:
+            arrs["parents"] = np.zeros(1, dtype=np.uint32)
+        d = _lib.pbn_desc(self.n, float(net["p"]), _ptr(arrs["fn_off"], C.c_uint32),
+                          _ptr(arrs["sel_prob"], C.c_double), _ptr(arrs["par_off"], C.c_uint32),
+                          _ptr(arrs["parents"], C.c_uint32), _ptr(arrs["tt_off"], C.c_uint32),
+                          _ptr(arrs["tt"], C.c_uint64))
+        h = C.c_void_p()
+        check(lib().pbn_net_create(C.byref(d), C.byref(h)))
+        self.handle = h
+
+    def tables(self):
+        """(Q[0..n], cum[n,3], rank[n]) of the random-number contract."""
+        q = np.zeros(self.n + 1, dtype=np.uint64)
+        cum = np.zeros(3 * self.n, dtype=np.uint32)
+        rank = np.zeros(self.n, dtype=np.int32)
+        check(lib().pbn_net_tables(self.handle, _ptr(q, C.c_uint64), _ptr(cum, C.c_uint32),
+                                   _ptr(rank, C.c_int32)))
+        return q, cum.reshape(self.n, 3), rank
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib._lib is not None:
+            _lib._lib.pbn_net_destroy(h)
+            self.handle = None
+
+
+def default_opts():
+    o = _lib.pbn_plan_opts()
+    lib().pbn_plan_opts_default(C.byref(o))
+    return o
+
+
+class Plan:
+    """Prepared network (Algorithm 5's Preparation) and its device blob."""
+
+    def __init__(self, net, interest=(), **opts):
+        self.net = net if isinstance(net, Net) else Net(net)
+        o = default_opts()
+        for k, v in opts.items():
+            if not hasattr(o, k):
+                raise TypeError(f"unknown plan option {k}")
+            setattr(o, k, int(v))
+        self.opts = o
+        ints = np.ascontiguousarray(sorted(set(int(x) for x in interest)), dtype=np.uint32)
+        if ints.size == 0:
+            ints = np.zeros(1, dtype=np.uint32)
+            nint = 0
+        else:
+            nint = ints.size
+        h = C.c_void_p()
+        check(lib().pbn_plan_build(self.net.handle, _ptr(ints, C.c_uint32), nint, C.byref(o), C.byref(h)))
+        self.handle = h
+        info = _lib.pbn_plan_info()
+        check(lib().pbn_plan_info_get(h, C.byref(info)))
+        self.info = {name: getattr(info, name) for name, _ in info._fields_ if name != "reserved"}
+        self._dev = None
+
+    @property
+    def n(self):
+        return self.info["n"]
+
+    def node_pos(self):
+        pos = np.zeros(self.n, dtype=np.uint32)
+        check(lib().pbn_plan_node_pos(self.handle, _ptr(pos, C.c_uint32)))
+        return pos
+
+    def slots(self):
+        slot = np.zeros(self.n, dtype=np.uint32)
+        is_table = np.zeros(max(1, self.info["n_slots"]), dtype=np.uint32)
+        check(lib().pbn_plan_slots(self.handle, _ptr(slot, C.c_uint32), _ptr(is_table, C.c_uint32)))
+        return slot, is_table[: self.info["n_slots"]]
+
+    def _groups(self, fn):
+        nm, ng = C.c_uint32(), C.c_uint32()
+        check(fn(self.handle, None, C.byref(nm), None, C.byref(ng)))
+        mem = np.zeros(max(1, nm.value), dtype=np.uint32)
+        off = np.zeros(ng.value + 1, dtype=np.uint32)
+        check(fn(self.handle, _ptr(mem, C.c_uint32), C.byref(nm), _ptr(off, C.c_uint32), C.byref(ng)))
+        return [mem[off[i]:off[i + 1]].tolist() for i in range(ng.value)]
+
+    def alg4_groups(self):
+        return self._groups(lib().pbn_plan_alg4_groups)
+
+    def single_groups(self):
+        return self._groups(lib().pbn_plan_single_groups)
+
+    def blob(self):
+        size = C.c_size_t()
+        check(lib().pbn_plan_export(self.handle, None, C.byref(size)))
+        buf = np.zeros(size.value, dtype=np.uint8)
+        check(lib().pbn_plan_export(self.handle, buf.ctypes.data_as(C.c_void_p), C.byref(size)))
+        return buf
+
+    def device(self):
+        """Device copy of the blob (torch uint8 tensor on the current device)."""
+        if self._dev is None:
+            import torch
+            self._dev = torch.from_numpy(self.blob()).to("cuda")
+        return self._dev
+
+    def targets(self, target_sets):
+        """pbn_targets for a list of target sets, each a list of (node, value)."""
+        node, val, tof = [], [], []
+        for t, tg in enumerate(target_sets):
+            for a, b in tg:
+                node.append(a)
+                val.append(b)
+                tof.append(t)
+        out = _lib.pbn_targets()
+        node = np.asarray(node, dtype=np.uint32)
+        val = np.asarray(val, dtype=np.uint32)
+        tof = np.asarray(tof, dtype=np.uint32)
+        check(lib().pbn_targets_build(self.handle, _ptr(node, C.c_uint32), _ptr(val, C.c_uint32),
+                                      _ptr(tof, C.c_uint32), node.size, len(target_sets), C.byref(out)))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib._lib is not None:
+            _lib._lib.pbn_plan_destroy(h)
+            self.handle = None
+
+
+def eq2_lower_bound(weights, theta):
+    w = np.ascontiguousarray(weights, dtype=np.uint64)
+    if w.size == 0:
+        w = np.zeros(1, dtype=np.uint64)
+        cnt = 0
+    else:
+        cnt = w.size
+    m = C.c_uint32()
+    check(lib().pbn_eq2_lower_bound(_ptr(w, C.c_uint64), cnt, int(theta), C.byref(m)))
+    return m.value or None
+
+
+# ------------------------------------------------------------------ device
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def new_state(plan, ntraj):
+    import torch
+    return torch.zeros((ntraj, plan.info["state_words"]), dtype=torch.int32, device="cuda")
+
+
+def new_counts(ntargets, ntraj):
+    import torch
+    return torch.zeros((ntargets, ntraj, 3), dtype=torch.int64, device="cuda")
+
+
+def state_init(plan, seed, ntraj, traj0=0, state=None, stream=None):
+    state = new_state(plan, ntraj) if state is None else state
+    check(lib().pbn_state_init(plan.handle, _dptr(plan.device()), int(seed), int(traj0), int(ntraj),
+                               _dptr(state), _stream(stream)))
+    return state
+
+
+def simulate(plan, seed, state, counts, targets, step0, nsteps, *, traj0=0, count_from=0, plain=False,
+             waves_per_block=0, stream=None):
+    """Advance trajectories traj0 .. traj0+ntraj-1 by nsteps (global steps step0..)."""
+    ntraj = state.shape[0]
+    lo = _lib.pbn_launch_opts(int(waves_per_block))
+    fn = lib().pbn_simulate_plain if plain else lib().pbn_simulate
+    check(fn(plan.handle, _dptr(plan.device()), int(seed), int(traj0), int(ntraj), int(step0), int(nsteps),
+             int(count_from), C.byref(targets), _dptr(state), _dptr(counts), C.byref(lo), _stream(stream)))
+    return state, counts
+
+
+def to_original(plan, state, stream=None):
+    import torch
+    ntraj = state.shape[0]
+    out = torch.zeros((ntraj, (plan.n + 31) // 32), dtype=torch.int32, device="cuda")
+    check(lib().pbn_state_to_original(plan.handle, _dptr(plan.device()), _dptr(state), int(ntraj),
+                                      _dptr(out), _stream(stream)))
+    return out
+
+
+def unpack_bits(words, n):
+    """Host helper: [ntraj, W] int32 words -> uint8 [ntraj, n] node values."""
+    w = np.asarray(words).astype(np.uint32)
+    bits = ((w[:, :, None] >> np.arange(32, dtype=np.uint32)) & 1).astype(np.uint8)
+    return bits.reshape(w.shape[0], -1)[:, :n]

@@ -1,0 +1,453 @@
+// device.hip -- HIP kernels for gfx950 and their C-ABI launchers.
+//
+// Step kernel (Algorithm 5's ParallelSimulation, Eq. 1 semantics): one
+// wavefront advances one trajectory.  Per step:
+//   * Philox calls of the step (one PERT call plus one SEL call per rank block
+//     holding a kept multi-predictor node) are spread over the 64 lanes; when a
+//     step needs <= 32 calls, one fill computes several future steps at once.
+//     Results go to a per-wave ring in LDS.
+//   * The first PERT word decides, wave-uniformly, whether any of the n
+//     original nodes is perturbed (u >= Q[n]).  If so, the skip chain walks
+//     the perturbed nodes (ballot counting over Q, radix 64), flips the kept
+//     ones in place, and no predictor is applied (Eq. 1, Algorithm 5).  Leaf
+//     perturbations only make the step perturbation-only (Algorithm 1's role).
+//   * Otherwise each lane evaluates its slot(s): an FN slot selects its
+//     predictor from its SEL word and integer thresholds and looks up the
+//     predictor's truth table over its parents; a TABLE slot combines the
+//     choices of its multi-predictor members into the combined-function index
+//     and reads one byte of the group's combined table (Section 3.3).  Results
+//     are written to the other state buffer (synchronous update).
+//   * Target hits: lanes holding target pairs compare the new state, a ballot
+//     collects mismatches, lane t counts hits of target t.
+// The state of a trajectory lives in LDS as one 32-bit word per slot (one byte
+// per member node); plan records and tables are staged in LDS when they fit.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <string>
+
+#include "internal.h"
+
+namespace {
+
+constexpr uint32_t kW0 = 0x9E3779B9u, kW1 = 0xBB67AE85u;
+constexpr uint32_t kM0 = 0xD2511F53u, kM1 = 0xCD9E8D57u;
+
+// Philox4x32-10 (Salmon et al., SC'11): counter (c0..c3), key (k0, k1).
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += kW0;
+      k1 += kW1;
+    }
+    const uint64_t p0 = uint64_t(kM0) * c0;
+    const uint64_t p1 = uint64_t(kM1) * c2;
+    const uint32_t n0 = uint32_t(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = uint32_t(p0 >> 32) ^ c3 ^ k1;
+    c1 = uint32_t(p1);
+    c3 = uint32_t(p0);
+    c0 = n0;
+    c2 = n2;
+  }
+  return make_uint4(c0, c1, c2, c3);
+}
+
+// Order LDS traffic between lanes of one wavefront (no hardware barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+struct SimParams {
+  const uint8_t* blob;
+  uint32_t* state;
+  unsigned long long* counts;
+  unsigned long long seed;
+  uint32_t traj0, ntraj, step0, nsteps, count_from;
+  uint32_t wpb;
+  uint32_t wave_bytes;   // LDS bytes per wave: two state buffers + ring
+  uint32_t pad;
+  pbn_targets tg;
+};
+
+template <bool IMG_LDS, bool TABLES>
+__global__ void __launch_bounds__(1024) k_simulate(SimParams a) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  const pbn_plan_header* H = reinterpret_cast<const pbn_plan_header*>(a.blob);
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wave = threadIdx.x >> 6;
+  const uint32_t n = H->n, nslots = H->n_slots, npass = H->n_passes, njobs = H->n_jobs;
+  const uint32_t fill = H->fill_steps, sd = H->state_dwords, zero_pos = H->zero_pos;
+  const uint32_t sdp = (sd + 3u) & ~3u;   // state buffer, padded to 16 bytes
+  const uint32_t img_bytes = H->image_bytes;
+  const uint8_t* gimg = a.blob + H->image_off;
+  const pbn_pass_info* pinfo = reinterpret_cast<const pbn_pass_info*>(a.blob + H->pass_off);
+  const unsigned long long* Q = reinterpret_cast<const unsigned long long*>(a.blob + H->q_off);
+  const uint32_t* o2p = reinterpret_cast<const uint32_t*>(a.blob + H->o2p_off);
+  const uint32_t* blk = reinterpret_cast<const uint32_t*>(a.blob + H->blk_off);
+
+  uint32_t img_lds = 0;
+  if constexpr (IMG_LDS) {
+    for (uint32_t o = threadIdx.x * 16u; o < img_bytes; o += blockDim.x * 16u)
+      *reinterpret_cast<uint4*>(smem + o) = *reinterpret_cast<const uint4*>(gimg + o);
+    img_lds = (img_bytes + 15u) & ~15u;
+  }
+  const uint8_t* img;
+  if constexpr (IMG_LDS)
+    img = smem;
+  else
+    img = gimg;
+  uint8_t* wb = smem + img_lds + wave * a.wave_bytes;
+  uint32_t* sbuf0 = reinterpret_cast<uint32_t*>(wb);
+  uint32_t* sbuf1 = reinterpret_cast<uint32_t*>(wb + 4u * sdp);
+  uint4* ring = reinterpret_cast<uint4*>(wb + 8u * sdp);
+  __syncthreads();
+  const uint32_t tl = blockIdx.x * a.wpb + wave;
+  if (tl >= a.ntraj) return;
+  const uint32_t traj = a.traj0 + tl;
+  const uint32_t k0 = uint32_t(a.seed), k1 = uint32_t(a.seed >> 32);
+
+  // unpack the packed state (bit 4 s + k) into one byte per member
+  const uint32_t W = H->state_words;
+  uint32_t* gst = a.state + size_t(tl) * W;
+  for (uint32_t s = lane; s < sd; s += 64u) {
+    uint32_t v = 0;
+    if (s < nslots) {
+      const uint32_t nib = (gst[s >> 3] >> ((s & 7u) * 4u)) & 0xFu;
+      v = (nib * 0x204081u) & 0x01010101u;
+    }
+    sbuf0[s] = v;
+    sbuf1[s] = 0;
+  }
+  wave_sync();
+
+  // targets: lane k holds pair k; lane t counts target t
+  const uint32_t npairs = a.tg.npairs, ntg = a.tg.ntargets;
+  const uint32_t my_pos = lane < npairs ? a.tg.pos[lane] : zero_pos;
+  const uint32_t my_val = lane < npairs ? a.tg.val[lane] : 0u;
+  const unsigned long long my_mask = lane < ntg ? a.tg.mask[lane] : 0ull;
+  auto target_z = [&](const uint8_t* s) -> bool {
+    const uint32_t b = s[my_pos];
+    const unsigned long long mism = __ballot(lane < npairs && b != my_val);
+    return (mism & my_mask) == 0ull;
+  };
+
+  // fixed Philox job of this lane when one fill covers several steps
+  const bool small_jobs = njobs <= 64u;
+  uint32_t my_s = 0, my_c2 = 0, my_c3 = PBN_STREAM_PERT;
+  if (small_jobs) {
+    const uint32_t j = lane % njobs;
+    my_s = lane / njobs;
+    my_c2 = j ? blk[j - 1] : 0u;
+    my_c3 = j ? PBN_STREAM_SEL : PBN_STREAM_PERT;
+  }
+  uint32_t stride0 = 1;
+  while (stride0 * 64u < n) stride0 *= 64u;
+  const unsigned long long Qn = Q[n];
+
+  uint32_t cur = 0;
+  bool zp = target_z(reinterpret_cast<const uint8_t*>(sbuf0));
+  uint32_t hits = 0, n01 = 0, n10 = 0;
+  uint32_t t = a.step0;
+  const uint32_t tend = a.step0 + a.nsteps;
+  while (t < tend) {
+    const uint32_t scount = small_jobs ? min(fill, tend - t) : 1u;
+    if (small_jobs) {
+      if (lane < scount * njobs) ring[lane] = philox(traj, t + my_s, my_c2, my_c3, k0, k1);
+    } else {
+      for (uint32_t j = lane; j < njobs; j += 64u)
+        ring[j] = philox(traj, t, j ? blk[j - 1] : 0u, j ? PBN_STREAM_SEL : PBN_STREAM_PERT, k0, k1);
+    }
+    wave_sync();
+    for (uint32_t s = 0; s < scount; ++s, ++t) {
+      const uint8_t* rs = reinterpret_cast<const uint8_t*>(ring + s * njobs);
+      const uint4 pr = *reinterpret_cast<const uint4*>(rs);
+      unsigned long long u = (static_cast<unsigned long long>(uniform(pr.y)) << 32) | uniform(pr.x);
+      uint32_t* cs = cur ? sbuf1 : sbuf0;
+      if (u >= Qn) {
+        // perturbation-only step: walk the skip chain over all n original nodes
+        uint8_t* csb = reinterpret_cast<uint8_t*>(cs);
+        uint32_t j0 = 0;
+        for (;;) {
+          uint32_t base = 0;
+          for (uint32_t st = stride0;; st /= 64u) {
+            const uint32_t h = base + st * (lane + 1u);
+            const bool gt = h <= n && Q[h] > u;
+            base += st * uint32_t(__popcll(__ballot(gt)));
+            if (st == 1u) break;
+          }
+          const uint32_t C = uniform(base);
+          if (C >= n - j0) break;
+          const uint32_t i = j0 + C;
+          const uint32_t pos = o2p[i];
+          if (pos != PBN_NONE && lane == 0) csb[pos] ^= 1u;
+          j0 = i + 1u;
+          if (j0 >= n) break;
+          const uint4 x = philox(traj, t, j0, PBN_STREAM_PERT, k0, k1);
+          u = (static_cast<unsigned long long>(uniform(x.y)) << 32) | uniform(x.x);
+        }
+        wave_sync();
+      } else {
+        const uint8_t* csb = reinterpret_cast<const uint8_t*>(cs);
+        uint32_t* ns = cur ? sbuf0 : sbuf1;
+        for (uint32_t p = 0; p < npass; ++p) {
+          const pbn_pass_info pi = pinfo[p];
+          const uint32_t slot = p * 64u + lane;
+          const uint4 rec = reinterpret_cast<const uint4*>(img)[slot];
+          uint32_t out = 0;
+          if (TABLES && (rec.x & PBN_SLOT_TABLE)) {
+            uint32_t c = 0;
+            const uint32_t nm = PBN_SLOT_NMULTI(rec.x);
+            for (uint32_t m = 0; m < pi.mmax; ++m) {
+              if (m < nm) {
+                const uint4 ch = *reinterpret_cast<const uint4*>(img + rec.z + 16u * m);
+                const uint32_t w = *reinterpret_cast<const uint32_t*>(rs + (ch.x & 0xFFFFFFu));
+                uint32_t j = uint32_t(w >= ch.y) + uint32_t(w >= ch.z) + uint32_t(w >= ch.w);
+                j = min(j, (ch.x >> 24) - 1u);
+                c += j * ((rec.w >> (8u * m)) & 0xFFu);
+              }
+            }
+            const uint8_t* tb = img + rec.y;
+            const uint4 u0 = *reinterpret_cast<const uint4*>(tb);
+            const uint4 u1 = *reinterpret_cast<const uint4*>(tb + 16);
+            const uint32_t pw[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+            uint32_t x = 0;
+#pragma unroll
+            for (uint32_t k = 0; k < 16u; ++k) {
+              if (k < pi.umax) {
+                const uint32_t pos = (k & 1u) ? (pw[k >> 1] >> 16) : (pw[k >> 1] & 0xFFFFu);
+                x |= uint32_t(csb[pos]) << k;
+              }
+            }
+            const uint32_t v = tb[32u + (c << PBN_SLOT_NU(rec.x)) + x];
+            out = (v * 0x204081u) & 0x01010101u;
+          } else if (rec.x & PBN_SLOT_VALID) {
+            uint32_t j = 0;
+            if (PBN_SLOT_NMULTI(rec.x)) {
+              const uint4 ch = *reinterpret_cast<const uint4*>(img + rec.z);
+              const uint32_t w = *reinterpret_cast<const uint32_t*>(rs + (ch.x & 0xFFFFFFu));
+              j = uint32_t(w >= ch.y) + uint32_t(w >= ch.z) + uint32_t(w >= ch.w);
+              j = min(j, (ch.x >> 24) - 1u);
+            }
+            const uint8_t* fr = img + rec.y + 32u * j;
+            const uint4 pp = *reinterpret_cast<const uint4*>(fr);
+            const uint32_t pw[4] = {pp.x, pp.y, pp.z, pp.w};
+            uint32_t idx = 0;
+#pragma unroll
+            for (uint32_t k = 0; k < 8u; ++k) {
+              if (k < pi.pmax) {
+                const uint32_t pos = (k & 1u) ? (pw[k >> 1] >> 16) : (pw[k >> 1] & 0xFFFFu);
+                idx |= uint32_t(csb[pos]) << k;
+              }
+            }
+            const uint32_t ttw = *reinterpret_cast<const uint32_t*>(fr + 16u + 4u * (idx >> 5));
+            out = (ttw >> (idx & 31u)) & 1u;
+          }
+          if (rec.x & PBN_SLOT_VALID) ns[slot] = out;
+        }
+        cur ^= 1u;
+        wave_sync();
+      }
+      const bool z = target_z(reinterpret_cast<const uint8_t*>(cur ? sbuf1 : sbuf0));
+      if (t >= a.count_from) hits += z;
+      if (uint64_t(t) >= uint64_t(a.count_from) + 1u) {
+        n01 += (!zp && z);
+        n10 += (zp && !z);
+      }
+      zp = z;
+    }
+    wave_sync();
+  }
+
+  if (lane < ntg) {
+    unsigned long long* c = a.counts + (size_t(lane) * a.ntraj + tl) * 3u;
+    c[0] += hits;
+    c[1] += n01;
+    c[2] += n10;
+  }
+  const uint32_t* fs = cur ? sbuf1 : sbuf0;
+  for (uint32_t w = lane; w < W; w += 64u) {
+    uint32_t word = 0;
+    for (uint32_t i = 0; i < 8u; ++i) {
+      const uint32_t s = 8u * w + i;
+      if (s < nslots) {
+        const uint32_t v = fs[s];
+        const uint32_t nib = (v & 1u) | ((v >> 7) & 2u) | ((v >> 14) & 4u) | ((v >> 21) & 8u);
+        word |= nib << (4u * i);
+      }
+    }
+    gst[w] = word;
+  }
+}
+
+// s(0): bit i of node i's INIT word, placed at the node's plan position.
+__global__ void k_state_init(const uint8_t* blob, unsigned long long seed, uint32_t traj0, uint32_t ntraj,
+                             uint32_t* state) {
+  const pbn_plan_header* H = reinterpret_cast<const pbn_plan_header*>(blob);
+  const uint32_t W = H->state_words, nbytes = 4u * H->n_slots;
+  const uint32_t* p2o = reinterpret_cast<const uint32_t*>(blob + H->p2o_off);
+  const uint32_t k0 = uint32_t(seed), k1 = uint32_t(seed >> 32);
+  const size_t total = size_t(ntraj) * W;
+  for (size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < total; idx += size_t(gridDim.x) * blockDim.x) {
+    const uint32_t tl = uint32_t(idx / W), w = uint32_t(idx % W);
+    uint32_t word = 0, cached = PBN_NONE;
+    uint4 x = make_uint4(0, 0, 0, 0);
+    for (uint32_t b = 0; b < 32u; ++b) {
+      const uint32_t pos = 32u * w + b;
+      if (pos >= nbytes) break;
+      const uint32_t o = p2o[pos];
+      if (o == PBN_NONE) continue;
+      if ((o >> 7) != cached) {
+        cached = o >> 7;
+        x = philox(traj0 + tl, 0u, cached, PBN_STREAM_INIT, k0, k1);
+      }
+      const uint32_t sel = (o >> 5) & 3u;
+      const uint32_t src = sel == 0 ? x.x : sel == 1 ? x.y : sel == 2 ? x.z : x.w;
+      word |= ((src >> (o & 31u)) & 1u) << b;
+    }
+    state[idx] = word;
+  }
+}
+
+__global__ void k_to_original(const uint8_t* blob, const uint32_t* state, uint32_t ntraj, uint32_t* out) {
+  const pbn_plan_header* H = reinterpret_cast<const pbn_plan_header*>(blob);
+  const uint32_t W = H->state_words, n = H->n, WO = (n + 31u) / 32u;
+  const uint32_t* o2p = reinterpret_cast<const uint32_t*>(blob + H->o2p_off);
+  const size_t total = size_t(ntraj) * WO;
+  for (size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < total; idx += size_t(gridDim.x) * blockDim.x) {
+    const uint32_t tl = uint32_t(idx / WO), w = uint32_t(idx % WO);
+    const uint32_t* st = state + size_t(tl) * W;
+    uint32_t word = 0;
+    for (uint32_t b = 0; b < 32u; ++b) {
+      const uint32_t i = 32u * w + b;
+      if (i >= n) break;
+      const uint32_t pos = o2p[i];
+      if (pos == PBN_NONE) continue;
+      word |= ((st[pos >> 5] >> (pos & 31u)) & 1u) << b;
+    }
+    out[idx] = word;
+  }
+}
+
+pbn_status fail(pbn_status code, const std::string& msg) {
+  pbn::set_error(msg);
+  return code;
+}
+
+pbn_status hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return PBN_OK;
+  return fail(PBN_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+uint32_t grid_for(size_t work, uint32_t block) {
+  const size_t g = (work + block - 1) / block;
+  return uint32_t(std::min<size_t>(std::max<size_t>(g, 1), 65536));
+}
+
+constexpr uint32_t kLdsMax = 160u * 1024u;
+
+template <bool IMG_LDS, bool TABLES>
+pbn_status launch_sim(const SimParams& p, uint32_t blocks, uint32_t lds, hipStream_t stream) {
+  auto* fn = k_simulate<IMG_LDS, TABLES>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       int(kLdsMax));
+    if (e != hipSuccess) return hip_check(e, "hipFuncSetAttribute");
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(fn, dim3(blocks), dim3(64u * p.wpb), lds, stream, p);
+  return hip_check(hipGetLastError(), "k_simulate launch");
+}
+
+pbn_status simulate_common(bool plain, const pbn_plan* plan, const void* d_plan, uint64_t seed, uint32_t traj0,
+                           uint32_t ntraj, uint32_t step0, uint32_t nsteps, uint32_t count_from,
+                           const pbn_targets* targets, uint32_t* d_state, uint64_t* d_counts,
+                           const pbn_launch_opts* launch, void* stream) {
+  pbn::clear_error();
+  if (!plan || !d_plan || !targets || (ntraj && (!d_state || !d_counts)))
+    return fail(PBN_EINVAL, "null argument");
+  if (uint64_t(traj0) + ntraj > (1ull << 32)) return fail(PBN_ERANGE, "trajectory ids exceed 32 bits");
+  if (uint64_t(step0) + nsteps > 0xFFFFFFFFull) return fail(PBN_ERANGE, "step counter exceeds 32 bits");
+  if (targets->ntargets < 1 || targets->ntargets > 64 || targets->npairs > PBN_MAX_PAIRS)
+    return fail(PBN_EINVAL, "bad targets (build them with pbn_targets_build)");
+  for (uint32_t k = 0; k < targets->npairs; ++k)
+    if (targets->pos[k] >= 4u * plan->info.n_slots) return fail(PBN_EINVAL, "target position outside the plan");
+  if (plain && plan->has_table) return fail(PBN_EINVAL, "the plain kernel needs a plan without table slots");
+  if (ntraj == 0 || nsteps == 0) return PBN_OK;
+
+  const uint32_t ring_entries = plan->n_jobs <= 64 ? plan->fill_steps * plan->n_jobs : plan->n_jobs;
+  const uint32_t wave_bytes = 8u * ((plan->state_dwords + 3u) & ~3u) + 16u * ring_entries;
+  const bool img_lds = plan->info.image_in_lds != 0;
+  const uint32_t img = img_lds ? ((plan->info.image_bytes + 15u) & ~15u) : 0u;
+  uint32_t wpb = launch && launch->waves_per_block ? launch->waves_per_block : 4u;
+  if (wpb > 16) return fail(PBN_EINVAL, "waves_per_block must be 1..16");
+  while (wpb > 1 && img + wpb * wave_bytes > kLdsMax) --wpb;
+  if (img + wpb * wave_bytes > kLdsMax)
+    return fail(PBN_ELDS, "one trajectory's state and ring do not fit in LDS");
+  SimParams p{};
+  p.blob = static_cast<const uint8_t*>(d_plan);
+  p.state = d_state;
+  p.counts = reinterpret_cast<unsigned long long*>(d_counts);
+  p.seed = seed;
+  p.traj0 = traj0;
+  p.ntraj = ntraj;
+  p.step0 = step0;
+  p.nsteps = nsteps;
+  p.count_from = count_from;
+  p.wpb = wpb;
+  p.wave_bytes = wave_bytes;
+  p.tg = *targets;
+  const uint32_t blocks = (ntraj + wpb - 1) / wpb;
+  const uint32_t lds = img + wpb * wave_bytes;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (plain)
+    return img_lds ? launch_sim<true, false>(p, blocks, lds, s) : launch_sim<false, false>(p, blocks, lds, s);
+  return img_lds ? launch_sim<true, true>(p, blocks, lds, s) : launch_sim<false, true>(p, blocks, lds, s);
+}
+
+}  // namespace
+
+extern "C" pbn_status pbn_state_init(const pbn_plan* plan, const void* d_plan, uint64_t seed, uint32_t traj0,
+                                     uint32_t ntraj, uint32_t* d_state, void* stream) {
+  pbn::clear_error();
+  if (!plan || !d_plan || (ntraj && !d_state)) return fail(PBN_EINVAL, "null argument");
+  if (uint64_t(traj0) + ntraj > (1ull << 32)) return fail(PBN_ERANGE, "trajectory ids exceed 32 bits");
+  if (ntraj == 0) return PBN_OK;
+  const size_t work = size_t(ntraj) * plan->info.state_words;
+  hipLaunchKernelGGL(k_state_init, dim3(grid_for(work, 256)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                     static_cast<const uint8_t*>(d_plan), (unsigned long long)seed, traj0, ntraj, d_state);
+  return hip_check(hipGetLastError(), "k_state_init launch");
+}
+
+extern "C" pbn_status pbn_simulate(const pbn_plan* plan, const void* d_plan, uint64_t seed, uint32_t traj0,
+                                   uint32_t ntraj, uint32_t step0, uint32_t nsteps, uint32_t count_from,
+                                   const pbn_targets* targets, uint32_t* d_state, uint64_t* d_counts,
+                                   const pbn_launch_opts* launch, void* stream) {
+  return simulate_common(false, plan, d_plan, seed, traj0, ntraj, step0, nsteps, count_from, targets, d_state,
+                         d_counts, launch, stream);
+}
+
+extern "C" pbn_status pbn_simulate_plain(const pbn_plan* plan, const void* d_plan, uint64_t seed, uint32_t traj0,
+                                         uint32_t ntraj, uint32_t step0, uint32_t nsteps, uint32_t count_from,
+                                         const pbn_targets* targets, uint32_t* d_state, uint64_t* d_counts,
+                                         const pbn_launch_opts* launch, void* stream) {
+  return simulate_common(true, plan, d_plan, seed, traj0, ntraj, step0, nsteps, count_from, targets, d_state,
+                         d_counts, launch, stream);
+}
+
+extern "C" pbn_status pbn_state_to_original(const pbn_plan* plan, const void* d_plan, const uint32_t* d_state,
+                                            uint32_t ntraj, uint32_t* d_out, void* stream) {
+  pbn::clear_error();
+  if (!plan || !d_plan || (ntraj && (!d_state || !d_out))) return fail(PBN_EINVAL, "null argument");
+  if (ntraj == 0) return PBN_OK;
+  const size_t work = size_t(ntraj) * ((plan->info.n + 31) / 32);
+  hipLaunchKernelGGL(k_to_original, dim3(grid_for(work, 256)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                     static_cast<const uint8_t*>(d_plan), d_state, ntraj, d_out);
+  return hip_check(hipGetLastError(), "k_to_original launch");
+}

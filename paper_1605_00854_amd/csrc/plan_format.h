@@ -1,0 +1,87 @@
+// plan_format.h -- device blob of a prepared PBN (the output of Algorithm 5's
+// Preparation, laid out for the step kernel).  Shared by the host builder and
+// the HIP kernels; plain C layout, little-endian, every section 16-byte aligned.
+//
+// Step-kernel model: one wavefront simulates one trajectory.  The kept nodes
+// are packed into "slots": a slot is either one node evaluated through its
+// selected predictor function (FN slot) or a group of up to 4 nodes evaluated
+// through one combined table (TABLE slot, Section 3.3).  Slot s is handled by
+// lane s % 64 in pass s / 64.  The trajectory state lives in LDS as one 32-bit
+// word per slot, byte k holding member k's value (0/1); one extra zero word
+// follows (ZERO position for unused parent entries).  Packed states in HBM use
+// bit 4*s + k for the same node.
+#pragma once
+#include <stdint.h>
+
+#define PBN_PLAN_MAGIC 0x314E4250u   // "PBN1"
+#define PBN_WAVE 64
+#define PBN_NONE 0xFFFFFFFFu
+
+// streams of the random-number contract
+#define PBN_STREAM_INIT 1u
+#define PBN_STREAM_PERT 2u
+#define PBN_STREAM_SEL 3u
+
+// slot-record info word
+#define PBN_SLOT_VALID 0x80000000u
+#define PBN_SLOT_TABLE 0x40000000u
+// bits 0-2: number of members - 1; bits 3-5: multi-predictor members;
+// bits 6-10: number of union parent bits (TABLE) / parent entries (FN, max over l)
+#define PBN_SLOT_NMEM(i) (((i) & 7u) + 1u)
+#define PBN_SLOT_NMULTI(i) (((i) >> 3) & 7u)
+#define PBN_SLOT_NU(i) (((i) >> 6) & 31u)
+
+// pass-info flags
+#define PBN_PASS_FN 1u
+#define PBN_PASS_TABLE 2u
+#define PBN_PASS_MULTI 4u
+
+struct pbn_plan_header {
+  uint32_t magic, version, blob_bytes, plan_id;
+  uint32_t n;              // original nodes
+  uint32_t n_kept;
+  uint32_t n_slots;
+  uint32_t n_passes;
+  uint32_t state_dwords;   // n_slots + 1 (zero word)
+  uint32_t state_words;    // packed words per trajectory = ceil(4 * n_slots / 32)
+  uint32_t n_jobs;         // 1 + number of SEL blocks with a kept member
+  uint32_t fill_steps;     // steps whose jobs are computed per fill (njobs <= 64)
+  uint32_t image_bytes;    // bytes of the image (slot, choice, fn records, tables)
+  uint32_t image_off;      // blob offset of the image
+  uint32_t q_off;          // blob offset of Q[0..n] (uint64)
+  uint32_t o2p_off;        // blob offset of orig -> byte position (uint32[n])
+  uint32_t p2o_off;        // blob offset of byte position -> orig (uint32[4 n_slots])
+  uint32_t blk_off;        // blob offset of SEL block ids (uint32[n_jobs - 1])
+  uint32_t pass_off;       // blob offset of pass info (pbn_pass_info[n_passes])
+  uint32_t zero_pos;       // byte position of the zero word (4 * n_slots)
+  uint32_t max_pmax;       // largest parent-entry count over all passes
+  uint32_t image_in_lds;
+  uint32_t has_table;
+  uint32_t pad[9];
+};
+
+struct pbn_pass_info {
+  uint32_t flags;   // PBN_PASS_*
+  uint32_t pmax;    // parent entries to gather in FN slots of this pass
+  uint32_t umax;    // union bits to gather in TABLE slots of this pass
+  uint32_t mmax;    // multi-predictor members of TABLE slots in this pass
+};
+
+// Image sections (offsets relative to the image base):
+//   [0, 16 * 64 * n_passes)  slot records (uint4 each)
+//   choice records (uint4):   x = draw byte offset within a step's ring segment
+//                                 | (l << 24);  y, z, w = thresholds CUM[0..2]
+//                                 (unused = 0xFFFFFFFF)
+//   fn records (32 bytes):    parent byte positions as 8 uint16 (unused = zero
+//                             position), then the 128-bit truth table
+//   tables:                   TABLE slot: 16 uint16 union-parent positions
+//                             (unused = zero position), then the byte table
+//                             T[c * 2^nu + x]
+// Slot record (uint4):
+//   x = info word (PBN_SLOT_*)
+//   y = FN: image offset of the fn record of predictor 0 (predictor j at +32 j)
+//       TABLE: image offset of the union-parent list (table follows at +32)
+//   z = image offset of the first choice record (multi-predictor members, in
+//       member order), or 0
+//   w = TABLE: mixed-radix weights of the multi-predictor members, one byte
+//       each (first member most significant digit); FN: 0

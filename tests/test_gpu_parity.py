@@ -1,0 +1,230 @@
+"""GPU parity: the HIP step kernel (through the C ABI) against the CPU oracle.
+
+Trajectories are compared bit for bit on the kept nodes (the oracle simulates
+the unreduced, ungrouped network; reduction and grouping must not change any
+kept node, Section 3.1), together with the per-target hit and transition
+counters.  Cases span several lane passes and a ragged last pass, Philox fills
+that cover many steps and fills that need several lane passes, chains with
+several perturbations, LDS- and global-resident plan images, combined tables
+with several multi-predictor members, ragged trajectory counts and chunked
+launches.
+"""
+import functools
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import pbn_synth as ps
+from oracle import contract, exact
+from oracle import simulate as osim
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_1605_00854_amd import api  # noqa: E402
+
+NONE = 0xFFFFFFFF
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+# --------------------------------------------------------------- networks
+
+def all_multi(n, seed, p=2e-3):
+    return ps.random_pbn(n, p, seed, nfn=lambda r: int(r.integers(2, 5)),
+                         nparents=lambda r: int(r.integers(1, 4)))
+
+
+def all_single(n, seed, p=5e-3):
+    return ps.random_pbn(n, p, seed, nfn=lambda r: 1, nparents=lambda r: int(r.integers(1, 6)))
+
+
+def sparse_multi(n, seed, p=3e-3):
+    # few parents per predictor so groups of multi-predictor nodes fit a table
+    return ps.random_pbn(n, p, seed, nfn=lambda r: int(r.integers(1, 4)),
+                         nparents=lambda r: int(r.integers(0, 3)), leaf_frac=0.2)
+
+
+NETS = {
+    "c1": ps.tiny_c1,
+    "c2": ps.medium_c2,
+    "c2_hot": lambda: ps.medium_c2(n=100, p=0.02, seed=31),
+    "c2_small": lambda: ps.medium_c2(n=37, p=0.01, seed=8),
+    "multi400": lambda: all_multi(400, 12),
+    "single200": lambda: all_single(200, 13),
+    "sparse120": lambda: sparse_multi(120, 14),
+    "c3_slice": lambda: ps.large_c3(n=1500, p=2e-4, seed=15),
+}
+
+
+@functools.lru_cache(maxsize=None)
+def net_of(name):
+    return NETS[name]()
+
+
+def targets_of(net):
+    t1 = ps.non_leaf_targets(net, 3)
+    t2 = [(t1[0][0], 0)]
+    t3 = [(a, (a + 1) % 2) for a, _ in ps.non_leaf_targets(net, 2)]
+    return [t1, t2, t3]
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_run(name, seed, traj0, ntraj, steps, count_from):
+    net = net_of(name)
+    say(f"[oracle] {name} seed={seed} traj={traj0}+{ntraj} steps={steps}")
+    return osim.run(net, seed, np.arange(traj0, traj0 + ntraj), steps, targets=targets_of(net),
+                    count_from=count_from)
+
+
+def gpu_run(name, opts, seed, traj0, ntraj, chunks, count_from=0, plain=False, wpb=0):
+    net = net_of(name)
+    tgs = targets_of(net)
+    interest = sorted({a for tg in tgs for a, _ in tg})
+    plan = api.Plan(net, interest=interest, **opts)
+    say(f"[gpu] {name} opts={opts} info={plan.info} traj={traj0}+{ntraj} chunks={chunks} plain={plain} wpb={wpb}")
+    tg = plan.targets(tgs)
+    state = api.state_init(plan, seed, ntraj, traj0=traj0)
+    counts = api.new_counts(len(tgs), ntraj)
+    step = 0
+    for c in chunks:
+        api.simulate(plan, seed, state, counts, tg, step, c, traj0=traj0, count_from=count_from,
+                     plain=plain, waves_per_block=wpb)
+        step += c
+    orig = api.unpack_bits(api.to_original(plan, state).cpu().numpy(), plan.n)
+    torch.cuda.synchronize()
+    return plan, orig, counts.cpu().numpy(), state.cpu().numpy()
+
+
+def check(name, opts, seed, traj0, ntraj, chunks, count_from=0, plain=False, wpb=0):
+    ref = oracle_run(name, seed, traj0, ntraj, sum(chunks), count_from)
+    plan, orig, counts, _ = gpu_run(name, opts, seed, traj0, ntraj, chunks, count_from, plain, wpb)
+    kept = plan.node_pos() != NONE
+    bad = np.nonzero((orig[:, kept] != ref["state"][:, kept]).any(axis=1))[0]
+    assert bad.size == 0, f"{bad.size} trajectories differ, first {traj0 + bad[0]}"
+    assert np.array_equal(counts[:, :, 0], ref["hits"])
+    assert np.array_equal(counts[:, :, 1], ref["n01"])
+    assert np.array_equal(counts[:, :, 2], ref["n10"])
+    return plan
+
+
+PLAIN = dict(reduce=0, group=0)
+REDUCED = dict(reduce=1, group=0)
+GROUPED = dict(reduce=1, group=1)
+MULTI_GROUPS = dict(reduce=1, group=1, weight_mode=0, theta=10**6, max_table_entries=1 << 14,
+                    max_parent_bits=12)
+GLOBAL_IMAGE = dict(reduce=1, group=1, lds_budget_bytes=0)
+
+CASES = [
+    # name, opts, seed, traj0, ntraj, chunks, count_from, plain, wpb
+    ("c1", PLAIN, 1, 0, 4, (3000,), 0, True, 0),
+    ("c1", GROUPED, 1, 0, 4, (3000,), 0, False, 0),
+    ("c2", PLAIN, 2, 0, 24, (300,), 0, True, 0),
+    ("c2", REDUCED, 2, 0, 24, (300,), 0, True, 0),
+    ("c2", GROUPED, 2, 0, 24, (300,), 0, False, 0),
+    ("c2", MULTI_GROUPS, 2, 0, 24, (300,), 0, False, 0),
+    ("c2", GLOBAL_IMAGE, 2, 0, 24, (300,), 0, False, 0),
+    ("c2_hot", GROUPED, 3, 5, 16, (120, 80), 50, False, 2),
+    ("c2_small", GROUPED, 4, 0, 37, (77, 23), 10, False, 4),
+    ("multi400", GROUPED, 5, 0, 6, (60,), 0, False, 1),
+    ("multi400", PLAIN, 5, 0, 6, (60,), 0, True, 3),
+    ("single200", GROUPED, 6, 0, 8, (200,), 0, False, 0),
+    ("sparse120", MULTI_GROUPS, 7, 0, 12, (150,), 0, False, 0),
+    ("c3_slice", GROUPED, 8, 0, 3, (25,), 0, False, 0),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}-{i}" for i, c in enumerate(CASES)])
+def test_trajectories_bit_exact(case):
+    name, opts, seed, traj0, ntraj, chunks, count_from, plain, wpb = case
+    plan = check(name, opts, seed, traj0, ntraj, chunks, count_from, plain, wpb)
+    if opts is MULTI_GROUPS and name == "sparse120":
+        assert plan.info["n_multi_groups"] > 0, "case must exercise multi-member tables"
+    if opts is GLOBAL_IMAGE:
+        assert plan.info["image_in_lds"] == 0
+
+
+@pytest.mark.parametrize("name,opts", [("c2", GROUPED), ("c3_slice", REDUCED), ("c1", PLAIN)])
+def test_initial_state_matches_oracle(name, opts):
+    net = net_of(name)
+    plan = api.Plan(net, interest=[0, 1, 2], **opts)
+    say(f"[gpu] init {name}")
+    state = api.state_init(plan, 11, 50, traj0=1000)
+    orig = api.unpack_bits(api.to_original(plan, state).cpu().numpy(), plan.n)
+    ref = contract.initial_state(net, 11, np.arange(1000, 1050))
+    kept = plan.node_pos() != NONE
+    assert np.array_equal(orig[:, kept], ref[:, kept])
+
+
+def test_chunked_launch_equals_single_launch():
+    a = gpu_run("c2", GROUPED, 9, 0, 64, (1000,))
+    b = gpu_run("c2", GROUPED, 9, 0, 64, (1, 2, 333, 664))
+    assert np.array_equal(a[3], b[3])
+    assert np.array_equal(a[2], b[2])
+
+
+def test_trajectory_subset_is_exact():
+    full = gpu_run("c2", GROUPED, 10, 0, 100, (500,))
+    part = gpu_run("c2", GROUPED, 10, 40, 10, (500,))
+    assert np.array_equal(full[3][40:50], part[3])
+
+
+def test_plain_reduced_grouped_agree_on_kept_nodes():
+    runs = [gpu_run("c2", o, 12, 0, 256, (2000,), plain=(o is not GROUPED)) for o in (PLAIN, REDUCED, GROUPED)]
+    kept = runs[1][0].node_pos() != NONE
+    for r in runs[1:]:
+        assert np.array_equal(r[1][:, kept], runs[0][1][:, kept])
+        assert np.array_equal(r[2], runs[0][2])
+
+
+def test_full_size_c2_sampled_against_oracle():
+    """C2 at its full trajectory count and launch shape; 8 sampled trajectories
+    (spread over the id range) are recomputed by the oracle."""
+    cfg = ps.config("C2")
+    net = cfg.net
+    plan = api.Plan(net, interest=[a for a, _ in cfg.targets[0]], **GROUPED)
+    tg = plan.targets(cfg.targets)
+    steps = 400
+    say("[gpu] full-size C2 4096 trajectories")
+    state = api.state_init(plan, cfg.seed, cfg.ntraj)
+    counts = api.new_counts(1, cfg.ntraj)
+    api.simulate(plan, cfg.seed, state, counts, tg, 0, steps)
+    orig = api.unpack_bits(api.to_original(plan, state).cpu().numpy(), plan.n)
+    c = counts.cpu().numpy()
+    sample = np.array([0, 1, 777, 1500, 2048, 3000, 4000, 4095])
+    ref = osim.run(net, cfg.seed, sample, steps, targets=cfg.targets)
+    kept = plan.node_pos() != NONE
+    assert np.array_equal(orig[sample][:, kept], ref["state"][:, kept])
+    assert np.array_equal(c[0, sample, 0], ref["hits"][0])
+
+
+def test_c1_estimate_matches_power_method():
+    """C1: one trajectory of 10^6 steps; batch-means interval around the exact
+    steady state of the 2^10-state chain (Eq. 1)."""
+    cfg = ps.config("C1")
+    net = cfg.net
+    plan = api.Plan(net, interest=[0, 1], **GROUPED)
+    tg = plan.targets(cfg.targets)
+    state = api.state_init(plan, cfg.seed, 1)
+    B = 50
+    per = cfg.steps // B
+    batch = []
+    say("[gpu] C1 10^6 steps in 50 batches")
+    for b in range(B):
+        counts = api.new_counts(1, 1)
+        api.simulate(plan, cfg.seed, state, counts, tg, b * per, per)
+        batch.append(int(counts.cpu().numpy()[0, 0, 0]))
+    pi = exact.steady_state(net)
+    want = exact.target_probability(pi, cfg.targets[0])
+    means = np.array(batch) / per
+    p_hat = means.mean()
+    hw = 3.29 * means.std(ddof=1) / math.sqrt(B)
+    assert abs(p_hat - want) < hw, (p_hat, want, hw)

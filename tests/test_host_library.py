@@ -1,0 +1,156 @@
+"""CPU tests of the C-ABI library: it loads, exports every declared symbol, and
+its host-side preparation agrees with the oracle (integer work: bit-exact)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import pbn_synth as ps
+from oracle import contract, structure
+from paper_1605_00854_amd import _lib, api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "pbn.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pbn_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    names = declared_symbols()
+    assert len(names) >= 19
+    for name in names:
+        assert hasattr(L, name), name
+        assert name in _lib.SIGNATURES, f"{name} has no Python declaration"
+
+
+NETS = {
+    "c1": ps.tiny_c1(),
+    "c2": ps.medium_c2(),
+    "c2_small": ps.medium_c2(n=40, seed=9),
+    "c3_slice": ps.large_c3(n=300, seed=4),
+}
+
+
+@pytest.mark.parametrize("name", sorted(NETS))
+def test_quantisation_matches_oracle(name):
+    net = NETS[name]
+    q, cum, rank = api.Net(net).tables()
+    Q = contract.perturbation_table(net["n"], net["p"])
+    assert [int(x) for x in q[1:]] == Q[1:]
+    for i in range(net["n"]):
+        c = contract.selection_thresholds(net["sel_prob"][net["fn_off"][i]:net["fn_off"][i + 1]])
+        assert [int(x) for x in cum[i][: len(c)]] == c
+        assert all(int(x) == 0xFFFFFFFF for x in cum[i][len(c):])
+    assert np.array_equal(rank, contract.multi_ranks(net))
+
+
+@pytest.mark.parametrize("name", sorted(NETS))
+@pytest.mark.parametrize("interest", [(), (0,), (0, 1, 2, 5)])
+def test_leaf_reduction_matches_definition_1(name, interest):
+    net = NETS[name]
+    plan = api.Plan(net, interest=interest, reduce=1, group=0)
+    removed = set(np.nonzero(plan.node_pos() == 0xFFFFFFFF)[0].tolist())
+    assert removed == structure.leaf_nodes(net, interest)
+
+
+def test_designated_leaves_are_removed():
+    net = NETS["c2"]
+    plan = api.Plan(net, interest=[a for a, _ in ps.non_leaf_targets(net)], reduce=1, group=0)
+    pos = plan.node_pos()
+    assert all(pos[v] == 0xFFFFFFFF for v in net["designated_leaves"])
+    assert plan.info["n_kept"] == net["n"] - len(structure.leaf_nodes(net, [0, 1, 2]))
+
+
+def oracle_groups(net, interest, weight_mode, theta, max_nodes, max_bits, max_entries):
+    removed = structure.leaf_nodes(net, interest)
+    kept = [v for v in range(net["n"]) if v not in removed]
+    nfn = np.diff(net["fn_off"])
+    par = {v: sorted(set(p for pa, _ in structure.node_functions(net, v) for p in pa)) for v in kept}
+    items = []
+    for v in kept:
+        if nfn[v] >= 2:
+            w = int(nfn[v]) * (2 ** len(par[v]) if weight_mode == 1 else 1)
+            items.append((v, min(w, structure.SATURATE)))
+    multi = structure.partition_multi(items, theta)
+    bits = max_bits
+    while bits > 0 and (1 << bits) > max_entries:
+        bits -= 1
+    single = structure.group_single([v for v in kept if nfn[v] == 1], par, max_nodes, bits)
+    return multi, single
+
+
+@pytest.mark.parametrize("name", sorted(NETS))
+@pytest.mark.parametrize("weight_mode,theta", [(0, 64), (0, 10**6), (1, 65536), (1, 10**9)])
+def test_grouping_matches_algorithms_3_and_4(name, weight_mode, theta):
+    net = NETS[name]
+    interest = [0, 1]
+    plan = api.Plan(net, interest=interest, reduce=1, group=1, weight_mode=weight_mode, theta=theta)
+    multi, single = oracle_groups(net, interest, weight_mode, theta, 4, 12, 4096)
+    assert plan.alg4_groups() == multi
+    assert plan.single_groups() == single
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_eq2_matches_oracle(seed):
+    rng = np.random.default_rng(seed)
+    k = int(rng.integers(1, 30))
+    w = [int(x) for x in rng.integers(2, 5000, size=k)]
+    theta = int(rng.integers(2, 10**7))
+    assert api.eq2_lower_bound(w, theta) == structure.eq2_lower_bound(w, theta)
+
+
+def test_eq2_exact_ties():
+    assert api.eq2_lower_bound([2, 2, 2, 2], 8) == 2
+    assert api.eq2_lower_bound([2] * 8, 16) == 4
+    assert api.eq2_lower_bound([2] * 8, 15) is None
+    assert api.eq2_lower_bound([3, 3], 9) == 1
+
+
+def test_plan_slots_cover_kept_nodes_once():
+    net = NETS["c3_slice"]
+    plan = api.Plan(net, interest=[0], reduce=1, group=1)
+    slot, is_table = plan.slots()
+    pos = plan.node_pos()
+    kept = pos != 0xFFFFFFFF
+    assert np.array_equal(slot != 0xFFFFFFFF, kept)
+    assert len(set(pos[kept].tolist())) == kept.sum()
+    assert np.all(pos[kept] // 4 == slot[kept])
+    assert is_table.size == plan.info["n_slots"]
+
+
+def test_invalid_networks_are_rejected():
+    good = ps.assemble(2, 0.1, [[(1.0, [1], [0, 1])], [(1.0, [0], [1, 0])]])
+    api.Net(good)
+    bad = dict(good)
+    bad["parents"] = np.array([5, 0], dtype=np.uint32)
+    with pytest.raises(_lib.PbnError) as e:
+        api.Net(bad)
+    assert e.value.code == _lib.EINVAL
+    bad = dict(good)
+    bad["sel_prob"] = np.array([0.5, 1.0])
+    with pytest.raises(_lib.PbnError):
+        api.Net(bad)
+    bad = dict(good)
+    bad["p"] = 1.0
+    with pytest.raises(_lib.PbnError):
+        api.Net(bad)
+    bad = dict(good)
+    bad["tt"] = np.array([0b110, 1], dtype=np.uint64)     # bit above 2^1
+    with pytest.raises(_lib.PbnError):
+        api.Net(bad)
+
+
+def test_targets_reject_removed_nodes():
+    net = NETS["c2"]
+    plan = api.Plan(net, interest=[0, 1, 2], reduce=1, group=0)
+    leaf = int(net["designated_leaves"][0])
+    with pytest.raises(_lib.PbnError):
+        plan.targets([[(leaf, 1)]])
+    tg = plan.targets([[(0, 1), (1, 0)], [(2, 1)]])
+    assert tg.ntargets == 2 and tg.npairs == 3 and tg.mask[0] == 0b011 and tg.mask[1] == 0b100
