@@ -1,0 +1,243 @@
+#!/usr/bin/env python3
+"""Throughput benchmark: node-updates/s of PBN simulation on one MI355X.
+
+One benchmark step is one pass of the whole hot path over the medium workload
+(C2: n = 100 nodes, 1-4 predictors of 2-5 parents, 15% designated leaves,
+p = 1e-3, 4096 trajectories x 10^6 steps):
+  host preparation (validation, quantisation, leaf reduction, grouping,
+  combined tables, device blob) -> upload -> s(0) -> 10^6 simulation steps in
+  chunked launches (perturbation chain, predictor selection, table lookups,
+  hit counting) -> per-trajectory counters -> steady-state estimate.
+
+node-updates = trajectories x (burn-in + steps) x n_original (leaves count),
+so the ratio of two kernels equals the paper's time-ratio speedup.
+
+The JSON line also reports the plain per-node kernel (Method_old analogue:
+no reduction, no grouping), the reduced kernel (Method_reduction analogue),
+the roofline of the dominant kernel and the CPU oracle on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import pbn_synth as ps  # noqa: E402
+
+PEAK_ALU = 256 * 64 * 2.4e9        # int32 VALU lane-operations per second (256 CUs x 64 lanes x 2.4 GHz)
+PHILOX_SLOTS = 100                 # 10 rounds x (2 quarter-rate 32x32->64 multiplies + 2 xor3)
+
+PLANS = {
+    "grouped": dict(reduce=1, group=1),
+    "reduction": dict(reduce=1, group=0),
+    "plain": dict(reduce=0, group=0),
+}
+
+
+def algorithmic_ops(net, plan_info, slots_desc, n_targets, n_pairs):
+    """VALU lane-operations one trajectory-step must perform (the work model).
+
+    Every step draws the perturbation chain (1 + n p Philox calls on average)
+    and compares; a step without perturbation (probability (1-p)^n) also draws
+    the SEL blocks and evaluates every slot: 2 ops per parent bit gathered,
+    3 per lookup/write, 4 per multi-predictor selection; hit tests cost 3 per
+    target pair.
+    """
+    n, p = net["n"], net["p"]
+    f = (1.0 - p) ** n
+    B = plan_info["n_jobs"] - 1
+    chain = PHILOX_SLOTS * (1 + n * p) + 2 * (1 + n * p)
+    func = PHILOX_SLOTS * B + sum(2 * bits + 3 + 4 * nmulti for bits, nmulti in slots_desc)
+    return chain + f * func + 3 * n_pairs + n_targets
+
+
+def slot_work(net, plan):
+    """(parent bits gathered, multi-predictor members) per slot of the plan."""
+    slot, is_table = plan.slots()
+    fn_off, par_off = net["fn_off"], net["par_off"]
+    out = []
+    for s in range(plan.info["n_slots"]):
+        members = np.nonzero(slot == s)[0]
+        nmulti = int(sum(1 for v in members if fn_off[v + 1] - fn_off[v] > 1))
+        if is_table[s]:
+            union = set()
+            for v in members:
+                for fi in range(fn_off[v], fn_off[v + 1]):
+                    union.update(net["parents"][par_off[fi]:par_off[fi + 1]].tolist())
+            out.append((len(union), nmulti))
+        else:
+            v = members[0]
+            probs = net["sel_prob"][fn_off[v]:fn_off[v + 1]]
+            phis = np.diff(par_off[fn_off[v]:fn_off[v + 1] + 1])
+            out.append((float((probs * phis).sum()), nmulti))
+    return out
+
+
+# ------------------------------------------------------------ CPU baseline
+
+def _oracle_worker(args):
+    from oracle import simulate as osim
+    cfg_name, traj, steps = args
+    cfg = ps.config(cfg_name)
+    osim.run(cfg.net, cfg.seed, np.asarray(traj), steps, targets=cfg.targets)
+    return len(traj)
+
+
+def cpu_baseline(cfg_name, ntraj, steps):
+    """The oracle as it stands, one worker per host core, on a bounded sample."""
+    import multiprocessing as mp
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    chunks = [c.tolist() for c in np.array_split(np.arange(ntraj), cores) if c.size]
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(len(chunks)) as pool:
+        pool.map(_oracle_worker, [(cfg_name, c, steps) for c in chunks])
+    dt = time.perf_counter() - t0
+    n = ps.config(cfg_name).net["n"]
+    return {"value": ntraj * steps * n / dt, "unit": "node-updates/s", "cores": len(chunks),
+            "kind": "oracle", "sample": f"{cfg_name}: {ntraj} trajectories x {steps} steps "
+                                        f"(numpy oracle, unreduced network), {dt:.1f} s wall"}
+
+
+# --------------------------------------------------------------- GPU path
+
+def run_step(api, torch, cfg, opts, plain, chunk, events, wpb=0):
+    """One pass of the hot path.  Returns (estimate, half-width, prep seconds)."""
+    net = cfg.net
+    interest = sorted({a for tg in cfg.targets for a, _ in tg})
+    t0 = time.perf_counter()
+    plan = api.Plan(net, interest=interest, **opts)
+    tg = plan.targets(cfg.targets)
+    prep = time.perf_counter() - t0
+    plan.device()
+    state = api.state_init(plan, cfg.seed, cfg.ntraj)
+    counts = api.new_counts(len(cfg.targets), cfg.ntraj)
+    total = cfg.burn_in + cfg.steps
+    step = 0
+    stream = torch.cuda.current_stream()
+    while step < total:
+        c = min(chunk, total - step)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        api.simulate(plan, cfg.seed, state, counts, tg, step, c, count_from=cfg.burn_in, plain=plain,
+                     waves_per_block=wpb)
+        e1.record(stream)
+        events.append((e0, e1, c))
+        step += c
+    hits = counts[0, :, 0].cpu().numpy().astype(np.float64)    # synchronises
+    means = hits / cfg.steps
+    p_hat = float(means.mean())
+    hw = 1.96 * float(means.std(ddof=1)) / math.sqrt(means.size) if means.size > 1 else float("nan")
+    return plan, p_hat, hw, prep
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="C2")
+    ap.add_argument("--chunk", type=int, default=250000, help="simulation steps per kernel launch")
+    ap.add_argument("--sim-steps", type=int, default=0, help="override T (for quick runs)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the plain and reduction kernels")
+    ap.add_argument("--wpb", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is design-only "
+                                   "(trajectories shard by id, counters reduce with one integer all-reduce)"}))
+        sys.exit(2)
+
+    cfg = ps.config(args.config)
+    if args.sim_steps:
+        cfg.steps = args.sim_steps
+    cpu = None
+    if not args.no_cpu:
+        # before any GPU initialisation: the pool forks
+        sample = {"C1": (1, 20000), "C2": (512, 400), "C3": (32, 40)}[args.config]
+        cpu = cpu_baseline(args.config, *sample)
+
+    import torch
+    from paper_1605_00854_amd import api
+    torch.cuda.set_device(0)
+    net = cfg.net
+    n = net["n"]
+    work = cfg.ntraj * (cfg.burn_in + cfg.steps) * n
+
+    for _ in range(args.warmup):
+        run_step(api, torch, cfg, PLANS["grouped"], False, args.chunk, [], args.wpb)
+    torch.cuda.synchronize()
+    events = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan, p_hat, hw, prep = run_step(api, torch, cfg, PLANS["grouped"], False, args.chunk, events, args.wpb)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = 1e3 * dt / args.steps
+    value = work * args.steps / dt
+
+    # dominant kernel: the step kernel; algorithmic ops per launch / launch time
+    durs = [(e0.elapsed_time(e1) * 1e-3, c) for e0, e1, c in events]
+    avg_launch = sum(d for d, _ in durs) / len(durs)
+    avg_steps = sum(c for _, c in durs) / len(durs)
+    npairs = sum(len(t) for t in cfg.targets)
+    w_step = algorithmic_ops(net, plan.info, slot_work(net, plan), len(cfg.targets), npairs)
+    achieved = w_step * cfg.ntraj * avg_steps / avg_launch
+    kernel_rate = cfg.ntraj * avg_steps * n / avg_launch
+
+    compare = {}
+    if not args.no_compare:
+        for name in ("plain", "reduction"):
+            ev = []
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            pl, ph, _, _ = run_step(api, torch, cfg, PLANS[name], True, args.chunk, ev, args.wpb)
+            torch.cuda.synchronize()
+            d = time.perf_counter() - t1
+            kt = sum(e0.elapsed_time(e1) * 1e-3 for e0, e1, _ in ev)
+            compare[name] = {"node_updates_per_s": work / d, "kernel_node_updates_per_s": work / kt,
+                             "n_kept": pl.info["n_kept"], "slots": pl.info["n_slots"], "p_hat": ph}
+        compare["grouped_over_plain"] = value / compare["plain"]["node_updates_per_s"]
+        compare["grouped_over_reduction"] = value / compare["reduction"]["node_updates_per_s"]
+
+    out = {
+        "metric": "node-updates/sec on 1 MI355X (grouped vs plain kernel)",
+        "value": value,
+        "unit": "node-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: random PBN n={n}, p={net['p']}, "
+                               f"{cfg.ntraj} trajectories x {cfg.steps} steps (+{cfg.burn_in} burn-in)",
+                   "n": n, "n_kept": plan.info["n_kept"], "slots": plan.info["n_slots"],
+                   "table_slots": plan.info["n_table_slots"], "trajectories": cfg.ntraj,
+                   "sim_steps": cfg.steps, "burn_in": cfg.burn_in,
+                   "function_step_fraction": (1 - net["p"]) ** n,
+                   "density": ps.density(net), "prep_seconds": prep,
+                   "estimate": {"p_hat": p_hat, "half_width_95": hw}},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_ALU / 1e12,
+                     "unit": "Tops/s (int32 VALU lane-ops)", "frac": achieved / PEAK_ALU, "traffic": None,
+                     "kernel": "k_simulate", "ops_per_traj_step": w_step,
+                     "avg_launch_ms": avg_launch * 1e3, "steps_per_launch": avg_steps,
+                     "kernel_node_updates_per_s": kernel_rate},
+        "compare": compare,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

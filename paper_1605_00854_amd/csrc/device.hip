@@ -75,8 +75,129 @@ struct SimParams {
   pbn_targets tg;
 };
 
-template <bool IMG_LDS, bool TABLES>
+// Per-lane data of one slot, either cached in registers for the whole launch
+// (plans of at most NREG lane passes) or reloaded from the image every pass.
+template <int PW, int TTW>
+struct SlotRegs {
+  uint32_t info, base, choice, radix;   // slot record
+  uint32_t draw, thr0, thr1, thr2;      // FN slot of a multi-predictor node: its choice record
+  uint32_t pw[PW];                      // FN single-predictor: parent words; TABLE: union parents
+  uint32_t tt[TTW];                     // FN single-predictor: truth-table words
+};
+
+template <int K>
+__device__ __forceinline__ uint32_t gather(const uint8_t* cs, const uint32_t* pw) {
+  // all K byte reads are independent: issued back to back, one wait
+  uint32_t b[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) b[k] = cs[(k & 1) ? (pw[k >> 1] >> 16) : (pw[k >> 1] & 0xFFFFu)];
+  uint32_t idx = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) idx |= b[k] << k;
+  return idx;
+}
+
+__device__ __forceinline__ uint32_t choose(uint32_t w, uint32_t t0, uint32_t t1, uint32_t t2, uint32_t nfn) {
+  const uint32_t j = uint32_t(w >= t0) + uint32_t(w >= t1) + uint32_t(w >= t2);
+  return min(j, nfn - 1u);
+}
+
+template <int PM, int UM>
+struct Shape {
+  static constexpr int PW = ((PM > UM ? PM : UM) + 1) / 2;
+  static constexpr int TTW = PM <= 5 ? 1 : 4;
+};
+
+template <int PM, int UM>
+__device__ __forceinline__ void load_slot(SlotRegs<Shape<PM, UM>::PW, Shape<PM, UM>::TTW>& r, const uint8_t* img,
+                                          uint32_t slot) {
+  constexpr int PW = Shape<PM, UM>::PW, TTW = Shape<PM, UM>::TTW;
+  const uint4 rec = reinterpret_cast<const uint4*>(img)[slot];
+  r.info = rec.x;
+  r.base = rec.y;
+  r.choice = rec.z;
+  r.radix = rec.w;
+  r.draw = 0;
+  r.thr0 = r.thr1 = r.thr2 = 0xFFFFFFFFu;
+#pragma unroll
+  for (int k = 0; k < PW; ++k) r.pw[k] = 0;
+#pragma unroll
+  for (int k = 0; k < TTW; ++k) r.tt[k] = 0;
+  if (!(rec.x & PBN_SLOT_VALID)) return;
+  if (UM > 0 && (rec.x & PBN_SLOT_TABLE)) {
+    const uint32_t* up = reinterpret_cast<const uint32_t*>(img + rec.y);
+#pragma unroll
+    for (int k = 0; k < PW; ++k) r.pw[k] = up[k];
+    return;
+  }
+  if (PBN_SLOT_NMULTI(rec.x)) {
+    const uint4 ch = *reinterpret_cast<const uint4*>(img + rec.z);
+    r.draw = ch.x;
+    r.thr0 = ch.y;
+    r.thr1 = ch.z;
+    r.thr2 = ch.w;
+  } else {
+    const uint32_t* fr = reinterpret_cast<const uint32_t*>(img + rec.y);
+#pragma unroll
+    for (int k = 0; k < PW; ++k) r.pw[k] = fr[k];
+#pragma unroll
+    for (int k = 0; k < TTW; ++k) r.tt[k] = fr[4 + k];
+  }
+}
+
+// Evaluate one slot from state `cs`; returns the word to store (one byte per member).
+template <int PM, int UM>
+__device__ __forceinline__ uint32_t eval_slot(const SlotRegs<Shape<PM, UM>::PW, Shape<PM, UM>::TTW>& r,
+                                              const uint8_t* img, const uint8_t* cs, const uint8_t* rs) {
+  constexpr int PW = Shape<PM, UM>::PW, TTW = Shape<PM, UM>::TTW;
+  uint32_t out = 0;
+  if (UM > 0 && (r.info & PBN_SLOT_TABLE)) {
+    // combined predictor functions of a group: mixed-radix choice, union parents
+    uint32_t c = 0;
+    const uint32_t nm = PBN_SLOT_NMULTI(r.info);
+    for (uint32_t m = 0; m < nm; ++m) {
+      const uint4 ch = *reinterpret_cast<const uint4*>(img + r.choice + 16u * m);
+      const uint32_t w = *reinterpret_cast<const uint32_t*>(rs + (ch.x & 0xFFFFFFu));
+      c += choose(w, ch.y, ch.z, ch.w, ch.x >> 24) * ((r.radix >> (8u * m)) & 0xFFu);
+    }
+    const uint32_t x = gather<(UM > 0 ? UM : 1)>(cs, r.pw);
+    const uint32_t v = img[r.base + 32u + (c << PBN_SLOT_NU(r.info)) + x];
+    out = (v * 0x204081u) & 0x01010101u;
+  } else {
+    uint32_t pw[PW], tt[TTW];
+#pragma unroll
+    for (int k = 0; k < PW; ++k) pw[k] = r.pw[k];
+#pragma unroll
+    for (int k = 0; k < TTW; ++k) tt[k] = r.tt[k];
+    if (PBN_SLOT_NMULTI(r.info)) {
+      const uint32_t w = *reinterpret_cast<const uint32_t*>(rs + (r.draw & 0xFFFFFFu));
+      const uint32_t j = choose(w, r.thr0, r.thr1, r.thr2, r.draw >> 24);
+      const uint4* fr = reinterpret_cast<const uint4*>(img + r.base + 32u * j);
+      const uint4 a0 = fr[0], a1 = fr[1];
+      const uint32_t f[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+#pragma unroll
+      for (int k = 0; k < PW; ++k) pw[k] = f[k];
+#pragma unroll
+      for (int k = 0; k < TTW; ++k) tt[k] = f[4 + k];
+    }
+    const uint32_t idx = gather<PM>(cs, pw);
+    uint32_t ttw = tt[0];
+    if constexpr (TTW > 1) {
+      const uint32_t q = idx >> 5;
+      ttw = q == 0 ? tt[0] : q == 1 ? tt[1] : q == 2 ? tt[2] : tt[3];
+    }
+    out = (ttw >> (idx & 31u)) & 1u;
+  }
+  return out;
+}
+
+// PM: parent bytes gathered per FN slot (>= the plan's largest predictor);
+// UM: union bits gathered per TABLE slot (0: no table slots);
+// NREG: lane passes whose slot data stay in registers (0: reload every pass).
+template <bool IMG_LDS, int PM, int UM, int NREG>
 __global__ void __launch_bounds__(1024) k_simulate(SimParams a) {
+  constexpr int PW = Shape<PM, UM>::PW, TTW = Shape<PM, UM>::TTW;
+  using Regs = SlotRegs<PW, TTW>;
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   const pbn_plan_header* H = reinterpret_cast<const pbn_plan_header*>(a.blob);
   const uint32_t lane = threadIdx.x & 63u;
@@ -86,7 +207,6 @@ __global__ void __launch_bounds__(1024) k_simulate(SimParams a) {
   const uint32_t sdp = (sd + 3u) & ~3u;   // state buffer, padded to 16 bytes
   const uint32_t img_bytes = H->image_bytes;
   const uint8_t* gimg = a.blob + H->image_off;
-  const pbn_pass_info* pinfo = reinterpret_cast<const pbn_pass_info*>(a.blob + H->pass_off);
   const unsigned long long* Q = reinterpret_cast<const unsigned long long*>(a.blob + H->q_off);
   const uint32_t* o2p = reinterpret_cast<const uint32_t*>(a.blob + H->o2p_off);
   const uint32_t* blk = reinterpret_cast<const uint32_t*>(a.blob + H->blk_off);
@@ -123,6 +243,17 @@ __global__ void __launch_bounds__(1024) k_simulate(SimParams a) {
     }
     sbuf0[s] = v;
     sbuf1[s] = 0;
+  }
+
+  Regs cached[NREG > 0 ? NREG : 1];
+  if constexpr (NREG > 0) {
+#pragma unroll
+    for (int p = 0; p < NREG; ++p) {
+      if (uint32_t(p) < npass)
+        load_slot<PM, UM>(cached[p], img, uint32_t(p) * 64u + lane);
+      else
+        cached[p].info = 0;   // no such pass: the slot-record region ends before it
+    }
   }
   wave_sync();
 
@@ -195,60 +326,17 @@ __global__ void __launch_bounds__(1024) k_simulate(SimParams a) {
       } else {
         const uint8_t* csb = reinterpret_cast<const uint8_t*>(cs);
         uint32_t* ns = cur ? sbuf0 : sbuf1;
-        for (uint32_t p = 0; p < npass; ++p) {
-          const pbn_pass_info pi = pinfo[p];
-          const uint32_t slot = p * 64u + lane;
-          const uint4 rec = reinterpret_cast<const uint4*>(img)[slot];
-          uint32_t out = 0;
-          if (TABLES && (rec.x & PBN_SLOT_TABLE)) {
-            uint32_t c = 0;
-            const uint32_t nm = PBN_SLOT_NMULTI(rec.x);
-            for (uint32_t m = 0; m < pi.mmax; ++m) {
-              if (m < nm) {
-                const uint4 ch = *reinterpret_cast<const uint4*>(img + rec.z + 16u * m);
-                const uint32_t w = *reinterpret_cast<const uint32_t*>(rs + (ch.x & 0xFFFFFFu));
-                uint32_t j = uint32_t(w >= ch.y) + uint32_t(w >= ch.z) + uint32_t(w >= ch.w);
-                j = min(j, (ch.x >> 24) - 1u);
-                c += j * ((rec.w >> (8u * m)) & 0xFFu);
-              }
-            }
-            const uint8_t* tb = img + rec.y;
-            const uint4 u0 = *reinterpret_cast<const uint4*>(tb);
-            const uint4 u1 = *reinterpret_cast<const uint4*>(tb + 16);
-            const uint32_t pw[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
-            uint32_t x = 0;
+        if constexpr (NREG > 0) {
 #pragma unroll
-            for (uint32_t k = 0; k < 16u; ++k) {
-              if (k < pi.umax) {
-                const uint32_t pos = (k & 1u) ? (pw[k >> 1] >> 16) : (pw[k >> 1] & 0xFFFFu);
-                x |= uint32_t(csb[pos]) << k;
-              }
-            }
-            const uint32_t v = tb[32u + (c << PBN_SLOT_NU(rec.x)) + x];
-            out = (v * 0x204081u) & 0x01010101u;
-          } else if (rec.x & PBN_SLOT_VALID) {
-            uint32_t j = 0;
-            if (PBN_SLOT_NMULTI(rec.x)) {
-              const uint4 ch = *reinterpret_cast<const uint4*>(img + rec.z);
-              const uint32_t w = *reinterpret_cast<const uint32_t*>(rs + (ch.x & 0xFFFFFFu));
-              j = uint32_t(w >= ch.y) + uint32_t(w >= ch.z) + uint32_t(w >= ch.w);
-              j = min(j, (ch.x >> 24) - 1u);
-            }
-            const uint8_t* fr = img + rec.y + 32u * j;
-            const uint4 pp = *reinterpret_cast<const uint4*>(fr);
-            const uint32_t pw[4] = {pp.x, pp.y, pp.z, pp.w};
-            uint32_t idx = 0;
-#pragma unroll
-            for (uint32_t k = 0; k < 8u; ++k) {
-              if (k < pi.pmax) {
-                const uint32_t pos = (k & 1u) ? (pw[k >> 1] >> 16) : (pw[k >> 1] & 0xFFFFu);
-                idx |= uint32_t(csb[pos]) << k;
-              }
-            }
-            const uint32_t ttw = *reinterpret_cast<const uint32_t*>(fr + 16u + 4u * (idx >> 5));
-            out = (ttw >> (idx & 31u)) & 1u;
+          for (int p = 0; p < NREG; ++p) {
+            if (cached[p].info & PBN_SLOT_VALID) ns[uint32_t(p) * 64u + lane] = eval_slot<PM, UM>(cached[p], img, csb, rs);
           }
-          if (rec.x & PBN_SLOT_VALID) ns[slot] = out;
+        } else {
+          for (uint32_t p = 0; p < npass; ++p) {
+            Regs r;
+            load_slot<PM, UM>(r, img, p * 64u + lane);
+            if (r.info & PBN_SLOT_VALID) ns[p * 64u + lane] = eval_slot<PM, UM>(r, img, csb, rs);
+          }
         }
         cur ^= 1u;
         wave_sync();
@@ -351,9 +439,9 @@ uint32_t grid_for(size_t work, uint32_t block) {
 
 constexpr uint32_t kLdsMax = 160u * 1024u;
 
-template <bool IMG_LDS, bool TABLES>
+template <bool IMG_LDS, int PM, int UM, int NREG>
 pbn_status launch_sim(const SimParams& p, uint32_t blocks, uint32_t lds, hipStream_t stream) {
-  auto* fn = k_simulate<IMG_LDS, TABLES>;
+  auto* fn = k_simulate<IMG_LDS, PM, UM, NREG>;
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -363,6 +451,27 @@ pbn_status launch_sim(const SimParams& p, uint32_t blocks, uint32_t lds, hipStre
   }
   hipLaunchKernelGGL(fn, dim3(blocks), dim3(64u * p.wpb), lds, stream, p);
   return hip_check(hipGetLastError(), "k_simulate launch");
+}
+
+// Instantiation choice: the smallest gather widths that cover the plan.
+template <bool IMG_LDS, int PM, int UM>
+pbn_status dispatch_nreg(const SimParams& p, uint32_t npass, uint32_t blocks, uint32_t lds, hipStream_t s) {
+  if (npass <= 2) return launch_sim<IMG_LDS, PM, UM, 2>(p, blocks, lds, s);
+  return launch_sim<IMG_LDS, PM, UM, 0>(p, blocks, lds, s);
+}
+
+template <bool IMG_LDS, int PM>
+pbn_status dispatch_um(const SimParams& p, uint32_t umax, uint32_t npass, uint32_t blocks, uint32_t lds, hipStream_t s) {
+  if (umax == 0) return dispatch_nreg<IMG_LDS, PM, 0>(p, npass, blocks, lds, s);
+  if (umax <= 8) return dispatch_nreg<IMG_LDS, PM, 8>(p, npass, blocks, lds, s);
+  return dispatch_nreg<IMG_LDS, PM, 16>(p, npass, blocks, lds, s);
+}
+
+template <bool IMG_LDS>
+pbn_status dispatch_pm(const SimParams& p, uint32_t pmax, uint32_t umax, uint32_t npass, uint32_t blocks, uint32_t lds,
+                       hipStream_t s) {
+  if (pmax <= 5) return dispatch_um<IMG_LDS, 5>(p, umax, npass, blocks, lds, s);
+  return dispatch_um<IMG_LDS, 7>(p, umax, npass, blocks, lds, s);
 }
 
 pbn_status simulate_common(bool plain, const pbn_plan* plan, const void* d_plan, uint64_t seed, uint32_t traj0,
@@ -406,9 +515,11 @@ pbn_status simulate_common(bool plain, const pbn_plan* plan, const void* d_plan,
   const uint32_t blocks = (ntraj + wpb - 1) / wpb;
   const uint32_t lds = img + wpb * wave_bytes;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (plain)
-    return img_lds ? launch_sim<true, false>(p, blocks, lds, s) : launch_sim<false, false>(p, blocks, lds, s);
-  return img_lds ? launch_sim<true, true>(p, blocks, lds, s) : launch_sim<false, true>(p, blocks, lds, s);
+  const uint32_t pmax = plan->info.max_fn_parents, umax = plan->info.max_union_bits;
+  const uint32_t npass = plan->info.n_passes;
+  if (pmax > 7 || umax > 16) return fail(PBN_ELDS, "plan exceeds the kernel's gather widths");
+  return img_lds ? dispatch_pm<true>(p, pmax, umax, npass, blocks, lds, s)
+                 : dispatch_pm<false>(p, pmax, umax, npass, blocks, lds, s);
 }
 
 }  // namespace
