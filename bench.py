@@ -149,6 +149,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the plain and reduction kernels")
     ap.add_argument("--wpb", type=int, default=0)
+    ap.add_argument("--quick-tune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is design-only "
@@ -171,13 +172,26 @@ def main():
     n = net["n"]
     work = cfg.ntraj * (cfg.burn_in + cfg.steps) * n
 
+    # autotuner: preparation options and launch shape, by short probe runs
+    from paper_1605_00854_amd import autotune
+    interest = sorted({a for tg in cfg.targets for a, _ in tg})
+    t_tune = time.perf_counter()
+    best_opts, best_wpb, trials = autotune.tune(net, interest, cfg.targets, cfg.ntraj, seed=cfg.seed,
+                                                quick=args.quick_tune)
+    t_tune = time.perf_counter() - t_tune
+    if args.wpb:
+        best_wpb = args.wpb
+    grouped_trials = [t for t in trials if t.get("opts", {}).get("group") and "node_updates_per_s" in t]
+    best_grouped = max(grouped_trials, key=lambda t: t["node_updates_per_s"]) if grouped_trials else None
+    product_plain = not best_opts.get("group", 0)
+
     for _ in range(args.warmup):
-        run_step(api, torch, cfg, PLANS["grouped"], False, args.chunk, [], args.wpb)
+        run_step(api, torch, cfg, best_opts, product_plain, args.chunk, [], best_wpb)
     torch.cuda.synchronize()
     events = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        plan, p_hat, hw, prep = run_step(api, torch, cfg, PLANS["grouped"], False, args.chunk, events, args.wpb)
+        plan, p_hat, hw, prep = run_step(api, torch, cfg, best_opts, product_plain, args.chunk, events, best_wpb)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_per_step = 1e3 * dt / args.steps
@@ -194,18 +208,28 @@ def main():
 
     compare = {}
     if not args.no_compare:
-        for name in ("plain", "reduction"):
+        variants = {"plain": (PLANS["plain"], True, 0), "reduction": (PLANS["reduction"], True, 0),
+                    "grouped_default": (PLANS["grouped"], False, 0)}
+        if best_grouped:
+            variants["grouped_tuned"] = (best_grouped["opts"], False, best_grouped["wpb"])
+        for name, (opts, plain, wpb) in variants.items():
             ev = []
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            pl, ph, _, _ = run_step(api, torch, cfg, PLANS[name], True, args.chunk, ev, args.wpb)
+            pl, ph, _, _ = run_step(api, torch, cfg, opts, plain, args.chunk, ev, wpb)
             torch.cuda.synchronize()
             d = time.perf_counter() - t1
             kt = sum(e0.elapsed_time(e1) * 1e-3 for e0, e1, _ in ev)
             compare[name] = {"node_updates_per_s": work / d, "kernel_node_updates_per_s": work / kt,
-                             "n_kept": pl.info["n_kept"], "slots": pl.info["n_slots"], "p_hat": ph}
-        compare["grouped_over_plain"] = value / compare["plain"]["node_updates_per_s"]
-        compare["grouped_over_reduction"] = value / compare["reduction"]["node_updates_per_s"]
+                             "n_kept": pl.info["n_kept"], "slots": pl.info["n_slots"],
+                             "table_slots": pl.info["n_table_slots"], "opts": opts, "p_hat": ph}
+        compare["product_over_plain"] = value / compare["plain"]["node_updates_per_s"]
+        compare["reduction_over_plain"] = (compare["reduction"]["node_updates_per_s"]
+                                           / compare["plain"]["node_updates_per_s"])
+        for name in ("grouped_default", "grouped_tuned"):
+            if name in compare:
+                compare[name + "_over_plain"] = (compare[name]["node_updates_per_s"]
+                                                 / compare["plain"]["node_updates_per_s"])
 
     out = {
         "metric": "node-updates/sec on 1 MI355X (grouped vs plain kernel)",
@@ -227,6 +251,8 @@ def main():
                    "sim_steps": cfg.steps, "burn_in": cfg.burn_in,
                    "function_step_fraction": (1 - net["p"]) ** n,
                    "density": ps.density(net), "prep_seconds": prep,
+                   "plan": best_opts, "waves_per_block": best_wpb, "autotune_seconds": t_tune,
+                   "autotune_trials": len(trials),
                    "estimate": {"p_hat": p_hat, "half_width_95": hw}},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_ALU / 1e12,
                      "unit": "Tops/s (int32 VALU lane-ops)", "frac": achieved / PEAK_ALU, "traffic": None,

@@ -1,0 +1,90 @@
+"""Autotuner: picks the preparation options (reduction, grouping caps, weights)
+and the launch shape (trajectories per workgroup) of the step kernel by timing
+short probe runs on the device.
+
+Every candidate simulates the same trajectories bit for bit (reduction and
+grouping never change a kept node), so the choice is purely a speed choice.
+The GPU payoff of the paper's node grouping depends on the network: grouping
+pays when it removes whole lane passes or lets several cheap nodes share one
+lookup (sparse networks with many single-predictor nodes), and loses when
+combined tables need more parent bits than the nodes they merge (dense,
+multi-predictor networks).
+"""
+import time
+
+import numpy as np
+
+from . import api
+
+PLAIN = dict(reduce=0, group=0)
+REDUCTION = dict(reduce=1, group=0)
+
+
+def candidates(quick=False):
+    out = [PLAIN, REDUCTION]
+    bits = (4, 6, 8) if quick else (4, 5, 6, 8, 10, 12)
+    nodes = (2, 4) if quick else (2, 3, 4)
+    for b in bits:
+        for g in nodes:
+            out.append(dict(reduce=1, group=1, max_parent_bits=b, max_group_nodes=g))
+    out.append(dict(reduce=1, group=1, weight_mode=0, theta=1 << 20, max_parent_bits=8, max_group_nodes=4))
+    return out
+
+
+_CACHE = {}
+
+
+def _probe(torch, plan, tg, seed, ntraj, steps, wpb, plain):
+    state = api.state_init(plan, seed, ntraj)
+    counts = api.new_counts(tg.ntargets, ntraj)
+    api.simulate(plan, seed, state, counts, tg, 0, min(steps, 64), plain=plain, waves_per_block=wpb)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    api.simulate(plan, seed, state, counts, tg, 64, steps, plain=plain, waves_per_block=wpb)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) * 1e-3
+
+
+def tune(net, interest, target_sets, ntraj, seed=1, probe_steps=2000, wpbs=(2, 4, 8), quick=False,
+         key=None, verbose=False):
+    """Return (best plan options, best waves_per_block, list of trials).
+
+    Trials report node-updates/s of the probe (n_original per trajectory-step).
+    """
+    import torch
+    key = key or (id(net), ntraj, tuple(interest), probe_steps, quick)
+    if key in _CACHE:
+        return _CACHE[key]
+    n = int(net["n"])
+    trials = []
+    seen = set()
+    for opts in candidates(quick):
+        try:
+            plan = api.Plan(net, interest=interest, **opts)
+        except api._lib.PbnError as e:      # a cap the network cannot meet
+            trials.append({"opts": opts, "error": str(e)})
+            continue
+        sig = (plan.info["n_slots"], plan.info["n_table_slots"], plan.info["max_union_bits"],
+               plan.info["n_kept"], plan.info["image_in_lds"], plan.info["table_bytes"])
+        if sig in seen:
+            continue
+        seen.add(sig)
+        tg = plan.targets(target_sets)
+        plain = plan.info["n_table_slots"] == 0
+        for wpb in wpbs:
+            dt = _probe(torch, plan, tg, seed, ntraj, probe_steps, wpb, plain)
+            rate = ntraj * probe_steps * n / dt
+            trials.append({"opts": opts, "wpb": wpb, "node_updates_per_s": rate, "slots": plan.info["n_slots"],
+                           "table_slots": plan.info["n_table_slots"], "passes": plan.info["n_passes"]})
+            if verbose:
+                print(f"[autotune] {opts} wpb={wpb} slots={plan.info['n_slots']} "
+                      f"tables={plan.info['n_table_slots']} {rate:.3e}", flush=True)
+    ok = [t for t in trials if "node_updates_per_s" in t]
+    best = max(ok, key=lambda t: t["node_updates_per_s"])
+    out = (best["opts"], best["wpb"], trials)
+    _CACHE[key] = out
+    return out

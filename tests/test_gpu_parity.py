@@ -228,3 +228,29 @@ def test_c1_estimate_matches_power_method():
     p_hat = means.mean()
     hw = 3.29 * means.std(ddof=1) / math.sqrt(B)
     assert abs(p_hat - want) < hw, (p_hat, want, hw)
+
+
+@pytest.mark.parametrize("name", ["c2", "sparse120"])
+def test_autotune_candidates_are_bit_identical(name):
+    """Every preparation the autotuner may pick simulates the same kept-node bits."""
+    from paper_1605_00854_amd import autotune
+    net = net_of(name)
+    tgs = targets_of(net)
+    interest = sorted({a for tg in tgs for a, _ in tg})
+    ref = None
+    for opts in autotune.candidates(quick=True):
+        plan = api.Plan(net, interest=interest, **opts)
+        say(f"[gpu] autotune candidate {name} {opts} slots={plan.info['n_slots']}")
+        tg = plan.targets(tgs)
+        state = api.state_init(plan, 21, 40)
+        counts = api.new_counts(len(tgs), 40)
+        api.simulate(plan, 21, state, counts, tg, 0, 500, plain=plan.info["n_table_slots"] == 0,
+                     waves_per_block=2)
+        orig = api.unpack_bits(api.to_original(plan, state).cpu().numpy(), plan.n)
+        kept = plan.node_pos() != NONE
+        c = counts.cpu().numpy()
+        if ref is None:
+            ref = (orig, kept, c)
+        common = kept & ref[1]
+        assert np.array_equal(orig[:, common], ref[0][:, common]), opts
+        assert np.array_equal(c, ref[2]), opts
