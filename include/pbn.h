@@ -275,6 +275,61 @@ pbn_status pbn_simulate_plain(const pbn_plan* plan, const void* d_plan, uint64_t
 pbn_status pbn_state_to_original(const pbn_plan* plan, const void* d_plan, const uint32_t* d_state,
                                  uint32_t ntraj, uint32_t* d_out, void* stream);
 
+/* ----------------------------------------------------------------- batches
+ * Many networks of uneven size advanced together by one persistent launch
+ * (the step kernel of pbn_simulate, per trajectory, with a task loop on top).
+ * A task is up to `waves_per_block` consecutive trajectories of one network;
+ * workgroups claim tasks with one atomic increment of d_ctl->next_task and exit
+ * when none is left.  Every item is simulated over the device-held step window
+ * [d_ctl->step0, d_ctl->step0 + d_ctl->nsteps); each launch resets the task
+ * counter first and advances step0 by nsteps last, with small kernels (no
+ * memset, no allocation, no host synchronisation), so launches can be captured
+ * into a HIP graph and replayed.  Results are bit-identical to pbn_simulate on
+ * each network alone.
+ *
+ * pbn_work (device array, caller-owned, one per network):
+ *   d_plan     device blob of plans[k];  d_targets  device copy of its pbn_targets
+ *   d_state    [ntraj][state_words];     d_counts   [ntargets][ntraj][3] (added to)
+ *   seed, traj0, ntraj, count_from as in pbn_simulate
+ * pbn_batch_tasks: host; task order (largest networks first).  tasks / task_first
+ *   receive the item and first trajectory of each task (NULL to query *ntasks).
+ * pbn_batch_launch: enqueue one pass on `stream`.
+ * pbn_batch_graph_create: capture `passes` consecutive launches into a graph,
+ *   replayed by pbn_graph_launch (each replay advances by passes * nsteps).
+ * Errors: PBN_EINVAL, PBN_ELDS (one workgroup's states exceed LDS), PBN_EHIP. */
+typedef struct pbn_work {
+  const void* d_plan;
+  const pbn_targets* d_targets;
+  uint32_t* d_state;
+  uint64_t* d_counts;
+  uint64_t seed;
+  uint32_t traj0, ntraj;
+  uint32_t count_from;
+  uint32_t reserved;
+} pbn_work;
+
+typedef struct pbn_batch_ctl {
+  uint32_t next_task;
+  uint32_t step0;
+  uint32_t nsteps;
+  uint32_t reserved;
+} pbn_batch_ctl;
+
+typedef struct pbn_graph pbn_graph;
+
+pbn_status pbn_batch_tasks(const pbn_plan* const* plans, const uint32_t* ntraj, uint32_t nitems,
+                           uint32_t waves_per_block, uint32_t* tasks, uint32_t* task_first,
+                           uint32_t* ntasks);
+pbn_status pbn_batch_launch(const pbn_plan* const* plans, uint32_t nitems, const pbn_work* d_items,
+                            const uint32_t* d_tasks, const uint32_t* d_task_first, uint32_t ntasks,
+                            pbn_batch_ctl* d_ctl, uint32_t waves_per_block, void* stream);
+pbn_status pbn_batch_graph_create(const pbn_plan* const* plans, uint32_t nitems, const pbn_work* d_items,
+                                  const uint32_t* d_tasks, const uint32_t* d_task_first, uint32_t ntasks,
+                                  pbn_batch_ctl* d_ctl, uint32_t waves_per_block, uint32_t passes,
+                                  pbn_graph** out);
+pbn_status pbn_graph_launch(pbn_graph* graph, void* stream);
+pbn_status pbn_graph_destroy(pbn_graph* graph);
+
 #ifdef __cplusplus
 }
 #endif

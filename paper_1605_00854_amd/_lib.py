@@ -49,6 +49,12 @@ class pbn_launch_opts(C.Structure):
     _fields_ = [("waves_per_block", C.c_uint32), ("reserved", C.c_uint32 * 3)]
 
 
+class pbn_work(C.Structure):
+    _fields_ = [("d_plan", C.c_void_p), ("d_targets", C.c_void_p), ("d_state", C.c_void_p),
+                ("d_counts", C.c_void_p), ("seed", C.c_uint64), ("traj0", C.c_uint32),
+                ("ntraj", C.c_uint32), ("count_from", C.c_uint32), ("reserved", C.c_uint32)]
+
+
 _lib = None
 
 # name -> (restype, argtypes)
@@ -77,6 +83,12 @@ SIGNATURES = {
     "pbn_simulate_plain": (C.c_int32, [_P, _P, _U64, _U32, _U32, _U32, _U32, _U32,
                                        C.POINTER(pbn_targets), _P, _P, C.POINTER(pbn_launch_opts), _P]),
     "pbn_state_to_original": (C.c_int32, [_P, _P, _P, _U32, _P, _P]),
+    "pbn_batch_tasks": (C.c_int32, [C.POINTER(_P), _pU32, _U32, _U32, _pU32, _pU32, _pU32]),
+    "pbn_batch_launch": (C.c_int32, [C.POINTER(_P), _U32, _P, _P, _P, _U32, _P, _U32, _P]),
+    "pbn_batch_graph_create": (C.c_int32, [C.POINTER(_P), _U32, _P, _P, _P, _U32, _P, _U32, _U32,
+                                           C.POINTER(_P)]),
+    "pbn_graph_launch": (C.c_int32, [_P, _P]),
+    "pbn_graph_destroy": (C.c_int32, [_P]),
 }
 
 

@@ -219,3 +219,89 @@ def unpack_bits(words, n):
     w = np.asarray(words).astype(np.uint32)
     bits = ((w[:, :, None] >> np.arange(32, dtype=np.uint32)) & 1).astype(np.uint8)
     return bits.reshape(w.shape[0], -1)[:, :n]
+
+
+# ----------------------------------------------------------------- batches
+
+def _to_device_bytes(obj):
+    import torch
+    raw = np.frombuffer(C.string_at(C.addressof(obj), C.sizeof(obj)), dtype=np.uint8).copy()
+    return torch.from_numpy(raw).to("cuda")
+
+
+class Batch:
+    """Many networks advanced by one persistent launch (pbn_batch_launch).
+
+    items: list of (plan, seed, ntraj, target_sets); every trajectory of every
+    network shares the device step window held in the control block.
+    """
+
+    def __init__(self, items, count_from=0, waves_per_block=4):
+        import torch
+        self.plans = [it[0] for it in items]
+        self.wpb = int(waves_per_block)
+        self.targets, self.states, self.counts, self._tg_dev = [], [], [], []
+        works = (_lib.pbn_work * len(items))()
+        for k, (plan, seed, ntraj, target_sets) in enumerate(items):
+            tg = plan.targets(target_sets)
+            tg_dev = _to_device_bytes(tg)
+            state = new_state(plan, ntraj)
+            counts = new_counts(tg.ntargets, ntraj)
+            self.targets.append(tg)
+            self._tg_dev.append(tg_dev)
+            self.states.append(state)
+            self.counts.append(counts)
+            works[k] = _lib.pbn_work(plan.device().data_ptr(), tg_dev.data_ptr(), state.data_ptr(),
+                                     counts.data_ptr(), int(seed), 0, int(ntraj), int(count_from), 0)
+            self.states[k] = state
+        self.seeds = [int(it[1]) for it in items]
+        self._works = works
+        self.items_dev = _to_device_bytes(works)
+        self._plan_arr = (C.c_void_p * len(items))(*[p.handle.value for p in self.plans])
+        ntraj = np.asarray([it[2] for it in items], dtype=np.uint32)
+        nt = C.c_uint32()
+        check(lib().pbn_batch_tasks(self._plan_arr, _ptr(ntraj, C.c_uint32), len(items), self.wpb,
+                                    None, None, C.byref(nt)))
+        tasks = np.zeros(max(1, nt.value), dtype=np.uint32)
+        first = np.zeros(max(1, nt.value), dtype=np.uint32)
+        check(lib().pbn_batch_tasks(self._plan_arr, _ptr(ntraj, C.c_uint32), len(items), self.wpb,
+                                    _ptr(tasks, C.c_uint32), _ptr(first, C.c_uint32), C.byref(nt)))
+        self.ntasks = nt.value
+        self.tasks_dev = torch.from_numpy(tasks.astype(np.int32)).to("cuda")
+        self.first_dev = torch.from_numpy(first.astype(np.int32)).to("cuda")
+        self.ctl = torch.zeros(4, dtype=torch.int32, device="cuda")
+
+    def init_states(self, stream=None):
+        for plan, seed, state in zip(self.plans, self.seeds, self.states):
+            check(lib().pbn_state_init(plan.handle, _dptr(plan.device()), seed, 0, state.shape[0],
+                                       _dptr(state), _stream(stream)))
+
+    def set_window(self, step0, nsteps):
+        import torch
+        self.ctl.copy_(torch.tensor([0, int(step0), int(nsteps), 0], dtype=torch.int32))
+
+    def _args(self):
+        return (self._plan_arr, len(self.plans), _dptr(self.items_dev), _dptr(self.tasks_dev),
+                _dptr(self.first_dev), self.ntasks, _dptr(self.ctl), self.wpb)
+
+    def launch(self, stream=None):
+        check(lib().pbn_batch_launch(*self._args(), _stream(stream)))
+
+    def graph(self, passes):
+        g = C.c_void_p()
+        check(lib().pbn_batch_graph_create(*self._args(), int(passes), C.byref(g)))
+        return Graph(g)
+
+
+class Graph:
+    def __init__(self, handle):
+        self.handle = handle
+
+    def launch(self, stream=None):
+        check(lib().pbn_graph_launch(self.handle, _stream(stream)))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib._lib is not None:
+            _lib._lib.pbn_graph_destroy(h)
+            self.handle = None

@@ -191,50 +191,46 @@ __device__ __forceinline__ uint32_t eval_slot(const SlotRegs<Shape<PM, UM>::PW, 
   return out;
 }
 
+// Everything one wavefront needs to advance one trajectory.
+struct TrajArgs {
+  const uint8_t* blob;              // plan blob (global memory)
+  const uint8_t* img;               // plan image: LDS copy or the blob's own image
+  uint8_t* wb;                      // this wave's LDS: two state buffers + ring
+  unsigned long long seed;
+  uint32_t traj;                    // global trajectory id (Philox counter word 0)
+  uint32_t tl;                      // index within the launch's state/count arrays
+  uint32_t ntraj;                   // trajectories of the launch (count layout)
+  uint32_t step0, nsteps, count_from;
+  uint32_t* state;                  // [ntraj][state_words]
+  unsigned long long* counts;       // [ntargets][ntraj][3]
+  const pbn_targets* tg;
+};
+
 // PM: parent bytes gathered per FN slot (>= the plan's largest predictor);
 // UM: union bits gathered per TABLE slot (0: no table slots);
 // NREG: lane passes whose slot data stay in registers (0: reload every pass).
-template <bool IMG_LDS, int PM, int UM, int NREG>
-__global__ void __launch_bounds__(1024) k_simulate(SimParams a) {
+template <int PM, int UM, int NREG>
+__device__ __forceinline__ void run_traj(const TrajArgs& a) {
   constexpr int PW = Shape<PM, UM>::PW, TTW = Shape<PM, UM>::TTW;
   using Regs = SlotRegs<PW, TTW>;
-  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   const pbn_plan_header* H = reinterpret_cast<const pbn_plan_header*>(a.blob);
   const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t wave = threadIdx.x >> 6;
   const uint32_t n = H->n, nslots = H->n_slots, npass = H->n_passes, njobs = H->n_jobs;
   const uint32_t fill = H->fill_steps, sd = H->state_dwords, zero_pos = H->zero_pos;
   const uint32_t sdp = (sd + 3u) & ~3u;   // state buffer, padded to 16 bytes
-  const uint32_t img_bytes = H->image_bytes;
-  const uint8_t* gimg = a.blob + H->image_off;
   const unsigned long long* Q = reinterpret_cast<const unsigned long long*>(a.blob + H->q_off);
   const uint32_t* o2p = reinterpret_cast<const uint32_t*>(a.blob + H->o2p_off);
   const uint32_t* blk = reinterpret_cast<const uint32_t*>(a.blob + H->blk_off);
-
-  uint32_t img_lds = 0;
-  if constexpr (IMG_LDS) {
-    for (uint32_t o = threadIdx.x * 16u; o < img_bytes; o += blockDim.x * 16u)
-      *reinterpret_cast<uint4*>(smem + o) = *reinterpret_cast<const uint4*>(gimg + o);
-    img_lds = (img_bytes + 15u) & ~15u;
-  }
-  const uint8_t* img;
-  if constexpr (IMG_LDS)
-    img = smem;
-  else
-    img = gimg;
-  uint8_t* wb = smem + img_lds + wave * a.wave_bytes;
-  uint32_t* sbuf0 = reinterpret_cast<uint32_t*>(wb);
-  uint32_t* sbuf1 = reinterpret_cast<uint32_t*>(wb + 4u * sdp);
-  uint4* ring = reinterpret_cast<uint4*>(wb + 8u * sdp);
-  __syncthreads();
-  const uint32_t tl = blockIdx.x * a.wpb + wave;
-  if (tl >= a.ntraj) return;
-  const uint32_t traj = a.traj0 + tl;
+  const uint8_t* img = a.img;
+  uint32_t* sbuf0 = reinterpret_cast<uint32_t*>(a.wb);
+  uint32_t* sbuf1 = reinterpret_cast<uint32_t*>(a.wb + 4u * sdp);
+  uint4* ring = reinterpret_cast<uint4*>(a.wb + 8u * sdp);
+  const uint32_t traj = a.traj;
   const uint32_t k0 = uint32_t(a.seed), k1 = uint32_t(a.seed >> 32);
 
   // unpack the packed state (bit 4 s + k) into one byte per member
   const uint32_t W = H->state_words;
-  uint32_t* gst = a.state + size_t(tl) * W;
+  uint32_t* gst = a.state + size_t(a.tl) * W;
   for (uint32_t s = lane; s < sd; s += 64u) {
     uint32_t v = 0;
     if (s < nslots) {
@@ -258,10 +254,10 @@ __global__ void __launch_bounds__(1024) k_simulate(SimParams a) {
   wave_sync();
 
   // targets: lane k holds pair k; lane t counts target t
-  const uint32_t npairs = a.tg.npairs, ntg = a.tg.ntargets;
-  const uint32_t my_pos = lane < npairs ? a.tg.pos[lane] : zero_pos;
-  const uint32_t my_val = lane < npairs ? a.tg.val[lane] : 0u;
-  const unsigned long long my_mask = lane < ntg ? a.tg.mask[lane] : 0ull;
+  const uint32_t npairs = a.tg->npairs, ntg = a.tg->ntargets;
+  const uint32_t my_pos = lane < npairs ? a.tg->pos[lane] : zero_pos;
+  const uint32_t my_val = lane < npairs ? a.tg->val[lane] : 0u;
+  const unsigned long long my_mask = lane < ntg ? a.tg->mask[lane] : 0ull;
   auto target_z = [&](const uint8_t* s) -> bool {
     const uint32_t b = s[my_pos];
     const unsigned long long mism = __ballot(lane < npairs && b != my_val);
@@ -353,7 +349,7 @@ __global__ void __launch_bounds__(1024) k_simulate(SimParams a) {
   }
 
   if (lane < ntg) {
-    unsigned long long* c = a.counts + (size_t(lane) * a.ntraj + tl) * 3u;
+    unsigned long long* c = a.counts + (size_t(lane) * a.ntraj + a.tl) * 3u;
     c[0] += hits;
     c[1] += n01;
     c[2] += n10;
@@ -372,6 +368,103 @@ __global__ void __launch_bounds__(1024) k_simulate(SimParams a) {
     gst[w] = word;
   }
 }
+
+// One network: one wavefront per trajectory, the plan image staged in LDS when
+// it fits (IMG_LDS), shared by the workgroup's waves.
+template <bool IMG_LDS, int PM, int UM, int NREG>
+__global__ void __launch_bounds__(1024) k_simulate(SimParams a) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  const pbn_plan_header* H = reinterpret_cast<const pbn_plan_header*>(a.blob);
+  const uint32_t wave = threadIdx.x >> 6;
+  const uint32_t img_bytes = H->image_bytes;
+  const uint8_t* gimg = a.blob + H->image_off;
+  uint32_t img_lds = 0;
+  if constexpr (IMG_LDS) {
+    for (uint32_t o = threadIdx.x * 16u; o < img_bytes; o += blockDim.x * 16u)
+      *reinterpret_cast<uint4*>(smem + o) = *reinterpret_cast<const uint4*>(gimg + o);
+    img_lds = (img_bytes + 15u) & ~15u;
+  }
+  __syncthreads();
+  const uint32_t tl = blockIdx.x * a.wpb + wave;
+  if (tl >= a.ntraj) return;
+  TrajArgs t;
+  t.blob = a.blob;
+  if constexpr (IMG_LDS)
+    t.img = smem;
+  else
+    t.img = gimg;
+  t.wb = smem + img_lds + wave * a.wave_bytes;
+  t.seed = a.seed;
+  t.traj = a.traj0 + tl;
+  t.tl = tl;
+  t.ntraj = a.ntraj;
+  t.step0 = a.step0;
+  t.nsteps = a.nsteps;
+  t.count_from = a.count_from;
+  t.state = a.state;
+  t.counts = a.counts;
+  t.tg = &a.tg;
+  run_traj<PM, UM, NREG>(t);
+}
+
+// ---------------------------------------------------------------- batches
+// Many networks of uneven size in one persistent launch.  Work is cut into
+// tasks of `wpb` consecutive trajectories of one network, ordered by the host
+// (largest networks first); each workgroup repeatedly claims the next task with
+// one atomic increment and stops when none is left, so every wave reaches the
+// exit.  Plan images stay in global memory (the L2 serves them); each wave's
+// LDS holds its trajectory's state buffers and Philox ring.
+struct BatchParams {
+  const pbn_work* items;
+  const uint32_t* tasks;           // item of task k
+  const uint32_t* task_first;      // first trajectory (local index) of task k
+  uint32_t ntasks;
+  uint32_t wpb;
+  uint32_t wave_bytes;
+  uint32_t pad;
+  pbn_batch_ctl* ctl;              // device: task counter and the step window
+};
+
+template <int PM, int UM>
+__global__ void __launch_bounds__(1024) k_batch(BatchParams a) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  uint32_t& claimed = *reinterpret_cast<uint32_t*>(smem);   // first 16 bytes: the claimed task
+  const uint32_t wave = threadIdx.x >> 6;
+  const uint32_t step0 = a.ctl->step0, nsteps = a.ctl->nsteps;
+  for (;;) {
+    if (threadIdx.x == 0) claimed = atomicAdd(&a.ctl->next_task, 1u);
+    __syncthreads();
+    const uint32_t task = claimed;
+    __syncthreads();
+    if (task >= a.ntasks) return;        // uniform across the workgroup
+    const pbn_work& it = a.items[a.tasks[task]];
+    const uint32_t tl = a.task_first[task] + wave;
+    if (tl < it.ntraj) {
+      const uint8_t* blob = static_cast<const uint8_t*>(it.d_plan);
+      const pbn_plan_header* H = reinterpret_cast<const pbn_plan_header*>(blob);
+      TrajArgs t;
+      t.blob = blob;
+      t.img = blob + H->image_off;
+      t.wb = smem + 16u + wave * a.wave_bytes;
+      t.seed = it.seed;
+      t.traj = it.traj0 + tl;
+      t.tl = tl;
+      t.ntraj = it.ntraj;
+      t.step0 = step0;
+      t.nsteps = nsteps;
+      t.count_from = it.count_from;
+      t.state = it.d_state;
+      t.counts = reinterpret_cast<unsigned long long*>(it.d_counts);
+      t.tg = it.d_targets;
+      run_traj<PM, UM, 0>(t);
+    }
+  }
+}
+
+// Graph-friendly control updates (no memset nodes): reset the task counter
+// before a batch pass, advance the step window after it.
+__global__ void k_batch_begin(pbn_batch_ctl* ctl) { ctl->next_task = 0; }
+__global__ void k_batch_end(pbn_batch_ctl* ctl) { ctl->step0 += ctl->nsteps; }
 
 // s(0): bit i of node i's INIT word, placed at the node's plan position.
 __global__ void k_state_init(const uint8_t* blob, unsigned long long seed, uint32_t traj0, uint32_t ntraj,
@@ -561,4 +654,165 @@ extern "C" pbn_status pbn_state_to_original(const pbn_plan* plan, const void* d_
   hipLaunchKernelGGL(k_to_original, dim3(grid_for(work, 256)), dim3(256), 0, static_cast<hipStream_t>(stream),
                      static_cast<const uint8_t*>(d_plan), d_state, ntraj, d_out);
   return hip_check(hipGetLastError(), "k_to_original launch");
+}
+
+// ------------------------------------------------------------------ batches
+
+struct pbn_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+struct BatchShape {
+  uint32_t pm = 5, um = 0, wave_bytes = 0;
+};
+
+pbn_status batch_shape(const pbn_plan* const* plans, uint32_t nitems, BatchShape& sh) {
+  for (uint32_t k = 0; k < nitems; ++k) {
+    const pbn_plan* p = plans[k];
+    if (!p) return fail(PBN_EINVAL, "null plan in batch");
+    if (p->info.max_fn_parents > 7 || p->info.max_union_bits > 16)
+      return fail(PBN_ELDS, "plan exceeds the kernel's gather widths");
+    if (p->info.max_fn_parents > 5) sh.pm = 7;
+    sh.um = std::max(sh.um, p->info.max_union_bits);
+    const uint32_t ring = p->n_jobs <= 64 ? p->fill_steps * p->n_jobs : p->n_jobs;
+    sh.wave_bytes = std::max(sh.wave_bytes, 8u * ((p->state_dwords + 3u) & ~3u) + 16u * ring);
+  }
+  sh.um = sh.um == 0 ? 0 : sh.um <= 8 ? 8 : 16;
+  return PBN_OK;
+}
+
+template <int PM, int UM>
+pbn_status launch_batch_t(const BatchParams& p, uint32_t lds, hipStream_t s) {
+  auto* fn = k_batch<PM, UM>;
+  int dev = 0, ncu = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize, int(kLdsMax));
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, int(64u * p.wpb), lds);
+  if (e != hipSuccess) return hip_check(e, "batch occupancy query");
+  const uint32_t resident = uint32_t(std::max(1, per_cu) * std::max(1, ncu));
+  const uint32_t blocks = std::max(1u, std::min(p.ntasks, resident));
+  hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(1), 0, s, p.ctl);
+  hipLaunchKernelGGL(fn, dim3(blocks), dim3(64u * p.wpb), lds, s, p);
+  hipLaunchKernelGGL(k_batch_end, dim3(1), dim3(1), 0, s, p.ctl);
+  return hip_check(hipGetLastError(), "k_batch launch");
+}
+
+pbn_status batch_enqueue(const pbn_plan* const* plans, uint32_t nitems, const pbn_work* d_items,
+                         const uint32_t* d_tasks, const uint32_t* d_task_first, uint32_t ntasks, pbn_batch_ctl* d_ctl,
+                         uint32_t wpb, hipStream_t s) {
+  if (!plans || !d_items || !d_tasks || !d_task_first || !d_ctl) return fail(PBN_EINVAL, "null argument");
+  if (wpb < 1 || wpb > 16) return fail(PBN_EINVAL, "waves_per_block must be 1..16");
+  if (nitems == 0 || ntasks == 0) return PBN_OK;
+  BatchShape sh;
+  pbn_status st = batch_shape(plans, nitems, sh);
+  if (st != PBN_OK) return st;
+  if (16u + wpb * sh.wave_bytes > kLdsMax) return fail(PBN_ELDS, "states and rings of one workgroup exceed LDS");
+  BatchParams p{};
+  p.items = d_items;
+  p.tasks = d_tasks;
+  p.task_first = d_task_first;
+  p.ntasks = ntasks;
+  p.wpb = wpb;
+  p.wave_bytes = sh.wave_bytes;
+  p.ctl = d_ctl;
+  const uint32_t lds = 16u + wpb * sh.wave_bytes;
+  if (sh.pm == 5) {
+    if (sh.um == 0) return launch_batch_t<5, 0>(p, lds, s);
+    if (sh.um == 8) return launch_batch_t<5, 8>(p, lds, s);
+    return launch_batch_t<5, 16>(p, lds, s);
+  }
+  if (sh.um == 0) return launch_batch_t<7, 0>(p, lds, s);
+  if (sh.um == 8) return launch_batch_t<7, 8>(p, lds, s);
+  return launch_batch_t<7, 16>(p, lds, s);
+}
+
+}  // namespace
+
+extern "C" pbn_status pbn_batch_tasks(const pbn_plan* const* plans, const uint32_t* ntraj, uint32_t nitems,
+                                      uint32_t wpb, uint32_t* tasks, uint32_t* task_first, uint32_t* ntasks) {
+  pbn::clear_error();
+  if (!plans || !ntraj || !ntasks || wpb < 1 || wpb > 16) return fail(PBN_EINVAL, "bad argument");
+  // largest networks (most slots x passes) first, so the tail of the persistent
+  // launch is made of short tasks
+  std::vector<uint32_t> order(nitems);
+  for (uint32_t k = 0; k < nitems; ++k) {
+    if (!plans[k]) return fail(PBN_EINVAL, "null plan in batch");
+    order[k] = k;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+    return uint64_t(plans[a]->info.n_passes) * plans[a]->n_jobs + plans[a]->info.n_slots >
+           uint64_t(plans[b]->info.n_passes) * plans[b]->n_jobs + plans[b]->info.n_slots;
+  });
+  uint32_t count = 0;
+  for (uint32_t k : order) {
+    for (uint32_t f = 0; f < ntraj[k]; f += wpb) {
+      if (tasks) tasks[count] = k;
+      if (task_first) task_first[count] = f;
+      ++count;
+    }
+  }
+  *ntasks = count;
+  return PBN_OK;
+}
+
+extern "C" pbn_status pbn_batch_launch(const pbn_plan* const* plans, uint32_t nitems, const pbn_work* d_items,
+                                       const uint32_t* d_tasks, const uint32_t* d_task_first, uint32_t ntasks,
+                                       pbn_batch_ctl* d_ctl, uint32_t waves_per_block, void* stream) {
+  pbn::clear_error();
+  return batch_enqueue(plans, nitems, d_items, d_tasks, d_task_first, ntasks, d_ctl, waves_per_block,
+                       static_cast<hipStream_t>(stream));
+}
+
+extern "C" pbn_status pbn_batch_graph_create(const pbn_plan* const* plans, uint32_t nitems, const pbn_work* d_items,
+                                             const uint32_t* d_tasks, const uint32_t* d_task_first, uint32_t ntasks,
+                                             pbn_batch_ctl* d_ctl, uint32_t waves_per_block, uint32_t passes,
+                                             pbn_graph** out) {
+  pbn::clear_error();
+  if (!out || passes == 0) return fail(PBN_EINVAL, "bad argument");
+  *out = nullptr;
+  hipStream_t s = nullptr;
+  pbn_status st = hip_check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+  if (st != PBN_OK) return st;
+  st = hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  if (st == PBN_OK) {
+    for (uint32_t k = 0; k < passes && st == PBN_OK; ++k)
+      st = batch_enqueue(plans, nitems, d_items, d_tasks, d_task_first, ntasks, d_ctl, waves_per_block, s);
+    hipGraph_t g = nullptr;
+    const pbn_status end = hip_check(hipStreamEndCapture(s, &g), "hipStreamEndCapture");
+    if (st == PBN_OK) st = end;
+    if (st == PBN_OK) {
+      auto* pg = new pbn_graph;
+      pg->graph = g;
+      st = hip_check(hipGraphInstantiate(&pg->exec, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+      if (st == PBN_OK)
+        *out = pg;
+      else {
+        (void)hipGraphDestroy(g);
+        delete pg;
+      }
+    } else if (g) {
+      (void)hipGraphDestroy(g);
+    }
+  }
+  (void)hipStreamDestroy(s);
+  return st;
+}
+
+extern "C" pbn_status pbn_graph_launch(pbn_graph* g, void* stream) {
+  pbn::clear_error();
+  if (!g || !g->exec) return fail(PBN_EINVAL, "null graph");
+  return hip_check(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)), "hipGraphLaunch");
+}
+
+extern "C" pbn_status pbn_graph_destroy(pbn_graph* g) {
+  if (!g) return PBN_OK;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  return PBN_OK;
 }

@@ -1,0 +1,118 @@
+"""Batched persistent launch over networks of uneven size (C4 pattern):
+per-network results must match the per-network oracle and single-network
+launches bit for bit, also when the launches are captured in a HIP graph and
+replayed."""
+import sys
+
+import numpy as np
+import pytest
+
+import pbn_synth as ps
+from oracle import simulate as osim
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_1605_00854_amd import api  # noqa: E402
+
+NONE = 0xFFFFFFFF
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def make_items(count, seed, nmin, nmax, ntraj, grouped):
+    rng = np.random.default_rng(seed)
+    items, nets = [], []
+    for k in range(count):
+        n = int(rng.integers(nmin, nmax + 1))
+        p = float(rng.choice([1e-3, 1e-2]))
+        net = ps.medium_c2(n=n, p=p, seed=seed * 100 + k)
+        tgs = [ps.non_leaf_targets(net, 2), [(ps.non_leaf_targets(net, 1)[0][0], 0)]]
+        interest = sorted({a for tg in tgs for a, _ in tg})
+        opts = dict(reduce=1, group=1, max_parent_bits=6) if grouped and k % 2 else dict(reduce=1, group=0)
+        plan = api.Plan(net, interest=interest, **opts)
+        items.append((plan, 1000 + k, ntraj[k % len(ntraj)], tgs))
+        nets.append(net)
+    return items, nets
+
+
+@pytest.mark.parametrize("grouped", [False, True])
+def test_batch_matches_oracle_per_network(grouped):
+    items, nets = make_items(10, 3 + grouped, 20, 260, [5, 9, 4], grouped)
+    say(f"[gpu] batch of {len(items)} networks grouped={grouped}")
+    b = api.Batch(items, count_from=30, waves_per_block=4)
+    b.init_states()
+    b.set_window(0, 150)
+    b.launch()
+    b.set_window(150, 90)           # a second window continues the same trajectories
+    b.launch()
+    torch.cuda.synchronize()
+    for k, ((plan, seed, ntraj, tgs), net) in enumerate(zip(items, nets)):
+        ref = osim.run(net, seed, np.arange(ntraj), 240, targets=tgs, count_from=30)
+        orig = api.unpack_bits(api.to_original(plan, b.states[k]).cpu().numpy(), plan.n)
+        kept = plan.node_pos() != NONE
+        assert np.array_equal(orig[:, kept], ref["state"][:, kept]), f"network {k}"
+        c = b.counts[k].cpu().numpy()
+        assert np.array_equal(c[:, :, 0], ref["hits"]), f"network {k}"
+        assert np.array_equal(c[:, :, 1], ref["n01"]), f"network {k}"
+        assert np.array_equal(c[:, :, 2], ref["n10"]), f"network {k}"
+
+
+def single_launch_states(items, steps):
+    out = []
+    for plan, seed, ntraj, tgs in items:
+        tg = plan.targets(tgs)
+        st = api.state_init(plan, seed, ntraj)
+        cn = api.new_counts(tg.ntargets, ntraj)
+        api.simulate(plan, seed, st, cn, tg, 0, steps, plain=plan.info["n_table_slots"] == 0)
+        out.append((st.cpu().numpy(), cn.cpu().numpy()))
+    return out
+
+
+def test_batch_graph_replays_match_eager_launches():
+    items, _ = make_items(24, 7, 20, 700, [16, 7, 33], True)
+    ref_a = single_launch_states(items, 200)
+    ref_b = single_launch_states(items, 400)
+    b = api.Batch(items, waves_per_block=4)
+    b.init_states()
+    b.set_window(0, 100)
+    say("[gpu] capture batch graph (2 passes x 100 steps)")
+    g = b.graph(2)
+    torch.cuda.synchronize()
+    for replay, ref in ((0, ref_a), (1, ref_b)):
+        say(f"[gpu] graph replay {replay}")
+        g.launch()
+        torch.cuda.synchronize()
+        # eager work between replays
+        junk = torch.arange(1000, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert int(junk) == 499500
+        for k in range(len(items)):
+            assert np.array_equal(b.states[k].cpu().numpy(), ref[k][0]), f"replay {replay} network {k}"
+            assert np.array_equal(b.counts[k].cpu().numpy(), ref[k][1]), f"replay {replay} network {k}"
+    assert int(b.ctl.cpu()[1]) == 400
+
+
+def test_batch_large_uneven_sampled():
+    """Uneven sizes up to 1500 nodes (the batched workload's range); two networks
+    are recomputed by the oracle on a trajectory subset."""
+    items, nets = make_items(40, 11, 20, 1500, [64, 40], False)
+    b = api.Batch(items, waves_per_block=4)
+    b.init_states()
+    b.set_window(0, 60)
+    say("[gpu] batch of 40 networks up to 1500 nodes")
+    b.launch()
+    torch.cuda.synchronize()
+    for k in (0, int(np.argmax([it[0].n for it in items]))):
+        plan, seed, ntraj, tgs = items[k]
+        sample = np.array([0, ntraj // 2, ntraj - 1])
+        ref = osim.run(nets[k], seed, sample, 60, targets=tgs)
+        orig = api.unpack_bits(api.to_original(plan, b.states[k]).cpu().numpy(), plan.n)
+        kept = plan.node_pos() != NONE
+        assert np.array_equal(orig[sample][:, kept], ref["state"][:, kept])
