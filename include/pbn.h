@@ -275,6 +275,39 @@ pbn_status pbn_simulate_plain(const pbn_plan* plan, const void* d_plan, uint64_t
 pbn_status pbn_state_to_original(const pbn_plan* plan, const void* d_plan, const uint32_t* d_state,
                                  uint32_t ntraj, uint32_t* d_out, void* stream);
 
+/* ---------------------------------------------------------------- estimate
+ * Steady-state estimate of one target from per-unit counters (host, double
+ * precision).  A unit is one trajectory, or one batch of one long trajectory
+ * (batch means); every unit counted `steps_per_unit` states.
+ *   counts   [units][3] as written by pbn_simulate for one target (hits, 0->1, 1->0)
+ *   p_hat        sum hits / (units * steps_per_unit)
+ *   half_width   t quantile (1 + conf) / 2 with units - 1 degrees of freedom times
+ *                sd(unit means) / sqrt(units); NaN for one unit
+ *   alpha, beta  two-state chain of the hit indicator: 0->1 changes per visit of
+ *                state 0 and 1->0 changes per visit of state 1 (pooled over units)
+ *   n_required   the two-state chain approach's sample size for precision
+ *                `precision` at confidence `conf`:
+ *                alpha beta (2 - alpha - beta) / (alpha + beta)^3 (z / precision)^2
+ *   burn_in      log(1e-3 (alpha + beta) / max(alpha, beta)) / log|1 - alpha - beta|
+ * Errors: PBN_EINVAL. */
+typedef struct pbn_estimate_out {
+  double p_hat;
+  double half_width;
+  double alpha, beta;
+  double n_required;
+  double burn_in;
+  uint32_t units;
+  uint32_t reserved;
+} pbn_estimate_out;
+
+pbn_status pbn_estimate(const uint64_t* counts, uint32_t units, uint64_t steps_per_unit, double conf,
+                        double precision, pbn_estimate_out* out);
+
+/* Quantiles used by pbn_estimate: Student t with nu degrees of freedom, and the
+ * standard normal.  p in (0, 1). */
+double pbn_t_quantile(double p, double nu);
+double pbn_normal_quantile(double p);
+
 /* ----------------------------------------------------------------- batches
  * Many networks of uneven size advanced together by one persistent launch
  * (the step kernel of pbn_simulate, per trajectory, with a task loop on top).
@@ -291,6 +324,9 @@ pbn_status pbn_state_to_original(const pbn_plan* plan, const void* d_plan, const
  *   d_plan     device blob of plans[k];  d_targets  device copy of its pbn_targets
  *   d_state    [ntraj][state_words];     d_counts   [ntargets][ntraj][3] (added to)
  *   seed, traj0, ntraj, count_from as in pbn_simulate
+ *   step0      offset of this item's window: it advances steps
+ *              step0 + d_ctl->step0 .. + d_ctl->nsteps - 1 (callers must keep the
+ *              sum below 2^32)
  * pbn_batch_tasks: host; task order (largest networks first).  tasks / task_first
  *   receive the item and first trajectory of each task (NULL to query *ntasks).
  * pbn_batch_launch: enqueue one pass on `stream`.
@@ -305,7 +341,7 @@ typedef struct pbn_work {
   uint64_t seed;
   uint32_t traj0, ntraj;
   uint32_t count_from;
-  uint32_t reserved;
+  uint32_t step0;
 } pbn_work;
 
 typedef struct pbn_batch_ctl {

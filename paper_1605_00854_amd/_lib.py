@@ -52,7 +52,13 @@ class pbn_launch_opts(C.Structure):
 class pbn_work(C.Structure):
     _fields_ = [("d_plan", C.c_void_p), ("d_targets", C.c_void_p), ("d_state", C.c_void_p),
                 ("d_counts", C.c_void_p), ("seed", C.c_uint64), ("traj0", C.c_uint32),
-                ("ntraj", C.c_uint32), ("count_from", C.c_uint32), ("reserved", C.c_uint32)]
+                ("ntraj", C.c_uint32), ("count_from", C.c_uint32), ("step0", C.c_uint32)]
+
+
+class pbn_estimate_out(C.Structure):
+    _fields_ = [("p_hat", C.c_double), ("half_width", C.c_double), ("alpha", C.c_double),
+                ("beta", C.c_double), ("n_required", C.c_double), ("burn_in", C.c_double),
+                ("units", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 _lib = None
@@ -89,6 +95,9 @@ SIGNATURES = {
                                            C.POINTER(_P)]),
     "pbn_graph_launch": (C.c_int32, [_P, _P]),
     "pbn_graph_destroy": (C.c_int32, [_P]),
+    "pbn_estimate": (C.c_int32, [_pU64, _U32, _U64, C.c_double, C.c_double, C.POINTER(pbn_estimate_out)]),
+    "pbn_t_quantile": (C.c_double, [C.c_double, C.c_double]),
+    "pbn_normal_quantile": (C.c_double, [C.c_double]),
 }
 
 

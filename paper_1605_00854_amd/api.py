@@ -165,6 +165,15 @@ def eq2_lower_bound(weights, theta):
     return m.value or None
 
 
+def estimate(counts, steps_per_unit, conf=0.95, precision=0.01):
+    """pbn_estimate on host counters [units][3] of one target; returns a dict."""
+    c = np.ascontiguousarray(np.asarray(counts).reshape(-1, 3), dtype=np.uint64)
+    out = _lib.pbn_estimate_out()
+    check(lib().pbn_estimate(_ptr(c, C.c_uint64), c.shape[0], int(steps_per_unit), float(conf),
+                             float(precision), C.byref(out)))
+    return {name: getattr(out, name) for name, _ in out._fields_ if name != "reserved"}
+
+
 # ------------------------------------------------------------------ device
 
 def _stream(stream):

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpbn_amd.so")
 ARCH = "gfx950"
 
-HOST_SOURCES = ["host_net.cpp", "host_plan.cpp"]
+HOST_SOURCES = ["host_net.cpp", "host_plan.cpp", "host_stats.cpp"]
 DEVICE_SOURCES = ["device.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall", "-Wno-unused-function"]

@@ -430,7 +430,7 @@ __global__ void __launch_bounds__(1024) k_batch(BatchParams a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   uint32_t& claimed = *reinterpret_cast<uint32_t*>(smem);   // first 16 bytes: the claimed task
   const uint32_t wave = threadIdx.x >> 6;
-  const uint32_t step0 = a.ctl->step0, nsteps = a.ctl->nsteps;
+  const uint32_t wstep0 = a.ctl->step0, nsteps = a.ctl->nsteps;
   for (;;) {
     if (threadIdx.x == 0) claimed = atomicAdd(&a.ctl->next_task, 1u);
     __syncthreads();
@@ -450,7 +450,7 @@ __global__ void __launch_bounds__(1024) k_batch(BatchParams a) {
       t.traj = it.traj0 + tl;
       t.tl = tl;
       t.ntraj = it.ntraj;
-      t.step0 = step0;
+      t.step0 = it.step0 + wstep0;
       t.nsteps = nsteps;
       t.count_from = it.count_from;
       t.state = it.d_state;

@@ -1,0 +1,147 @@
+// host_stats.cpp -- steady-state estimate from per-unit hit counters (host,
+// double precision).  A unit is one trajectory, or one batch of a single long
+// trajectory (batch means).  The paper estimates steady-state probabilities
+// with the two-state Markov chain approach of Raftery and Lewis (Sections 1
+// and 4.2); its published figures are reported beside the confidence interval.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <limits>
+
+#include "internal.h"
+
+namespace {
+
+pbn_status fail(pbn_status code, const char* msg) {
+  pbn::set_error(msg);
+  return code;
+}
+
+// Standard normal quantile: bisection on the CDF 0.5 erfc(-x / sqrt 2), then
+// two Newton steps (the density is known in closed form).
+double normal_quantile(double p) {
+  double lo = -40.0, hi = 40.0;
+  for (int it = 0; it < 200 && hi - lo > 1e-12; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    (0.5 * std::erfc(-mid / std::sqrt(2.0)) < p ? lo : hi) = mid;
+  }
+  double x = 0.5 * (lo + hi);
+  for (int it = 0; it < 2; ++it) {
+    const double f = 0.5 * std::erfc(-x / std::sqrt(2.0)) - p;
+    x -= f / (std::exp(-0.5 * x * x) / std::sqrt(2.0 * M_PI));
+  }
+  return x;
+}
+
+// Regularised incomplete beta I_x(a, b) by its continued fraction (modified Lentz).
+double betacf(double a, double b, double x) {
+  const double tiny = 1e-300, eps = 1e-16;
+  double c = 1.0, d = 1.0 - (a + b) * x / (a + 1.0);
+  if (std::fabs(d) < tiny) d = tiny;
+  d = 1.0 / d;
+  double h = d;
+  for (int m = 1; m <= 500; ++m) {
+    const double m2 = 2.0 * m;
+    double aa = m * (b - m) * x / ((a - 1.0 + m2) * (a + m2));
+    d = 1.0 + aa * d;
+    if (std::fabs(d) < tiny) d = tiny;
+    c = 1.0 + aa / c;
+    if (std::fabs(c) < tiny) c = tiny;
+    d = 1.0 / d;
+    h *= d * c;
+    aa = -(a + m) * (a + b + m) * x / ((a + m2) * (a + 1.0 + m2));
+    d = 1.0 + aa * d;
+    if (std::fabs(d) < tiny) d = tiny;
+    c = 1.0 + aa / c;
+    if (std::fabs(c) < tiny) c = tiny;
+    d = 1.0 / d;
+    const double del = d * c;
+    h *= del;
+    if (std::fabs(del - 1.0) < eps) break;
+  }
+  return h;
+}
+
+// x and its complement xc = 1 - x are passed separately: callers compute the
+// complement without cancellation.
+double inc_beta(double a, double b, double x, double xc) {
+  if (x <= 0) return 0;
+  if (xc <= 0) return 1;
+  const double lbt = std::lgamma(a + b) - std::lgamma(a) - std::lgamma(b) + a * std::log(x) + b * std::log(xc);
+  if (x < (a + 1) / (a + b + 2)) return std::exp(lbt) * betacf(a, b, x) / a;
+  return 1.0 - std::exp(lbt) * betacf(b, a, xc) / b;
+}
+
+// Student t CDF with nu degrees of freedom: 1 - I_x(nu/2, 1/2) / 2 for t >= 0,
+// x = nu / (nu + t^2).  Near t = 0 the central mass I_xc(1/2, nu/2) is used
+// directly so that small quantiles keep their relative precision.
+double t_cdf(double t, double nu) {
+  const double t2 = t * t;
+  const double x = nu / (nu + t2), xc = t2 / (nu + t2);
+  if (xc < 0.5) {
+    const double central = inc_beta(0.5, nu / 2, xc, x);   // P(|T| <= |t|)
+    return t >= 0 ? 0.5 + 0.5 * central : 0.5 - 0.5 * central;
+  }
+  const double tail = 0.5 * inc_beta(nu / 2, 0.5, x, xc);
+  return t >= 0 ? 1 - tail : tail;
+}
+
+// Student t quantile: bisection on the CDF (monotone), to 1e-14 relative.
+double t_quantile(double p, double nu) {
+  if (nu > 1e7) return normal_quantile(p);
+  double lo = -1.0, hi = 1.0;
+  while (t_cdf(lo, nu) > p) lo *= 2;
+  while (t_cdf(hi, nu) < p) hi *= 2;
+  for (int it = 0; it < 400 && hi - lo > 1e-15 * std::fmax(std::fabs(lo), std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    (t_cdf(mid, nu) < p ? lo : hi) = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+}  // namespace
+
+extern "C" double pbn_t_quantile(double p, double nu) { return t_quantile(p, nu); }
+extern "C" double pbn_normal_quantile(double p) { return normal_quantile(p); }
+
+extern "C" pbn_status pbn_estimate(const uint64_t* counts, uint32_t units, uint64_t steps_per_unit, double conf,
+                                   double precision, pbn_estimate_out* out) {
+  pbn::clear_error();
+  if (!counts || !out || units == 0 || steps_per_unit == 0) return fail(PBN_EINVAL, "bad argument");
+  if (!(conf > 0 && conf < 1)) return fail(PBN_EINVAL, "confidence must be in (0, 1)");
+  const double T = double(steps_per_unit);
+  double sum = 0, n01 = 0, n10 = 0;
+  for (uint32_t u = 0; u < units; ++u) {
+    sum += double(counts[3 * size_t(u)]);
+    n01 += double(counts[3 * size_t(u) + 1]);
+    n10 += double(counts[3 * size_t(u) + 2]);
+  }
+  const double mean = sum / (units * T);
+  double ss = 0;
+  for (uint32_t u = 0; u < units; ++u) {
+    const double m = double(counts[3 * size_t(u)]) / T - mean;
+    ss += m * m;
+  }
+  out->p_hat = mean;
+  out->units = units;
+  out->reserved = 0;
+  out->half_width = std::numeric_limits<double>::quiet_NaN();
+  if (units >= 2) {
+    const double sd = std::sqrt(ss / (units - 1));
+    out->half_width = t_quantile(0.5 + conf / 2, double(units - 1)) * sd / std::sqrt(double(units));
+  }
+  // two-state chain of the hit indicator: visits of state 1 = hits, of state 0 = the rest
+  const double v1 = sum, v0 = units * T - sum;
+  const double alpha = v0 > 0 ? n01 / v0 : 0.0, beta = v1 > 0 ? n10 / v1 : 0.0;
+  out->alpha = alpha;
+  out->beta = beta;
+  out->n_required = std::numeric_limits<double>::infinity();
+  out->burn_in = std::numeric_limits<double>::infinity();
+  if (alpha + beta > 0 && precision > 0) {
+    const double z = normal_quantile(0.5 + conf / 2);
+    out->n_required = alpha * beta * (2 - alpha - beta) / std::pow(alpha + beta, 3) * (z / precision) * (z / precision);
+    const double lam = std::fabs(1 - alpha - beta);
+    out->burn_in = lam == 0 ? 1.0 : std::log(1e-3 * (alpha + beta) / std::fmax(alpha, beta)) / std::log(lam);
+  }
+  return PBN_OK;
+}

@@ -1,0 +1,257 @@
+"""Continuous-batching server for steady-state queries.
+
+A query asks for P(target state set) of one resident network at precision r
+and confidence conf (the estimate of Section 4.2).  Network plans stay resident
+on the device.  Each query owns its trajectory slots: its trajectories are
+keyed by seed = H(network seed, query id), run a burn-in, then advance in
+chunks; after every chunk its own counters decide (t interval over its
+trajectories) whether its precision is met.  Because the keying and the chunk
+schedule depend only on the query, its result is bit-identical whether it runs
+alone or mixed with others; the mix only changes latency.
+
+Every tick advances all admitted queries by one chunk in a single persistent
+batched launch (pbn_batch_launch): queries that arrived while others were on
+the device join at the next tick as soon as their footprint (resident waves,
+LDS bytes, HBM bytes) fits, and leave when their precision is met.
+"""
+import hashlib
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import _lib, api
+
+
+@dataclass
+class Query:
+    qid: int
+    net: int                    # index of the resident network
+    targets: list               # [(node, value)]
+    precision: float
+    conf: float = 0.95
+    arrival: float = 0.0        # seconds since the start of the run
+    # filled by the server
+    status: str = "queued"
+    admitted: float = None
+    finished: float = None
+    steps: int = 0
+    result: dict = field(default_factory=dict)
+    error: str = None
+
+
+def query_seed(net_seed, qid):
+    h = hashlib.sha256(f"{net_seed}:{qid}".encode()).digest()
+    return int.from_bytes(h[:8], "little")
+
+
+class Footprint:
+    """Device budget for admission: resident waves, LDS bytes, HBM bytes."""
+
+    def __init__(self, waves=256 * 32, lds_bytes=256 * 160 * 1024, hbm_bytes=8 << 30):
+        self.cap = np.array([waves, lds_bytes, hbm_bytes], dtype=np.float64)
+        self.used = np.zeros(3)
+
+    def fits(self, need):
+        return bool(np.all(self.used + need <= self.cap))
+
+    def exceeds_device(self, need):
+        return bool(np.any(need > self.cap))
+
+    def take(self, need):
+        self.used += need
+
+    def give(self, need):
+        self.used -= need
+
+
+class Server:
+    def __init__(self, nets, net_seeds, *, plan_opts=None, traj_per_query=256, chunk=1000, burn_in=1000,
+                 min_counted=1000, max_steps=400000, waves_per_block=4, footprint=None):
+        import torch
+        self.torch = torch
+        self.nets = nets
+        self.net_seeds = list(net_seeds)
+        self.opts = dict(plan_opts or dict(reduce=1, group=0))
+        self.ntraj = int(traj_per_query)
+        self.chunk = int(chunk)
+        self.burn_in = int(burn_in)
+        self.min_counted = int(min_counted)
+        self.max_steps = int(max_steps)
+        self.wpb = int(waves_per_block)
+        self.fp = footprint or Footprint()
+        self.plans = {}
+        for k, net in enumerate(nets):
+            self._plan(k, ())
+        self.queue, self.active, self.done = [], [], []
+        self.node_updates = 0
+        self.ticks = 0
+        self.ctl = torch.tensor([0, 0, self.chunk, 0], dtype=torch.int32, device="cuda")
+
+    # -- resident plans: interest = every node a query may read
+    def _plan(self, k, extra):
+        net = self.nets[k]
+        leaves = set(int(x) for x in net.get("designated_leaves", []))
+        base = frozenset(i for i in range(net["n"]) if i not in leaves)
+        key = (k, base | frozenset(extra))
+        if key not in self.plans:
+            plan = api.Plan(net, interest=sorted(key[1]), **self.opts)
+            plan.device()
+            self.plans[key] = plan
+        return self.plans[key]
+
+    def _resident(self, k, targets):
+        plan = self._plan(k, ())
+        try:
+            return plan, plan.targets([targets])
+        except _lib.PbnError:
+            # a query on a node the reduction removed: prepare with that node kept
+            plan = self._plan(k, [a for a, _ in targets])
+            return plan, plan.targets([targets])
+
+    def footprint(self, plan):
+        ring = plan.info["n_jobs"]
+        fill = max(1, 64 // ring) if ring <= 64 else 1
+        wave_lds = 8 * ((plan.info["n_slots"] + 1 + 3) // 4 * 4) + 16 * (fill * ring if ring <= 64 else ring)
+        hbm = self.ntraj * (4 * plan.info["state_words"] + 24)
+        return np.array([self.ntraj, self.ntraj * wave_lds, hbm], dtype=np.float64)
+
+    # -- queue management
+    def submit(self, q, now):
+        try:
+            plan, tg = self._resident(q.net, q.targets)
+        except _lib.PbnError as e:
+            q.status, q.error, q.finished = "rejected", str(e), now
+            self.done.append(q)
+            return
+        need = self.footprint(plan)
+        if self.fp.exceeds_device(need):
+            q.status, q.error, q.finished = "rejected", "footprint exceeds the device budget", now
+            self.done.append(q)
+            return
+        q._plan, q._tg, q._need = plan, tg, need
+        self.queue.append(q)
+
+    def _admit(self, now):
+        torch = self.torch
+        while self.queue and self.fp.fits(self.queue[0]._need):
+            q = self.queue.pop(0)
+            self.fp.take(q._need)
+            q.status, q.admitted = "running", now
+            q._seed = query_seed(self.net_seeds[q.net], q.qid)
+            q._state = api.state_init(q._plan, q._seed, self.ntraj)
+            q._counts = api.new_counts(1, self.ntraj)
+            q._tg_dev = api._to_device_bytes(q._tg)
+            self.active.append(q)
+
+    def _launch(self):
+        torch = self.torch
+        act = self.active
+        works = (_lib.pbn_work * len(act))()
+        for k, q in enumerate(act):
+            works[k] = _lib.pbn_work(q._plan.device().data_ptr(), q._tg_dev.data_ptr(), q._state.data_ptr(),
+                                     q._counts.data_ptr(), q._seed, 0, self.ntraj, self.burn_in, q.steps)
+        items_dev = api._to_device_bytes(works)
+        plans = (api.C.c_void_p * len(act))(*[q._plan.handle.value for q in act])
+        ntraj = np.full(len(act), self.ntraj, dtype=np.uint32)
+        nt = api.C.c_uint32()
+        L = _lib.lib()
+        _lib.check(L.pbn_batch_tasks(plans, api._ptr(ntraj, api.C.c_uint32), len(act), self.wpb, None, None,
+                                     api.C.byref(nt)))
+        tasks = np.zeros(nt.value, dtype=np.uint32)
+        first = np.zeros(nt.value, dtype=np.uint32)
+        _lib.check(L.pbn_batch_tasks(plans, api._ptr(ntraj, api.C.c_uint32), len(act), self.wpb,
+                                     api._ptr(tasks, api.C.c_uint32), api._ptr(first, api.C.c_uint32),
+                                     api.C.byref(nt)))
+        tasks_dev = torch.from_numpy(tasks.astype(np.int32)).to("cuda")
+        first_dev = torch.from_numpy(first.astype(np.int32)).to("cuda")
+        self.ctl.copy_(torch.tensor([0, 0, self.chunk, 0], dtype=torch.int32))
+        _lib.check(L.pbn_batch_launch(plans, len(act), api._dptr(items_dev), api._dptr(tasks_dev),
+                                      api._dptr(first_dev), nt.value, api._dptr(self.ctl), self.wpb,
+                                      api._stream(None)))
+        return items_dev, tasks_dev, first_dev        # keep alive until the sync
+
+    def tick(self, now_fn):
+        """Admit, advance every active query by one chunk, retire finished ones."""
+        torch = self.torch
+        self._admit(now_fn())
+        if not self.active:
+            return False
+        keep = self._launch()
+        counts = torch.cat([q._counts.view(-1) for q in self.active]).cpu().numpy()   # synchronises
+        del keep
+        now = now_fn()
+        self.ticks += 1
+        per = 3 * self.ntraj
+        still = []
+        for k, q in enumerate(self.active):
+            q.steps += self.chunk
+            self.node_updates += self.ntraj * self.chunk * q._plan.n
+            counted = q.steps - self.burn_in
+            c = counts[k * per:(k + 1) * per].reshape(self.ntraj, 3)
+            finished = False
+            if counted >= self.min_counted:
+                est = api.estimate(c, counted, conf=q.conf, precision=q.precision)
+                q.result = est
+                if est["half_width"] <= q.precision:
+                    q.status = "done"
+                    finished = True
+                elif q.steps >= self.max_steps:
+                    q.status = "max_steps"
+                    finished = True
+            if finished:
+                q.finished = now
+                q.result["counts"] = c.copy()
+                self.fp.give(q._need)
+                for name in ("_state", "_counts", "_tg_dev"):
+                    setattr(q, name, None)
+                self.done.append(q)
+            else:
+                still.append(q)
+        self.active = still
+        return True
+
+    def run(self, queries, realtime=True):
+        """Serve `queries` (arrival times in seconds).  Returns the metrics dict."""
+        pending = sorted(queries, key=lambda q: q.arrival)
+        t0 = time.perf_counter()
+        now = (lambda: time.perf_counter() - t0) if realtime else (lambda: float(self.ticks))
+        i = 0
+        while i < len(pending) or self.queue or self.active:
+            tnow = now()
+            while i < len(pending) and (pending[i].arrival <= tnow or not realtime):
+                self.submit(pending[i], tnow)
+                i += 1
+            if not self.tick(now) and i < len(pending) and realtime:
+                time.sleep(max(0.0, min(0.01, pending[i].arrival - now())))
+        wall = time.perf_counter() - t0
+        return self.metrics(wall)
+
+    def metrics(self, wall):
+        lat = np.array([q.finished - q.arrival for q in self.done if q.status in ("done", "max_steps")])
+        return {
+            "queries": len(self.done),
+            "done": sum(q.status == "done" for q in self.done),
+            "max_steps": sum(q.status == "max_steps" for q in self.done),
+            "rejected": sum(q.status == "rejected" for q in self.done),
+            "p50_latency_s": float(np.percentile(lat, 50)) if lat.size else None,
+            "p99_latency_s": float(np.percentile(lat, 99)) if lat.size else None,
+            "node_updates_per_s": self.node_updates / wall if wall > 0 else None,
+            "wall_s": wall,
+            "ticks": self.ticks,
+        }
+
+
+def poisson_queries(nets, count, rate, seed=2005, precisions=(1e-2, 5e-3), conf=0.95):
+    """The served workload: Poisson arrivals, 1-5 random non-leaf nodes with a
+    random ON/OFF pattern, precision drawn from `precisions`."""
+    import pbn_synth as ps
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    out = []
+    for qid in range(count):
+        t += rng.exponential(1.0 / rate)
+        k = int(rng.integers(0, len(nets)))
+        tg = ps.random_query_targets(rng, nets[k])
+        out.append(Query(qid, k, tg, float(rng.choice(precisions)), conf, t))
+    return out

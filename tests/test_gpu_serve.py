@@ -1,0 +1,118 @@
+"""Continuous-batching query server (C5 pattern): each result is bit-identical
+alone and in the mix, admission respects the footprint budget, an oversize
+query is rejected while serving continues, and served estimates agree with the
+exact steady state of small networks."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import pbn_synth as ps
+from oracle import exact
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_1605_00854_amd import serve  # noqa: E402
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def small_nets():
+    return [ps.medium_c2(n=n, p=p, seed=s) for n, p, s in
+            ((30, 1e-2, 1), (80, 3e-3, 2), (200, 1e-3, 3), (12, 2e-2, 4))]
+
+
+def queries(nets, count, seed):
+    qs = serve.poisson_queries(nets, count, rate=1000.0, seed=seed, precisions=(0.04, 0.06))
+    return qs
+
+
+def make_server(nets, **kw):
+    kw.setdefault("traj_per_query", 64)
+    kw.setdefault("chunk", 400)
+    kw.setdefault("burn_in", 400)
+    kw.setdefault("min_counted", 400)
+    kw.setdefault("max_steps", 40000)
+    return serve.Server(nets, list(range(100, 100 + len(nets))), **kw)
+
+
+def test_results_identical_alone_and_in_mix():
+    nets = small_nets()
+    qs = queries(nets, 12, 5)
+    # a budget of ~5 resident queries forces staggered admission
+    srv = make_server(nets, footprint=serve.Footprint(waves=5 * 64 + 10))
+    say("[gpu] serving 12 queries mixed")
+    m = srv.run(qs, realtime=False)
+    assert m["done"] + m["max_steps"] == 12, m
+    mixed = {q.qid: q for q in srv.done}
+    for q in queries(nets, 12, 5):
+        say(f"[gpu] query {q.qid} alone")
+        alone = make_server(nets)
+        alone.run([q], realtime=False)
+        a = alone.done[0]
+        b = mixed[q.qid]
+        assert a.steps == b.steps, q.qid
+        assert np.array_equal(a.result["counts"], b.result["counts"]), q.qid
+        assert a.result["p_hat"] == b.result["p_hat"]
+
+
+def test_admission_respects_budget_and_rejects_oversize():
+    nets = small_nets()
+    big = ps.medium_c2(n=3000, p=1e-4, seed=9)
+    all_nets = nets + [big]
+    srv = make_server(all_nets, footprint=serve.Footprint(waves=4 * 64, lds_bytes=64 * 10 * 1024))
+    cap = srv.fp.cap.copy()
+    seen = []
+    orig_tick = srv.tick
+
+    def tick(now_fn):
+        r = orig_tick(now_fn)
+        seen.append(srv.fp.used.copy())
+        assert np.all(srv.fp.used <= cap + 1e-9)
+        return r
+
+    srv.tick = tick
+    qs = queries(nets, 8, 6)
+    over = serve.Query(999, len(all_nets) - 1, ps.non_leaf_targets(big, 2), 0.05)
+    say("[gpu] serving with an oversize query")
+    m = srv.run(qs[:4] + [over] + qs[4:], realtime=False)
+    rej = [q for q in srv.done if q.status == "rejected"]
+    assert [q.qid for q in rej] == [999]
+    assert m["done"] + m["max_steps"] == 8
+    assert max(u[0] for u in seen) <= 4 * 64
+
+
+def test_served_estimate_matches_exact_steady_state():
+    net = ps.random_pbn(8, 0.02, 21, nfn=lambda r: int(r.integers(1, 3)),
+                        nparents=lambda r: int(r.integers(1, 4)))
+    tg = [(0, 1), (3, 0)]
+    pi = exact.steady_state(net)
+    want = exact.target_probability(pi, tg)
+    srv = serve.Server([net], [7], traj_per_query=256, chunk=2000, burn_in=2000, min_counted=2000,
+                       max_steps=400000)
+    q = serve.Query(0, 0, tg, 0.004)
+    say("[gpu] served estimate vs power method")
+    srv.run([q], realtime=False)
+    r = srv.done[0].result
+    assert srv.done[0].status == "done"
+    # the run stops at half-width <= 0.004 (95%); gate at the 99.9% level
+    assert abs(r["p_hat"] - want) <= r["half_width"] * 3.29 / 1.96 + 1e-4, (r["p_hat"], want, r["half_width"])
+
+
+def test_realtime_poisson_stream_reports_latency():
+    nets = small_nets()
+    qs = serve.poisson_queries(nets, 40, rate=200.0, seed=8, precisions=(0.05,))
+    srv = make_server(nets)
+    say("[gpu] realtime stream of 40 queries")
+    m = srv.run(qs, realtime=True)
+    assert m["done"] + m["max_steps"] == 40
+    assert m["p50_latency_s"] is not None and m["p99_latency_s"] >= m["p50_latency_s"]
+    assert m["node_updates_per_s"] > 0

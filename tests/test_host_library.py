@@ -154,3 +154,50 @@ def test_targets_reject_removed_nodes():
         plan.targets([[(leaf, 1)]])
     tg = plan.targets([[(0, 1), (1, 0)], [(2, 1)]])
     assert tg.ntargets == 2 and tg.npairs == 3 and tg.mask[0] == 0b011 and tg.mask[1] == 0b100
+
+
+def test_quantiles_match_scipy():
+    from scipy import stats as st
+    L = _lib.lib()
+    for p in (0.5 + 1e-6, 0.6, 0.95, 0.975, 0.9995, 0.999999):
+        assert abs(L.pbn_normal_quantile(p) - st.norm.ppf(p)) < 1e-9 * max(1, abs(st.norm.ppf(p)))
+        for nu in (1, 2, 3, 5, 10, 49, 4095, 65535):
+            want = st.t.ppf(p, nu)
+            assert abs(L.pbn_t_quantile(p, nu) - want) < 1e-8 * max(1.0, abs(want)), (p, nu)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_estimate_matches_oracle_statistics(seed):
+    from oracle import stats as ost
+    rng = np.random.default_rng(seed)
+    units = int(rng.integers(2, 300))
+    T = int(rng.integers(100, 100000))
+    hits = rng.integers(0, T + 1, size=units)
+    n01 = rng.integers(0, 50, size=units)
+    n10 = rng.integers(0, 50, size=units)
+    counts = np.stack([hits, n01, n10], axis=1)
+    r = 10 ** rng.uniform(-3, -1.5)
+    got = api.estimate(counts, T, conf=0.95, precision=r)
+    p_hat, hw = ost.trajectory_mean_interval(hits, T, conf=0.95)
+    assert abs(got["p_hat"] - p_hat) < 1e-12
+    assert abs(got["half_width"] - hw) < 1e-9 * max(hw, 1e-12)
+    n1 = hits.sum()
+    n0 = units * T - n1
+    alpha, beta, nreq, burn = ost.two_state(n01.sum(), n10.sum(), n0, n1, r, conf=0.95)
+    assert abs(got["alpha"] - alpha) < 1e-15 and abs(got["beta"] - beta) < 1e-15
+    assert abs(got["n_required"] - nreq) < 1e-9 * nreq
+    assert abs(got["burn_in"] - burn) < 1e-9 * abs(burn)
+
+
+def test_two_state_sample_size_reduces_to_binomial():
+    """For an iid indicator, alpha = pi and beta = 1 - pi, and the two-state
+    sample size is the binomial one: pi (1 - pi) (z / r)^2."""
+    from scipy import stats as st
+    pi, T, units, r = 0.3, 10**6, 1, 0.01
+    hits = int(pi * T)
+    n01 = int(round((1 - pi) * T * pi))       # 0->1 per visit of 0 = pi
+    n10 = int(round(pi * T * (1 - pi)))       # 1->0 per visit of 1 = 1 - pi
+    got = api.estimate(np.array([[hits, n01, n10]]), T, conf=0.95, precision=r)
+    z = st.norm.ppf(0.975)
+    assert abs(got["n_required"] - pi * (1 - pi) * (z / r) ** 2) < 1e-6 * got["n_required"]
+    assert np.isnan(got["half_width"])
