@@ -138,6 +138,107 @@ def run_step(api, torch, cfg, opts, plain, chunk, events, wpb=0):
     return plan, p_hat, hw, prep
 
 
+def tuned_opts_for(api, torch, nets, seed, ntraj=256, sample=4):
+    """Autotune on a few networks spread over the size range; the options that
+    win most often are used for all of them (ties: the faster total)."""
+    from paper_1605_00854_amd import autotune
+    order = sorted(range(len(nets)), key=lambda k: nets[k]["n"])
+    picks = [order[int(round(i * (len(order) - 1) / max(1, sample - 1)))] for i in range(sample)]
+    votes = {}
+    for k in picks:
+        net = nets[k]
+        tg = [ps.non_leaf_targets(net, 2)]
+        interest = [a for a, _ in tg[0]]
+        best, wpb, trials = autotune.tune(net, interest, tg, ntraj, seed=seed, probe_steps=500, quick=True,
+                                          key=("multi", k, seed))
+        key = tuple(sorted(best.items()))
+        rate = max(t["node_updates_per_s"] for t in trials if "node_updates_per_s" in t)
+        v = votes.setdefault(key, [0, 0.0, wpb])
+        v[0] += 1
+        v[1] += rate
+    best = max(votes.items(), key=lambda kv: (kv[1][0], kv[1][1]))
+    return dict(best[0]), best[1][2]
+
+
+def bench_batch(args):
+    """C4: 512 uneven networks x 256 trajectories in one persistent launch per
+    chunk, the chunks captured in one HIP graph."""
+    import torch
+    from paper_1605_00854_amd import api
+    torch.cuda.set_device(0)
+    nets = ps.batch_c4()
+    ntraj, burn, T = 256, 10**4, 10**5
+    if args.sim_steps:
+        T = args.sim_steps
+        burn = min(burn, T // 10)
+    total = burn + T
+    chunk = args.chunk if args.chunk < total else total
+    passes = (total + chunk - 1) // chunk
+    total = passes * chunk
+    results = {}
+    for label, opts in (("product", None), ("plain", dict(reduce=0, group=0))):
+        if opts is None:
+            opts, wpb = tuned_opts_for(api, torch, nets, 4)
+        else:
+            wpb = 4
+        t0 = time.perf_counter()
+        items = []
+        for k, net in enumerate(nets):
+            tg = [ps.non_leaf_targets(net, 3)]
+            plan = api.Plan(net, interest=[a for a, _ in tg[0]], **opts)
+            items.append((plan, 1004000 + k, ntraj, tg))
+        b = api.Batch(items, count_from=burn, waves_per_block=wpb)
+        prep = time.perf_counter() - t0
+        b.init_states()
+        b.set_window(0, chunk)
+        g = b.graph(passes)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g.launch()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        work = sum(ntraj * total * net["n"] for net in nets)
+        results[label] = {"node_updates_per_s": work / dt, "seconds": dt, "prep_seconds": prep,
+                          "plan": opts, "waves_per_block": wpb, "graph_passes": passes, "chunk": chunk}
+        del g, b, items
+    out = {"metric": "node-updates/sec on 1 MI355X (batched uneven networks, one graph replay)",
+           "value": results["product"]["node_updates_per_s"], "unit": "node-updates/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "u32", "data": "synthetic",
+           "config": {"workload": f"C4: 512 random PBNs n~U[20,1500], 256 trajectories each, "
+                                  f"{T} steps + {burn} burn-in, hipGraph of {passes} persistent passes"},
+           "compare": results,
+           "product_over_plain": results["product"]["node_updates_per_s"] / results["plain"]["node_updates_per_s"]}
+    print(json.dumps(out))
+
+
+def bench_serve(args):
+    """C5: Poisson stream of 2000 queries at 200/s over 64 resident networks."""
+    import torch
+    from paper_1605_00854_amd import api, serve
+    torch.cuda.set_device(0)
+    nets = ps.served_c5()
+    nq = args.queries
+    results = {}
+    for label in ("product", "plain"):
+        if label == "product":
+            opts, wpb = tuned_opts_for(api, torch, nets, 5)
+        else:
+            opts, wpb = dict(reduce=0, group=0), 4
+        srv = serve.Server(nets, [1005000 + k for k in range(len(nets))], plan_opts=opts, traj_per_query=256,
+                           chunk=1000, burn_in=1000, min_counted=1000, max_steps=200000, waves_per_block=wpb)
+        qs = serve.poisson_queries(nets, nq, rate=200.0, seed=2005)
+        m = srv.run(qs, realtime=True)
+        m["plan"] = opts
+        results[label] = m
+    out = {"metric": "p50/p99 query latency and node-updates/sec on 1 MI355X (served queries)",
+           "value": results["product"]["p99_latency_s"], "unit": "s (p99 latency)", "n_gpus": 1,
+           "higher_is_better": False, "dtype": "u32", "data": "synthetic",
+           "config": {"workload": f"C5: {nq} queries, Poisson 200/s, 64 resident PBNs n~U[50,3000], "
+                                  "1-5 target nodes, r in {1e-2, 5e-3}, conf 0.95, 256 trajectories per query"},
+           "compare": results}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,12 +251,21 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the plain and reduction kernels")
     ap.add_argument("--wpb", type=int, default=0)
     ap.add_argument("--quick-tune", action="store_true")
+    ap.add_argument("--queries", type=int, default=2000, help="C5: number of served queries")
+    ap.add_argument("--plan", default="auto", choices=["auto", "plain", "reduction", "grouped"],
+                    help="product plan: autotuned, or a fixed preparation (profiling runs)")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="MiB copied once by a plain device copy (HBM counter calibration in profiles)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is design-only "
                                    "(trajectories shard by id, counters reduce with one integer all-reduce)"}))
         sys.exit(2)
 
+    if args.config == "C4":
+        return bench_batch(args)
+    if args.config == "C5":
+        return bench_serve(args)
     cfg = ps.config(args.config)
     if args.sim_steps:
         cfg.steps = args.sim_steps
@@ -175,9 +285,18 @@ def main():
     # autotuner: preparation options and launch shape, by short probe runs
     from paper_1605_00854_amd import autotune
     interest = sorted({a for tg in cfg.targets for a, _ in tg})
+    if args.copy_probe:
+        src = torch.ones(args.copy_probe << 18, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t_tune = time.perf_counter()
-    best_opts, best_wpb, trials = autotune.tune(net, interest, cfg.targets, cfg.ntraj, seed=cfg.seed,
-                                                quick=args.quick_tune)
+    if args.plan == "auto":
+        best_opts, best_wpb, trials = autotune.tune(net, interest, cfg.targets, cfg.ntraj, seed=cfg.seed,
+                                                    quick=args.quick_tune)
+    else:
+        best_opts, best_wpb, trials = PLANS[args.plan], 4, []
     t_tune = time.perf_counter() - t_tune
     if args.wpb:
         best_wpb = args.wpb
