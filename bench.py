@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 import pbn_synth as ps  # noqa: E402
 
 PEAK_ALU = 256 * 64 * 2.4e9        # int32 VALU lane-operations per second (256 CUs x 64 lanes x 2.4 GHz)
-PHILOX_SLOTS = 100                 # 10 rounds x (2 quarter-rate 32x32->64 multiplies + 2 xor3)
+PHILOX_SLOTS = 60                  # 10 rounds x (2 full-rate 32x32->64 multiplies + 4 two-input xors)
 
 PLANS = {
     "grouped": dict(reduce=1, group=1),

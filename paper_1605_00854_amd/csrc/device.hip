@@ -34,7 +34,19 @@ namespace {
 constexpr uint32_t kW0 = 0x9E3779B9u, kW1 = 0xBB67AE85u;
 constexpr uint32_t kM0 = 0xD2511F53u, kM1 = 0xCD9E8D57u;
 
-// Philox4x32-10 (Salmon et al., SC'11): counter (c0..c3), key (k0, k1).
+// Three-input XOR in one VALU instruction: gfx950's three-input bitwise op
+// with truth table 0x96 (a ^ b ^ c).  Pure ALU; the key operand is
+// wave-uniform and lives in an SGPR.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t k) {
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+  return r;
+}
+
+// Philox4x32-10 (Salmon et al., SC'11): counter (c0..c3), key (k0, k1).  Each
+// round multiplies words 0 and 2 by fixed constants (one full-rate
+// v_mad_u64_u32 each gives both halves) and mixes the high halves with words
+// 1 and 3 and the round key.
 __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
@@ -44,8 +56,8 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
     }
     const uint64_t p0 = uint64_t(kM0) * c0;
     const uint64_t p1 = uint64_t(kM1) * c2;
-    const uint32_t n0 = uint32_t(p1 >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = uint32_t(p0 >> 32) ^ c3 ^ k1;
+    const uint32_t n0 = xor3(uint32_t(p1 >> 32), c1, k0);
+    const uint32_t n2 = xor3(uint32_t(p0 >> 32), c3, k1);
     c1 = uint32_t(p1);
     c3 = uint32_t(p0);
     c0 = n0;
@@ -54,11 +66,13 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
   return make_uint4(c0, c1, c2, c3);
 }
 
-// Order LDS traffic between lanes of one wavefront (no hardware barrier).
+// Order LDS traffic between lanes of one wavefront.  The LDS executes the
+// instructions of one wave in issue order, so a read issued after a write of
+// the same wave observes it; only the compiler must be kept from reordering
+// (no hardware wait is needed).
 __device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
 __device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
@@ -117,13 +131,13 @@ __device__ __forceinline__ void load_slot(SlotRegs<Shape<PM, UM>::PW, Shape<PM, 
   r.base = rec.y;
   r.choice = rec.z;
   r.radix = rec.w;
-  r.draw = 0;
+  r.draw = 1u << 24;                    // one predictor, ring offset 0
   r.thr0 = r.thr1 = r.thr2 = 0xFFFFFFFFu;
 #pragma unroll
   for (int k = 0; k < PW; ++k) r.pw[k] = 0;
 #pragma unroll
   for (int k = 0; k < TTW; ++k) r.tt[k] = 0;
-  if (!(rec.x & PBN_SLOT_VALID)) return;
+  if (!(rec.x & PBN_SLOT_VALID)) return;   // padded lane: y points at the dummy record
   if (UM > 0 && (rec.x & PBN_SLOT_TABLE)) {
     const uint32_t* up = reinterpret_cast<const uint32_t*>(img + rec.y);
 #pragma unroll
@@ -245,10 +259,15 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   if constexpr (NREG > 0) {
 #pragma unroll
     for (int p = 0; p < NREG; ++p) {
-      if (uint32_t(p) < npass)
+      if (uint32_t(p) < npass) {
         load_slot<PM, UM>(cached[p], img, uint32_t(p) * 64u + lane);
-      else
-        cached[p].info = 0;   // no such pass: the slot-record region ends before it
+      } else {
+        // no such pass (the slot-record region ends before it): behave as a padded lane
+        cached[p] = Regs{};
+        cached[p].base = H->dummy_fn;
+        cached[p].draw = 1u << 24;
+        cached[p].thr0 = cached[p].thr1 = cached[p].thr2 = 0xFFFFFFFFu;
+      }
     }
   }
   wave_sync();
@@ -260,7 +279,7 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   const unsigned long long my_mask = lane < ntg ? a.tg->mask[lane] : 0ull;
   auto target_z = [&](const uint8_t* s) -> bool {
     const uint32_t b = s[my_pos];
-    const unsigned long long mism = __ballot(lane < npairs && b != my_val);
+    const unsigned long long mism = __ballot(b != my_val);   // lanes past npairs read the zero word, expect 0
     return (mism & my_mask) == 0ull;
   };
 

@@ -316,9 +316,11 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
 
   const uint32_t ns = uint32_t(slots.size());
   if (ns == 0) return fail(PBN_EINVAL, "plan has no nodes");
-  if (4ull * ns + 4 > 65535) return fail(PBN_ELDS, "too many slots (%u) for 16-bit state positions", ns);
   const uint32_t npass = (ns + PBN_WAVE - 1) / PBN_WAVE;
-  const uint32_t zero_pos = 4 * ns;
+  // every lane of every pass owns a state word (padded lanes write zeros there);
+  // the zero word read by unused parent entries follows them
+  if (4ull * npass * PBN_WAVE + 4 > 65535) return fail(PBN_ELDS, "too many slots (%u) for 16-bit state positions", ns);
+  const uint32_t zero_pos = 4 * npass * PBN_WAVE;
 
   plan.node_pos.assign(n, PBN_NONE);
   plan.node_slot.assign(n, PBN_NONE);
@@ -355,6 +357,7 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
     else
       nfnrec += g.nfn(s.members[0]);
   }
+  ++nfnrec;   // the dummy record read by padded lanes
   const size_t choice_base = slot_bytes;
   const size_t fn_base = choice_base + 16 * nchoice;
   const size_t tab_base = fn_base + 32 * nfnrec;
@@ -364,7 +367,11 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   std::vector<uint8_t> img(image_bytes, 0);
   auto put32 = [&](size_t off, uint32_t v) { std::memcpy(&img[off], &v, 4); };
   auto put16 = [&](size_t off, uint16_t v) { std::memcpy(&img[off], &v, 2); };
-  size_t choice_cur = choice_base, fn_cur = fn_base, tab_cur = tab_base;
+  // dummy FN record first: every parent is the zero position, truth table 0
+  const size_t dummy_fn = fn_base;
+  for (uint32_t b = 0; b < 8; ++b) put16(dummy_fn + 2 * b, uint16_t(zero_pos));
+  for (size_t s = ns; s < size_t(npass) * PBN_WAVE; ++s) put32(s * 16 + 4, uint32_t(dummy_fn));
+  size_t choice_cur = choice_base, fn_cur = fn_base + 32, tab_cur = tab_base;
   std::vector<pbn_pass_info> passes(npass, pbn_pass_info{0, 0, 0, 0});
   uint32_t max_fn_parents = 0, max_union = 0, multi_groups = 0;
   for (uint32_t s = 0; s < ns; ++s) {
@@ -471,7 +478,7 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   h.n_kept = uint32_t(kept.size());
   h.n_slots = ns;
   h.n_passes = npass;
-  h.state_dwords = ns + 1;
+  h.state_dwords = npass * PBN_WAVE + 1;
   h.state_words = (4 * ns + 31) / 32;
   h.n_jobs = njobs;
   h.fill_steps = njobs <= PBN_WAVE ? PBN_WAVE / njobs : 1;
@@ -486,6 +493,7 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   h.max_pmax = max_fn_parents;
   h.image_in_lds = image_bytes <= o.lds_budget_bytes ? 1u : 0u;
   h.has_table = max_union > 0 || std::any_of(slots.begin(), slots.end(), [](const Slot& s) { return s.table; });
+  h.dummy_fn = uint32_t(dummy_fn);
   std::memcpy(&plan.blob[0], &h, sizeof h);
   std::memcpy(&plan.blob[pass_off], passes.data(), sizeof(pbn_pass_info) * npass);
   std::memcpy(&plan.blob[q_off], g.Q.data(), 8 * size_t(n + 1));

@@ -7,9 +7,10 @@
 // selected predictor function (FN slot) or a group of up to 4 nodes evaluated
 // through one combined table (TABLE slot, Section 3.3).  Slot s is handled by
 // lane s % 64 in pass s / 64.  The trajectory state lives in LDS as one 32-bit
-// word per slot, byte k holding member k's value (0/1); one extra zero word
-// follows (ZERO position for unused parent entries).  Packed states in HBM use
-// bit 4*s + k for the same node.
+// word per lane of every pass, byte k holding member k's value (0/1); the
+// words of padded lanes only ever hold zeros; one extra zero word follows (the
+// position read by unused parent entries).  Packed states in HBM use bit
+// 4*s + k for the same node (valid slots only).
 #pragma once
 #include <stdint.h>
 
@@ -42,7 +43,7 @@ struct pbn_plan_header {
   uint32_t n_kept;
   uint32_t n_slots;
   uint32_t n_passes;
-  uint32_t state_dwords;   // n_slots + 1 (zero word)
+  uint32_t state_dwords;   // 64 * n_passes + 1 (zero word last)
   uint32_t state_words;    // packed words per trajectory = ceil(4 * n_slots / 32)
   uint32_t n_jobs;         // 1 + number of SEL blocks with a kept member
   uint32_t fill_steps;     // steps whose jobs are computed per fill (njobs <= 64)
@@ -53,11 +54,12 @@ struct pbn_plan_header {
   uint32_t p2o_off;        // blob offset of byte position -> orig (uint32[4 n_slots])
   uint32_t blk_off;        // blob offset of SEL block ids (uint32[n_jobs - 1])
   uint32_t pass_off;       // blob offset of pass info (pbn_pass_info[n_passes])
-  uint32_t zero_pos;       // byte position of the zero word (4 * n_slots)
+  uint32_t zero_pos;       // byte position of the zero word (256 * n_passes)
   uint32_t max_pmax;       // largest parent-entry count over all passes
   uint32_t image_in_lds;
   uint32_t has_table;
-  uint32_t pad[9];
+  uint32_t dummy_fn;       // image offset of an all-zero-position FN record (padded lanes)
+  uint32_t pad[8];
 };
 
 struct pbn_pass_info {
@@ -77,6 +79,8 @@ struct pbn_pass_info {
 //   tables:                   TABLE slot: 16 uint16 union-parent positions
 //                             (unused = zero position), then the byte table
 //                             T[c * 2^nu + x]
+// Padded lanes (slot index >= n_slots) have info = 0 and y = dummy_fn, an FN
+// record whose parents are all the zero position and whose truth table is 0.
 // Slot record (uint4):
 //   x = info word (PBN_SLOT_*)
 //   y = FN: image offset of the fn record of predictor 0 (predictor j at +32 j)
