@@ -1,0 +1,142 @@
+"""Edge cases of the step kernel against the oracle: degenerate networks,
+extreme perturbation rates, predictors too wide for an inline truth table,
+zero selection probabilities, empty launches, the node-count maximum and
+error returns of the device calls."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import pbn_synth as ps
+from oracle import exact
+from oracle import simulate as osim
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_1605_00854_amd import _lib, api  # noqa: E402
+
+NONE = 0xFFFFFFFF
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run_both(net, opts, targets, seed, ntraj, steps, chunks=None, wpb=0):
+    interest = sorted({a for tg in targets for a, _ in tg})
+    plan = api.Plan(net, interest=interest, **opts)
+    say(f"[gpu] n={net['n']} opts={opts} info={plan.info}")
+    tg = plan.targets(targets)
+    st = api.state_init(plan, seed, ntraj)
+    cn = api.new_counts(len(targets), ntraj)
+    step = 0
+    for c in (chunks or [steps]):
+        api.simulate(plan, seed, st, cn, tg, step, c, plain=plan.info["n_table_slots"] == 0,
+                     waves_per_block=wpb)
+        step += c
+    orig = api.unpack_bits(api.to_original(plan, st).cpu().numpy(), plan.n)
+    c = cn.cpu().numpy()
+    ref = osim.run(net, seed, np.arange(ntraj), steps, targets=targets)
+    kept = plan.node_pos() != NONE
+    assert np.array_equal(orig[:, kept], ref["state"][:, kept])
+    assert np.array_equal(c[:, :, 0], ref["hits"])
+    assert np.array_equal(c[:, :, 1], ref["n01"])
+    assert np.array_equal(c[:, :, 2], ref["n10"])
+    return plan, c
+
+
+@pytest.mark.parametrize("tt,closed", [([1, 1], "one"), ([1, 0], "half")])
+def test_single_node_networks(tt, closed):
+    p = 0.05
+    net = ps.assemble(1, p, [[(1.0, [0], tt)]])
+    plan, c = run_both(net, dict(reduce=1, group=1), [[(0, 1)]], 3, 64, 4000)
+    est = c[0, :, 0].sum() / (64 * 4000)
+    want = 1 / (1 + p) if closed == "one" else 0.5
+    assert abs(est - want) < 5 * math.sqrt(want * (1 - want) / 2000)
+
+
+@pytest.mark.parametrize("p", [0.5, 0.2, 1e-9])
+def test_extreme_perturbation_rates(p):
+    net = ps.medium_c2(n=50, p=p, seed=41)
+    run_both(net, dict(reduce=1, group=0), [ps.non_leaf_targets(net, 2)], 5, 16, 300)
+
+
+def test_only_interest_nodes_survive_reduction():
+    # a chain 0 -> 1 -> ... -> 9 plus a self-loop on 0: only node 9 is of interest,
+    # nothing below it can be removed, everything above it can
+    fns = [[(1.0, [0], [1, 0])]] + [[(1.0, [i - 1], [0, 1])] for i in range(1, 10)]
+    net = ps.assemble(10, 0.02, fns)
+    plan, _ = run_both(net, dict(reduce=1, group=1), [[(4, 1)]], 7, 8, 500)
+    assert plan.info["n_kept"] == 5
+
+
+def test_wide_predictors_use_table_slots():
+    # predictors with 8-10 parents cannot use the 128-bit inline table
+    rng = np.random.default_rng(3)
+    fns = []
+    n = 24
+    for i in range(n):
+        k = int(rng.integers(8, 11)) if i % 3 == 0 else int(rng.integers(1, 4))
+        l = 1 if i % 3 == 0 else int(rng.integers(1, 3))
+        probs = rng.dirichlet(np.ones(l)) if l > 1 else [1.0]
+        fns.append([(probs[j], list(rng.choice(n, size=k, replace=False)), rng.integers(0, 2, 1 << k))
+                    for j in range(l)])
+    net = ps.assemble(n, 0.01, fns)
+    plan, _ = run_both(net, dict(reduce=1, group=0), [[(0, 1), (1, 0)]], 9, 12, 400)
+    assert plan.info["n_table_slots"] >= n // 3
+
+
+def test_zero_selection_probabilities_and_four_predictors():
+    rng = np.random.default_rng(5)
+    n = 30
+    fns = []
+    for i in range(n):
+        probs = [0.0, 0.5, 0.0, 0.5] if i % 2 else [0.25, 0.25, 0.25, 0.25]
+        fns.append([(probs[j], list(rng.choice(n, size=3, replace=False)), rng.integers(0, 2, 8))
+                    for j in range(4)])
+    net = ps.assemble(n, 0.005, fns)
+    run_both(net, dict(reduce=1, group=0), [[(0, 1)]], 11, 20, 400)
+
+
+def test_empty_launches_and_ragged_shapes():
+    net = ps.medium_c2(n=70, p=0.01, seed=2)
+    plan = api.Plan(net, interest=[0, 1, 2])
+    tg = plan.targets([ps.non_leaf_targets(net, 2)])
+    st = api.state_init(plan, 1, 5)
+    before = st.clone()
+    cn = api.new_counts(1, 5)
+    api.simulate(plan, 1, st, cn, tg, 0, 0)                      # zero steps: no-op
+    assert torch.equal(st, before) and int(cn.abs().sum()) == 0
+    empty = api.new_state(plan, 0)
+    api.simulate(plan, 1, empty, api.new_counts(1, 0), tg, 0, 10)   # zero trajectories
+    # ragged: 5 trajectories over workgroups of 4, steps not a multiple of the fill
+    run_both(net, dict(reduce=1, group=1), [ps.non_leaf_targets(net, 2)], 1, 5, 97, chunks=[61, 36], wpb=4)
+
+
+def test_device_call_errors():
+    net = ps.medium_c2(n=40, p=0.01, seed=4)
+    plan = api.Plan(net, interest=[0, 1])
+    tg = plan.targets([[(0, 1)]])
+    st = api.state_init(plan, 1, 4)
+    cn = api.new_counts(1, 4)
+    with pytest.raises(_lib.PbnError) as e:
+        api.simulate(plan, 1, st, cn, tg, 0xFFFFFFF0, 100)
+    assert e.value.code == _lib.ERANGE
+    grouped = api.Plan(ps.large_c3(n=200, seed=5), interest=[0], reduce=1, group=1, max_parent_bits=6)
+    assert grouped.info["n_table_slots"] > 0
+    g_tg = grouped.targets([[(0, 1)]])
+    with pytest.raises(_lib.PbnError) as e:
+        api.simulate(grouped, 1, api.state_init(grouped, 1, 2), api.new_counts(1, 2), g_tg, 0, 10, plain=True)
+    assert e.value.code == _lib.EINVAL
+
+
+def test_maximum_node_count():
+    net = ps.random_pbn(16000, 1e-5, 77, nfn=lambda r: 1 if r.random() < 0.9 else 2,
+                        nparents=lambda r: int(r.integers(1, 4)))
+    run_both(net, dict(reduce=1, group=1, max_parent_bits=6), [[(0, 1), (15999, 0)]], 13, 2, 6)
