@@ -174,7 +174,8 @@ typedef struct pbn_plan_info {
   uint32_t max_fn_parents;  /* largest parent count of a predictor in FN slots   */
   uint32_t max_union_bits;  /* largest |union parents| of a table slot           */
   uint32_t n_multi_groups;  /* groups holding >= 2 multi-predictor nodes         */
-  uint32_t reserved[6];
+  uint32_t state_bytes;     /* LDS bytes of one trajectory state buffer          */
+  uint32_t reserved[5];
 } pbn_plan_info;
 
 pbn_status pbn_plan_info_get(const pbn_plan* plan, pbn_plan_info* info);

@@ -36,7 +36,7 @@ class pbn_plan_info(C.Structure):
     _fields_ = [(name, C.c_uint32) for name in (
         "n", "n_kept", "n_slots", "n_table_slots", "n_passes", "state_words", "n_jobs",
         "image_bytes", "table_bytes", "image_in_lds", "blob_bytes", "max_fn_parents",
-        "max_union_bits", "n_multi_groups")] + [("reserved", C.c_uint32 * 6)]
+        "max_union_bits", "n_multi_groups", "state_bytes")] + [("reserved", C.c_uint32 * 5)]
 
 
 class pbn_targets(C.Structure):

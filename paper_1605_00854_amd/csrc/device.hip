@@ -205,6 +205,15 @@ __device__ __forceinline__ uint32_t eval_slot(const SlotRegs<Shape<PM, UM>::PW, 
   return out;
 }
 
+// Store a slot's result: a table slot (s < ntab) writes its word of member
+// bytes, an FN slot writes its one byte.
+__device__ __forceinline__ void store_slot(uint32_t* ns, uint32_t s, uint32_t ntab, uint32_t fnb, uint32_t out) {
+  if (s < ntab)
+    ns[s] = out;
+  else
+    reinterpret_cast<uint8_t*>(ns)[fnb + (s - ntab)] = uint8_t(out);
+}
+
 // Everything one wavefront needs to advance one trajectory.
 struct TrajArgs {
   const uint8_t* blob;              // plan blob (global memory)
@@ -229,7 +238,7 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   using Regs = SlotRegs<PW, TTW>;
   const pbn_plan_header* H = reinterpret_cast<const pbn_plan_header*>(a.blob);
   const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t n = H->n, nslots = H->n_slots, npass = H->n_passes, njobs = H->n_jobs;
+  const uint32_t n = H->n, npass = H->n_passes, njobs = H->n_jobs;
   const uint32_t fill = H->fill_steps, sd = H->state_dwords, zero_pos = H->zero_pos;
   const uint32_t sdp = (sd + 3u) & ~3u;   // state buffer, padded to 16 bytes
   const unsigned long long* Q = reinterpret_cast<const unsigned long long*>(a.blob + H->q_off);
@@ -242,18 +251,20 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   const uint32_t traj = a.traj;
   const uint32_t k0 = uint32_t(a.seed), k1 = uint32_t(a.seed >> 32);
 
-  // unpack the packed state (bit 4 s + k) into one byte per member
+  // unpack the packed state (bit b = state byte b), eight 4-bit groups per word
   const uint32_t W = H->state_words;
   uint32_t* gst = a.state + size_t(a.tl) * W;
-  for (uint32_t s = lane; s < sd; s += 64u) {
-    uint32_t v = 0;
-    if (s < nslots) {
-      const uint32_t nib = (gst[s >> 3] >> ((s & 7u) * 4u)) & 0xFu;
-      v = (nib * 0x204081u) & 0x01010101u;
+  for (uint32_t w = lane; w < W; w += 64u) {
+    const uint32_t word = gst[w];
+#pragma unroll
+    for (uint32_t i = 0; i < 8u; ++i) {
+      sbuf0[8u * w + i] = (((word >> (4u * i)) & 0xFu) * 0x204081u) & 0x01010101u;
+      sbuf1[8u * w + i] = 0;
     }
-    sbuf0[s] = v;
-    sbuf1[s] = 0;
   }
+  // output position of this lane's slot in pass p: table slots own words,
+  // FN slots own bytes after them
+  const uint32_t ntab = H->n_table, fnb = H->fn_base;
 
   Regs cached[NREG > 0 ? NREG : 1];
   if constexpr (NREG > 0) {
@@ -344,13 +355,14 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
         if constexpr (NREG > 0) {
 #pragma unroll
           for (int p = 0; p < NREG; ++p) {
-            if (cached[p].info & PBN_SLOT_VALID) ns[uint32_t(p) * 64u + lane] = eval_slot<PM, UM>(cached[p], img, csb, rs);
+            if (cached[p].info & PBN_SLOT_VALID)
+              store_slot(ns, uint32_t(p) * 64u + lane, ntab, fnb, eval_slot<PM, UM>(cached[p], img, csb, rs));
           }
         } else {
           for (uint32_t p = 0; p < npass; ++p) {
             Regs r;
             load_slot<PM, UM>(r, img, p * 64u + lane);
-            if (r.info & PBN_SLOT_VALID) ns[p * 64u + lane] = eval_slot<PM, UM>(r, img, csb, rs);
+            if (r.info & PBN_SLOT_VALID) store_slot(ns, p * 64u + lane, ntab, fnb, eval_slot<PM, UM>(r, img, csb, rs));
           }
         }
         cur ^= 1u;
@@ -376,13 +388,11 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   const uint32_t* fs = cur ? sbuf1 : sbuf0;
   for (uint32_t w = lane; w < W; w += 64u) {
     uint32_t word = 0;
+#pragma unroll
     for (uint32_t i = 0; i < 8u; ++i) {
-      const uint32_t s = 8u * w + i;
-      if (s < nslots) {
-        const uint32_t v = fs[s];
-        const uint32_t nib = (v & 1u) | ((v >> 7) & 2u) | ((v >> 14) & 4u) | ((v >> 21) & 8u);
-        word |= nib << (4u * i);
-      }
+      const uint32_t v = fs[8u * w + i];
+      const uint32_t nib = (v & 1u) | ((v >> 7) & 2u) | ((v >> 14) & 4u) | ((v >> 21) & 8u);
+      word |= nib << (4u * i);
     }
     gst[w] = word;
   }
@@ -489,7 +499,7 @@ __global__ void k_batch_end(pbn_batch_ctl* ctl) { ctl->step0 += ctl->nsteps; }
 __global__ void k_state_init(const uint8_t* blob, unsigned long long seed, uint32_t traj0, uint32_t ntraj,
                              uint32_t* state) {
   const pbn_plan_header* H = reinterpret_cast<const pbn_plan_header*>(blob);
-  const uint32_t W = H->state_words, nbytes = 4u * H->n_slots;
+  const uint32_t W = H->state_words, nbytes = 32u * W;
   const uint32_t* p2o = reinterpret_cast<const uint32_t*>(blob + H->p2o_off);
   const uint32_t k0 = uint32_t(seed), k1 = uint32_t(seed >> 32);
   const size_t total = size_t(ntraj) * W;
@@ -598,7 +608,7 @@ pbn_status simulate_common(bool plain, const pbn_plan* plan, const void* d_plan,
   if (targets->ntargets < 1 || targets->ntargets > 64 || targets->npairs > PBN_MAX_PAIRS)
     return fail(PBN_EINVAL, "bad targets (build them with pbn_targets_build)");
   for (uint32_t k = 0; k < targets->npairs; ++k)
-    if (targets->pos[k] >= 4u * plan->info.n_slots) return fail(PBN_EINVAL, "target position outside the plan");
+    if (targets->pos[k] >= plan->info.state_bytes) return fail(PBN_EINVAL, "target position outside the plan");
   if (plain && plan->has_table) return fail(PBN_EINVAL, "the plain kernel needs a plan without table slots");
   if (ntraj == 0 || nsteps == 0) return PBN_OK;
 

@@ -302,10 +302,10 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
                     (unsigned long long)table_entries(s.members), o.max_table_entries);
     }
   }
-  // order: FN slots first (multi-predictor, then by parent count, descending),
-  // table slots last (by union size, descending)
+  // order: table slots first (by union size, descending), then FN slots
+  // (multi-predictor first, then by parent count, descending)
   std::stable_sort(slots.begin(), slots.end(), [&](const Slot& a, const Slot& b) {
-    if (a.table != b.table) return !a.table;
+    if (a.table != b.table) return a.table;
     if (!a.table) {
       const bool ma = g.nfn(a.members[0]) > 1, mb = g.nfn(b.members[0]) > 1;
       if (ma != mb) return ma;
@@ -317,10 +317,17 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   const uint32_t ns = uint32_t(slots.size());
   if (ns == 0) return fail(PBN_EINVAL, "plan has no nodes");
   const uint32_t npass = (ns + PBN_WAVE - 1) / PBN_WAVE;
-  // every lane of every pass owns a state word (padded lanes write zeros there);
-  // the zero word read by unused parent entries follows them
-  if (4ull * npass * PBN_WAVE + 4 > 65535) return fail(PBN_ELDS, "too many slots (%u) for 16-bit state positions", ns);
-  const uint32_t zero_pos = 4 * npass * PBN_WAVE;
+  // state bytes: table slot s (s < n_table) owns the word at 4 s (member k at
+  // byte k); FN slot s owns one byte at 4 n_table + (s - n_table); padded lanes
+  // of the last pass own the bytes after it; then the zero word read by unused
+  // parent entries
+  const uint32_t ntab = uint32_t(std::count_if(slots.begin(), slots.end(), [](const Slot& s) { return s.table; }));
+  const uint32_t fn_pos0 = 4 * ntab;
+  const uint32_t fn_end = fn_pos0 + (npass * PBN_WAVE - ntab);
+  const uint32_t zero_pos = (fn_end + 3) & ~3u;
+  const uint32_t state_words = (zero_pos + 4 + 31) / 32;
+  if (32ull * state_words > 65535) return fail(PBN_ELDS, "too many slots (%u) for 16-bit state positions", ns);
+  auto slot_pos = [&](uint32_t s, uint32_t k) { return s < ntab ? 4 * s + k : fn_pos0 + (s - ntab); };
 
   plan.node_pos.assign(n, PBN_NONE);
   plan.node_slot.assign(n, PBN_NONE);
@@ -328,7 +335,7 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   for (uint32_t s = 0; s < ns; ++s) {
     plan.slot_is_table[s] = slots[s].table;
     for (uint32_t k = 0; k < slots[s].members.size(); ++k) {
-      plan.node_pos[slots[s].members[k]] = 4 * s + k;
+      plan.node_pos[slots[s].members[k]] = slot_pos(s, k);
       plan.node_slot[slots[s].members[k]] = s;
     }
   }
@@ -464,7 +471,7 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   const size_t q_off = align16(pass_off + sizeof(pbn_pass_info) * npass);
   const size_t o2p_off = align16(q_off + 8 * size_t(n + 1));
   const size_t p2o_off = align16(o2p_off + 4 * size_t(n));
-  const size_t blk_off = align16(p2o_off + 4 * size_t(4 * ns));
+  const size_t blk_off = align16(p2o_off + 4 * size_t(32 * state_words));
   const size_t image_off = align16(blk_off + 4 * blocks.size() + 4);
   const size_t total = align16(image_off + image_bytes);
   if (total > 0xFFFFFFF0ull) return fail(PBN_ELDS, "plan blob too large");
@@ -478,8 +485,10 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   h.n_kept = uint32_t(kept.size());
   h.n_slots = ns;
   h.n_passes = npass;
-  h.state_dwords = npass * PBN_WAVE + 1;
-  h.state_words = (4 * ns + 31) / 32;
+  h.state_dwords = 8 * state_words;
+  h.state_words = state_words;
+  h.n_table = ntab;
+  h.fn_base = fn_pos0;
   h.n_jobs = njobs;
   h.fill_steps = njobs <= PBN_WAVE ? PBN_WAVE / njobs : 1;
   h.image_bytes = uint32_t(image_bytes);
@@ -498,7 +507,7 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   std::memcpy(&plan.blob[pass_off], passes.data(), sizeof(pbn_pass_info) * npass);
   std::memcpy(&plan.blob[q_off], g.Q.data(), 8 * size_t(n + 1));
   std::memcpy(&plan.blob[o2p_off], plan.node_pos.data(), 4 * size_t(n));
-  std::vector<uint32_t> p2o(4 * size_t(ns), PBN_NONE);
+  std::vector<uint32_t> p2o(32 * size_t(state_words), PBN_NONE);
   for (uint32_t v = 0; v < n; ++v)
     if (plan.node_pos[v] != PBN_NONE) p2o[plan.node_pos[v]] = v;
   std::memcpy(&plan.blob[p2o_off], p2o.data(), 4 * p2o.size());
@@ -517,6 +526,7 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   in.n_table_slots = uint32_t(std::count_if(slots.begin(), slots.end(), [](const Slot& s) { return s.table; }));
   in.n_passes = npass;
   in.state_words = h.state_words;
+  in.state_bytes = 32 * state_words;
   in.n_jobs = njobs;
   in.image_bytes = uint32_t(image_bytes);
   in.table_bytes = uint32_t(tab_bytes);

@@ -6,11 +6,12 @@
 // are packed into "slots": a slot is either one node evaluated through its
 // selected predictor function (FN slot) or a group of up to 4 nodes evaluated
 // through one combined table (TABLE slot, Section 3.3).  Slot s is handled by
-// lane s % 64 in pass s / 64.  The trajectory state lives in LDS as one 32-bit
-// word per lane of every pass, byte k holding member k's value (0/1); the
-// words of padded lanes only ever hold zeros; one extra zero word follows (the
-// position read by unused parent entries).  Packed states in HBM use bit
-// 4*s + k for the same node (valid slots only).
+// lane s % 64 in pass s / 64; table slots come first.  The trajectory state
+// lives in LDS as one byte per node value (0/1): table slot s (s < n_table)
+// owns the word at byte 4 s (member k at byte k), FN slot s owns the byte at
+// fn_base + (s - n_table); padded lanes own the bytes after the last FN slot
+// and only ever hold zeros; the zero word read by unused parent entries follows
+// at zero_pos.  Packed states in HBM use bit b for state byte b.
 #pragma once
 #include <stdint.h>
 
@@ -43,23 +44,25 @@ struct pbn_plan_header {
   uint32_t n_kept;
   uint32_t n_slots;
   uint32_t n_passes;
-  uint32_t state_dwords;   // 64 * n_passes + 1 (zero word last)
-  uint32_t state_words;    // packed words per trajectory = ceil(4 * n_slots / 32)
+  uint32_t state_dwords;   // LDS state buffer in words = 8 * state_words
+  uint32_t state_words;    // packed words per trajectory = ceil((zero_pos + 4) / 32)
   uint32_t n_jobs;         // 1 + number of SEL blocks with a kept member
   uint32_t fill_steps;     // steps whose jobs are computed per fill (njobs <= 64)
   uint32_t image_bytes;    // bytes of the image (slot, choice, fn records, tables)
   uint32_t image_off;      // blob offset of the image
   uint32_t q_off;          // blob offset of Q[0..n] (uint64)
   uint32_t o2p_off;        // blob offset of orig -> byte position (uint32[n])
-  uint32_t p2o_off;        // blob offset of byte position -> orig (uint32[4 n_slots])
+  uint32_t p2o_off;        // blob offset of byte position -> orig (uint32[32 state_words])
   uint32_t blk_off;        // blob offset of SEL block ids (uint32[n_jobs - 1])
   uint32_t pass_off;       // blob offset of pass info (pbn_pass_info[n_passes])
-  uint32_t zero_pos;       // byte position of the zero word (256 * n_passes)
+  uint32_t zero_pos;       // byte position of the zero word
   uint32_t max_pmax;       // largest parent-entry count over all passes
   uint32_t image_in_lds;
   uint32_t has_table;
   uint32_t dummy_fn;       // image offset of an all-zero-position FN record (padded lanes)
-  uint32_t pad[8];
+  uint32_t n_table;        // table slots (slots 0 .. n_table - 1)
+  uint32_t fn_base;        // byte position of the first FN slot (4 n_table)
+  uint32_t pad[6];
 };
 
 struct pbn_pass_info {

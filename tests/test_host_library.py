@@ -120,8 +120,14 @@ def test_plan_slots_cover_kept_nodes_once():
     kept = pos != 0xFFFFFFFF
     assert np.array_equal(slot != 0xFFFFFFFF, kept)
     assert len(set(pos[kept].tolist())) == kept.sum()
-    assert np.all(pos[kept] // 4 == slot[kept])
     assert is_table.size == plan.info["n_slots"]
+    ntab = int(is_table.sum())
+    assert np.all(is_table[:ntab]) and not np.any(is_table[ntab:])     # table slots first
+    s = slot[kept]
+    tab = s < ntab
+    assert np.all(pos[kept][tab] // 4 == s[tab])                        # a word per table slot
+    assert np.all(pos[kept][~tab] == 4 * ntab + (s[~tab] - ntab))       # a byte per FN slot
+    assert pos[kept].max() < plan.info["state_bytes"] - 4
 
 
 def test_invalid_networks_are_rejected():
