@@ -19,8 +19,9 @@
 //     are written to the other state buffer (synchronous update).
 //   * Target hits: lanes holding target pairs compare the new state, a ballot
 //     collects mismatches, lane t counts hits of target t.
-// The state of a trajectory lives in LDS as one 32-bit word per slot (one byte
-// per member node); plan records and tables are staged in LDS when they fit.
+// The state of a trajectory lives in LDS as one byte per node value (a 32-bit
+// word per table slot, a byte per FN slot); plan records and tables are staged
+// in LDS when they fit.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
