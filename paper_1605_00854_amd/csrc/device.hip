@@ -78,6 +78,30 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// (b ^ want) & care in one VALU instruction (three-input bitwise op); the
+// table is symmetric in its first and third inputs.
+__device__ __forceinline__ uint32_t masked_xor(uint32_t b, uint32_t care, uint32_t want) {
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x48" : "=v"(r) : "s"(b), "v"(care), "v"(want));
+  return r;
+}
+
+// (a << 1) | b in one VALU instruction (keeps gather chains from being
+// re-associated into shift-and-or trees that take more instructions).
+__device__ __forceinline__ uint32_t shl1_or(uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("v_lshl_or_b32 %0, %1, 1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
+// High word of w + c for a 64-bit c = 2^64 - t: 0 when w >= t, all ones when
+// w < t (t <= 2^32).  One full-rate multiply-add (w * 1 + c).
+__device__ __forceinline__ uint32_t borrow_hi(uint32_t w, unsigned long long c) {
+  unsigned long long d, carry;
+  asm("v_mad_u64_u32 %0, %1, %2, 1, %3" : "=v"(d), "=s"(carry) : "v"(w), "v"(c));
+  return uint32_t(d >> 32);
+}
+
 struct SimParams {
   const uint8_t* blob;
   uint32_t* state;
@@ -90,25 +114,44 @@ struct SimParams {
   pbn_targets tg;
 };
 
+template <int PM, int UM>
+struct Shape {
+  static constexpr int PW = (PM + 1) / 2;                    // parent-position words of an FN record
+  static constexpr int TTW = PM <= 5 ? 1 : 4;                // truth-table words of an FN record
+  static constexpr int UW = UM > 0 ? UM / 2 : 1;             // union-position words of a TABLE slot
+  static constexpr int XW = PW > UW ? PW : UW;               // position words held per slot
+};
+
+// The part of an FN record a lookup needs: parent positions and truth table.
+template <int PW, int TTW>
+struct FnRec {
+  uint32_t pw[PW];
+  uint32_t tt[TTW];
+};
+
 // Per-lane data of one slot, either cached in registers for the whole launch
 // (plans of at most NREG lane passes) or reloaded from the image every pass.
-template <int PW, int TTW>
+template <int XW, int TTW>
 struct SlotRegs {
-  uint32_t info, base, choice, radix;   // slot record
-  uint32_t draw, thr0, thr1, thr2;      // FN slot of a multi-predictor node: its choice record
-  uint32_t pw[PW];                      // FN single-predictor: parent words; TABLE: union parents
-  uint32_t tt[TTW];                     // FN single-predictor: truth-table words
+  uint32_t info;                    // slot-record info word (PBN_SLOT_*)
+  uint32_t base;                    // FN: record of predictor 0; TABLE: union-parent list
+  uint32_t choice, radix;           // TABLE: first choice record, mixed-radix weights
+  uint32_t draw, thr0, thr1, thr2;  // FN: its choice record (ring offset | l << 24, thresholds)
+  uint32_t spos;                    // state byte written by the slot
+  uint32_t pw[XW];                  // TABLE: union parents; one-predictor FN: its parents
+  uint32_t tt[TTW];                 // one-predictor FN: its truth table
 };
 
 template <int K>
 __device__ __forceinline__ uint32_t gather(const uint8_t* cs, const uint32_t* pw) {
-  // all K byte reads are independent: issued back to back, one wait
+  // all K byte reads are independent: issued back to back, one wait; state
+  // bytes are 0 or 1, so the index is a chain of shift-or steps
   uint32_t b[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) b[k] = cs[(k & 1) ? (pw[k >> 1] >> 16) : (pw[k >> 1] & 0xFFFFu)];
-  uint32_t idx = 0;
+  uint32_t idx = b[K - 1];
 #pragma unroll
-  for (int k = 0; k < K; ++k) idx |= b[k] << k;
+  for (int k = K - 2; k >= 0; --k) idx = shl1_or(idx, b[k]);
   return idx;
 }
 
@@ -117,102 +160,176 @@ __device__ __forceinline__ uint32_t choose(uint32_t w, uint32_t t0, uint32_t t1,
   return min(j, nfn - 1u);
 }
 
-template <int PM, int UM>
-struct Shape {
-  static constexpr int PW = ((PM > UM ? PM : UM) + 1) / 2;
-  static constexpr int TTW = PM <= 5 ? 1 : 4;
+// The same choice from negated thresholds (2^64 - CUM[m] for m < l - 1, and
+// 2^64 - 2^32, never reached, for the others): 3 + the three borrows.
+struct NegThr {
+  unsigned long long c0, c1, c2;
 };
 
+__device__ __forceinline__ NegThr neg_thresholds(uint32_t t0, uint32_t t1, uint32_t t2, uint32_t nfn) {
+  constexpr unsigned long long kNever = 0xFFFFFFFF00000000ull;
+  NegThr n;
+  n.c0 = nfn > 1u ? 0ull - t0 : kNever;
+  n.c1 = nfn > 2u ? 0ull - t1 : kNever;
+  n.c2 = nfn > 3u ? 0ull - t2 : kNever;
+  return n;
+}
+
+__device__ __forceinline__ uint32_t choose_neg(uint32_t w, const NegThr& n) {
+  return 3u + borrow_hi(w, n.c0) + borrow_hi(w, n.c1) + borrow_hi(w, n.c2);
+}
+
+// Layout of a plan's FN records (header fields) and the zero-position pair.
+struct FnFmt {
+  uint32_t units;     // 16-byte units per record
+  uint32_t jshift;    // log2 of the bytes from predictor j's record to j + 1's
+  uint32_t hoff;      // bytes from a record's first unit to its second
+  uint32_t zp2;       // zero position in both halves of a word
+};
+
+// FN record of predictor j of the slot whose predictor 0 is at image offset
+// `base`: one 16-byte unit (5 positions, 32-entry table) or two units (7
+// positions; 128-entry table).  A gather-width-7 kernel reads two-unit plans;
+// with MIXED (batches of plans of both kinds) it also reads one-unit plans
+// (positions 5-7 = the zero position, table words 1-3 never selected).
+template <int PM, int UM, bool MIXED>
+__device__ __forceinline__ FnRec<Shape<PM, UM>::PW, Shape<PM, UM>::TTW> load_fn(const uint8_t* img, uint32_t base,
+                                                                               uint32_t j, const FnFmt& fm) {
+  constexpr int TTW = Shape<PM, UM>::TTW;
+  FnRec<Shape<PM, UM>::PW, TTW> r;
+  const uint8_t* rp = img + base + (j << fm.jshift);
+  const uint4 a = *reinterpret_cast<const uint4*>(rp);
+  r.pw[0] = a.x;
+  r.pw[1] = a.y;
+  r.pw[2] = a.z;
+  if constexpr (TTW == 1) {
+    r.tt[0] = a.w;
+  } else {
+    if (!MIXED || fm.units == 2u) {
+      const uint4 b = *reinterpret_cast<const uint4*>(rp + fm.hoff);
+      r.pw[3] = a.w;
+      r.tt[0] = b.x;
+      r.tt[1] = b.y;
+      r.tt[2] = b.z;
+      r.tt[3] = b.w;
+    } else {
+      r.pw[3] = fm.zp2;
+      r.tt[0] = a.w;
+      r.tt[1] = r.tt[2] = r.tt[3] = 0u;
+    }
+  }
+  return r;
+}
+
+// Look up an FN record's truth table over its parents in state `cs`.
 template <int PM, int UM>
-__device__ __forceinline__ void load_slot(SlotRegs<Shape<PM, UM>::PW, Shape<PM, UM>::TTW>& r, const uint8_t* img,
-                                          uint32_t slot) {
-  constexpr int PW = Shape<PM, UM>::PW, TTW = Shape<PM, UM>::TTW;
-  const uint4 rec = reinterpret_cast<const uint4*>(img)[slot];
+__device__ __forceinline__ uint32_t eval_fn(const FnRec<Shape<PM, UM>::PW, Shape<PM, UM>::TTW>& r, const uint8_t* cs) {
+  constexpr int TTW = Shape<PM, UM>::TTW;
+  const uint32_t idx = gather<PM>(cs, r.pw);
+  uint32_t ttw = r.tt[0];
+  if constexpr (TTW > 1) {
+    // word idx / 32 of the 128-bit table, selected among scalars (an indexed
+    // array here would be placed in scratch memory)
+    const uint32_t t1 = r.tt[1], t2 = r.tt[2], t3 = r.tt[3];
+    const uint32_t lo = (idx & 32u) ? t1 : ttw, hi = (idx & 32u) ? t3 : t2;
+    ttw = (idx & 64u) ? hi : lo;
+  }
+  return __builtin_amdgcn_ubfe(ttw, idx, 1u);   // bit idx % 32
+}
+
+// Slot record of `slot` (lane slot % 64 of pass slot / 64) and what it points
+// at: a table slot's union parents, a multi-predictor node's choice record, a
+// one-predictor node's own FN record.
+template <int PM, int UM, bool MIXED>
+__device__ __forceinline__ void load_slot(SlotRegs<Shape<PM, UM>::XW, Shape<PM, UM>::TTW>& r, const uint8_t* img,
+                                          uint32_t slot, const FnFmt& fm) {
+  constexpr int XW = Shape<PM, UM>::XW, TTW = Shape<PM, UM>::TTW, PW = Shape<PM, UM>::PW, UW = Shape<PM, UM>::UW;
+  uint4 rec = reinterpret_cast<const uint4*>(img)[slot];
+  // all four words are taken here: keeps the record one 16-byte read instead
+  // of pieces re-read inside the branches below
+  asm volatile("" : "+v"(rec.x), "+v"(rec.y), "+v"(rec.z), "+v"(rec.w));
   r.info = rec.x;
   r.base = rec.y;
   r.choice = rec.z;
   r.radix = rec.w;
-  r.draw = 1u << 24;                    // one predictor, ring offset 0
+  r.draw = 1u << 24;
   r.thr0 = r.thr1 = r.thr2 = 0xFFFFFFFFu;
 #pragma unroll
-  for (int k = 0; k < PW; ++k) r.pw[k] = 0;
+  for (int k = 0; k < XW; ++k) r.pw[k] = 0;
 #pragma unroll
   for (int k = 0; k < TTW; ++k) r.tt[k] = 0;
-  if (!(rec.x & PBN_SLOT_VALID)) return;   // padded lane: y points at the dummy record
   if (UM > 0 && (rec.x & PBN_SLOT_TABLE)) {
+    r.spos = 4u * slot;
     const uint32_t* up = reinterpret_cast<const uint32_t*>(img + rec.y);
 #pragma unroll
-    for (int k = 0; k < PW; ++k) r.pw[k] = up[k];
-    return;
-  }
-  if (PBN_SLOT_NMULTI(rec.x)) {
-    const uint4 ch = *reinterpret_cast<const uint4*>(img + rec.z);
-    r.draw = ch.x;
-    r.thr0 = ch.y;
-    r.thr1 = ch.z;
-    r.thr2 = ch.w;
+    for (int k = 0; k < UW; ++k) r.pw[k] = up[k];
   } else {
-    const uint32_t* fr = reinterpret_cast<const uint32_t*>(img + rec.y);
+    r.spos = rec.w;   // FN slot or padded lane: its state byte
+    if (PBN_SLOT_NMULTI(rec.x)) {
+      const uint4 ch = *reinterpret_cast<const uint4*>(img + rec.z);
+      r.draw = ch.x;
+      r.thr0 = ch.y;
+      r.thr1 = ch.z;
+      r.thr2 = ch.w;
+    } else {
+      // one-predictor node or padded lane (a dummy record)
+      const auto f = load_fn<PM, UM, MIXED>(img, rec.y, 0u, fm);
 #pragma unroll
-    for (int k = 0; k < PW; ++k) r.pw[k] = fr[k];
+      for (int k = 0; k < PW; ++k) r.pw[k] = f.pw[k];
 #pragma unroll
-    for (int k = 0; k < TTW; ++k) r.tt[k] = fr[4 + k];
+      for (int k = 0; k < TTW; ++k) r.tt[k] = f.tt[k];
+    }
   }
 }
 
-// Evaluate one slot from state `cs`; returns the word to store (one byte per member).
+// TABLE slot: combined-function index from its multi-predictor members'
+// choices (mixed radix), union parents, one table byte expanded to one byte
+// per member (Section 3.3).
 template <int PM, int UM>
-__device__ __forceinline__ uint32_t eval_slot(const SlotRegs<Shape<PM, UM>::PW, Shape<PM, UM>::TTW>& r,
-                                              const uint8_t* img, const uint8_t* cs, const uint8_t* rs) {
-  constexpr int PW = Shape<PM, UM>::PW, TTW = Shape<PM, UM>::TTW;
-  uint32_t out = 0;
-  if (UM > 0 && (r.info & PBN_SLOT_TABLE)) {
-    // combined predictor functions of a group: mixed-radix choice, union parents
-    uint32_t c = 0;
-    const uint32_t nm = PBN_SLOT_NMULTI(r.info);
-    for (uint32_t m = 0; m < nm; ++m) {
-      const uint4 ch = *reinterpret_cast<const uint4*>(img + r.choice + 16u * m);
-      const uint32_t w = *reinterpret_cast<const uint32_t*>(rs + (ch.x & 0xFFFFFFu));
-      c += choose(w, ch.y, ch.z, ch.w, ch.x >> 24) * ((r.radix >> (8u * m)) & 0xFFu);
-    }
-    const uint32_t x = gather<(UM > 0 ? UM : 1)>(cs, r.pw);
-    const uint32_t v = img[r.base + 32u + (c << PBN_SLOT_NU(r.info)) + x];
-    out = (v * 0x204081u) & 0x01010101u;
-  } else {
-    uint32_t pw[PW], tt[TTW];
-#pragma unroll
-    for (int k = 0; k < PW; ++k) pw[k] = r.pw[k];
-#pragma unroll
-    for (int k = 0; k < TTW; ++k) tt[k] = r.tt[k];
-    if (PBN_SLOT_NMULTI(r.info)) {
-      const uint32_t w = *reinterpret_cast<const uint32_t*>(rs + (r.draw & 0xFFFFFFu));
-      const uint32_t j = choose(w, r.thr0, r.thr1, r.thr2, r.draw >> 24);
-      const uint4* fr = reinterpret_cast<const uint4*>(img + r.base + 32u * j);
-      const uint4 a0 = fr[0], a1 = fr[1];
-      const uint32_t f[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
-#pragma unroll
-      for (int k = 0; k < PW; ++k) pw[k] = f[k];
-#pragma unroll
-      for (int k = 0; k < TTW; ++k) tt[k] = f[4 + k];
-    }
-    const uint32_t idx = gather<PM>(cs, pw);
-    uint32_t ttw = tt[0];
-    if constexpr (TTW > 1) {
-      const uint32_t q = idx >> 5;
-      ttw = q == 0 ? tt[0] : q == 1 ? tt[1] : q == 2 ? tt[2] : tt[3];
-    }
-    out = (ttw >> (idx & 31u)) & 1u;
+__device__ __forceinline__ uint32_t eval_table(const SlotRegs<Shape<PM, UM>::XW, Shape<PM, UM>::TTW>& r,
+                                               const uint8_t* img, const uint8_t* cs, const uint8_t* rs) {
+  uint32_t c = 0;
+  const uint32_t nm = PBN_SLOT_NMULTI(r.info);
+  for (uint32_t m = 0; m < nm; ++m) {
+    const uint4 ch = *reinterpret_cast<const uint4*>(img + r.choice + 16u * m);
+    const uint32_t w = *reinterpret_cast<const uint32_t*>(rs + (ch.x & 0xFFFFFFu));
+    c += choose(w, ch.y, ch.z, ch.w, ch.x >> 24) * ((r.radix >> (8u * m)) & 0xFFu);
   }
-  return out;
+  const uint32_t x = gather<(UM > 0 ? UM : 1)>(cs, r.pw);
+  const uint32_t v = img[r.base + 32u + (c << PBN_SLOT_NU(r.info)) + x];
+  return (v * 0x204081u) & 0x01010101u;
 }
 
-// Store a slot's result: a table slot (s < ntab) writes its word of member
-// bytes, an FN slot writes its one byte.
-__device__ __forceinline__ void store_slot(uint32_t* ns, uint32_t s, uint32_t ntab, uint32_t fnb, uint32_t out) {
-  if (s < ntab)
-    ns[s] = out;
+// One slot: a table slot, a multi-predictor node (select from its drawn word,
+// then read the chosen record) or a one-predictor node (record already held).
+// `nt`: the slot's negated thresholds when held for the launch, else null.
+template <int PM, int UM, bool MIXED>
+__device__ __forceinline__ uint32_t eval_slot(const SlotRegs<Shape<PM, UM>::XW, Shape<PM, UM>::TTW>& r,
+                                              const NegThr* nt, const uint8_t* img, const uint8_t* cs,
+                                              const uint8_t* rs, const FnFmt& fm) {
+  constexpr int PW = Shape<PM, UM>::PW, TTW = Shape<PM, UM>::TTW;
+  if (UM > 0 && (r.info & PBN_SLOT_TABLE)) return eval_table<PM, UM>(r, img, cs, rs);
+  FnRec<PW, TTW> f;
+#pragma unroll
+  for (int k = 0; k < PW; ++k) f.pw[k] = r.pw[k];
+#pragma unroll
+  for (int k = 0; k < TTW; ++k) f.tt[k] = r.tt[k];
+  if (PBN_SLOT_NMULTI(r.info)) {
+    const uint32_t w = *reinterpret_cast<const uint32_t*>(rs + (r.draw & 0xFFFFFFu));
+    const uint32_t j = nt ? choose_neg(w, *nt) : choose(w, r.thr0, r.thr1, r.thr2, r.draw >> 24);
+    f = load_fn<PM, UM, MIXED>(img, r.base, j, fm);
+  }
+  return eval_fn<PM, UM>(f, cs);
+}
+
+// Store a slot's result: a table slot writes its word of member bytes, an FN
+// slot (or padded lane) its one byte.
+template <int UM>
+__device__ __forceinline__ void store_slot(uint8_t* ns, uint32_t info, uint32_t spos, uint32_t out) {
+  if (UM > 0 && (info & PBN_SLOT_TABLE))
+    *reinterpret_cast<uint32_t*>(ns + spos) = out;
   else
-    reinterpret_cast<uint8_t*>(ns)[fnb + (s - ntab)] = uint8_t(out);
+    ns[spos] = uint8_t(out);
 }
 
 // Everything one wavefront needs to advance one trajectory.
@@ -232,15 +349,26 @@ struct TrajArgs {
 
 // PM: parent bytes gathered per FN slot (>= the plan's largest predictor);
 // UM: union bits gathered per TABLE slot (0: no table slots);
-// NREG: lane passes whose slot data stay in registers (0: reload every pass).
-template <int PM, int UM, int NREG>
+// NREG: lane passes whose slot data stay in registers (0: reload every pass);
+// MIXED: FN records of one or two units (batches of plans of both kinds).
+template <int PM, int UM, int NREG, bool MIXED>
 __device__ __forceinline__ void run_traj(const TrajArgs& a) {
-  constexpr int PW = Shape<PM, UM>::PW, TTW = Shape<PM, UM>::TTW;
-  using Regs = SlotRegs<PW, TTW>;
+  constexpr int XW = Shape<PM, UM>::XW, TTW = Shape<PM, UM>::TTW;
+  constexpr int NR = NREG > 0 ? NREG : 1;
+  // FN-only plans with register-held slots read target values from the pass
+  // ballots (state byte b = bit b % 64 of pass b / 64's ballot)
+  constexpr bool kBallotTargets = UM == 0 && NREG > 0;
+  using Regs = SlotRegs<XW, TTW>;
   const pbn_plan_header* H = reinterpret_cast<const pbn_plan_header*>(a.blob);
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t n = H->n, npass = H->n_passes, njobs = H->n_jobs;
   const uint32_t fill = H->fill_steps, sd = H->state_dwords, zero_pos = H->zero_pos;
+  FnFmt fm;
+  fm.units = H->fn_units;
+  fm.jshift = H->fn_jshift;
+  fm.hoff = H->fn_hoff;
+  fm.zp2 = zero_pos | (zero_pos << 16);
+  const uint32_t zp2 = fm.zp2;
   const uint32_t sdp = (sd + 3u) & ~3u;   // state buffer, padded to 16 bytes
   const unsigned long long* Q = reinterpret_cast<const unsigned long long*>(a.blob + H->q_off);
   const uint32_t* o2p = reinterpret_cast<const uint32_t*>(a.blob + H->o2p_off);
@@ -263,26 +391,28 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
       sbuf1[8u * w + i] = 0;
     }
   }
-  // output position of this lane's slot in pass p: table slots own words,
-  // FN slots own bytes after them
-  const uint32_t ntab = H->n_table, fnb = H->fn_base;
 
-  Regs cached[NREG > 0 ? NREG : 1];
+  Regs cached[NR];
+  NegThr nthr[NR];
   if constexpr (NREG > 0) {
 #pragma unroll
     for (int p = 0; p < NREG; ++p) {
       if (uint32_t(p) < npass) {
-        load_slot<PM, UM>(cached[p], img, uint32_t(p) * 64u + lane);
+        load_slot<PM, UM, MIXED>(cached[p], img, uint32_t(p) * 64u + lane, fm);
       } else {
-        // no such pass (the slot-record region ends before it): behave as a padded lane
+        // no such pass: a one-predictor lane whose parents are all the zero
+        // position and whose table is 0, writing 0 into the zero word
         cached[p] = Regs{};
         cached[p].base = H->dummy_fn;
         cached[p].draw = 1u << 24;
         cached[p].thr0 = cached[p].thr1 = cached[p].thr2 = 0xFFFFFFFFu;
+        cached[p].spos = zero_pos;
+#pragma unroll
+        for (int k = 0; k < XW; ++k) cached[p].pw[k] = zp2;
       }
+      nthr[p] = neg_thresholds(cached[p].thr0, cached[p].thr1, cached[p].thr2, cached[p].draw >> 24);
     }
   }
-  wave_sync();
 
   // targets: lane k holds pair k; lane t counts target t
   const uint32_t npairs = a.tg->npairs, ntg = a.tg->ntargets;
@@ -294,9 +424,40 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
     const unsigned long long mism = __ballot(b != my_val);   // lanes past npairs read the zero word, expect 0
     return (mism & my_mask) == 0ull;
   };
+  // ballot form of target t (lane t): bits that must be 1 (want) among the bits
+  // it looks at (care), per pass (bit = slot = state byte of an FN-only plan);
+  // a pair on any other byte is never 1
+  uint32_t want_lo[NR], want_hi[NR], care_lo[NR], care_hi[NR];
+  bool never = false;
+#pragma unroll
+  for (int p = 0; p < NR; ++p) want_lo[p] = want_hi[p] = care_lo[p] = care_hi[p] = 0u;
+  if constexpr (kBallotTargets) {
+    const uint32_t nslots = H->n_slots;
+    for (unsigned long long m = my_mask; m; m &= m - 1ull) {
+      const uint32_t k = uint32_t(__builtin_ctzll(m));
+      const uint32_t pos = a.tg->pos[k], val = a.tg->val[k];
+      const uint32_t bit = 1u << (pos & 31u), hi = (pos >> 5) & 1u;
+      bool placed = false;
+#pragma unroll
+      for (int p = 0; p < NR; ++p) {
+        if (pos < nslots && (pos >> 6) == uint32_t(p)) {
+          care_lo[p] |= hi ? 0u : bit;
+          care_hi[p] |= hi ? bit : 0u;
+          if (val) {
+            want_lo[p] |= hi ? 0u : bit;
+            want_hi[p] |= hi ? bit : 0u;
+          }
+          placed = true;
+        }
+      }
+      if (!placed && val) never = true;
+    }
+  }
+  wave_sync();
 
   // fixed Philox job of this lane when one fill covers several steps
   const bool small_jobs = njobs <= 64u;
+  const uint32_t bsteps = small_jobs ? min(fill, 32u) : 1u;   // steps per fill
   uint32_t my_s = 0, my_c2 = 0, my_c3 = PBN_STREAM_PERT;
   if (small_jobs) {
     const uint32_t j = lane % njobs;
@@ -307,14 +468,39 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   uint32_t stride0 = 1;
   while (stride0 * 64u < n) stride0 *= 64u;
   const unsigned long long Qn = Q[n];
+  const uint32_t qn_lo = uint32_t(Qn), qn_hi = uint32_t(Qn >> 32);
 
+  // Target indicator z of each step is shifted into zacc (newest in bit 0);
+  // at most every 32 steps the bits are folded into the counters: hits count
+  // steps t >= count_from (state s(t+1)), changes count steps t >= count_from + 1
+  // against the previous step's z (zlast: z before the oldest bit).
   uint32_t cur = 0;
-  bool zp = target_z(reinterpret_cast<const uint8_t*>(sbuf0));
+  uint32_t zlast = target_z(reinterpret_cast<const uint8_t*>(sbuf0)) ? 1u : 0u;
+  uint32_t zacc = 0, nacc = 0;
   uint32_t hits = 0, n01 = 0, n10 = 0;
   uint32_t t = a.step0;
+  uint32_t tacc = t;   // step of the oldest accumulated bit
+  auto low_bits = [](long long m) -> uint32_t { return m <= 0 ? 0u : m >= 32 ? 0xFFFFFFFFu : (1u << m) - 1u; };
+  auto fold = [&]() {
+    if (nacc == 0u) return;
+    const long long newest = (long long)tacc + nacc - 1;   // step of bit 0
+    const uint32_t keep = low_bits(nacc);
+    const uint32_t hm = low_bits(newest - (long long)a.count_from + 1) & keep;
+    const uint32_t tm = low_bits(newest - (long long)a.count_from) & keep;
+    const uint32_t prev = (zacc >> 1) | (zlast << (nacc - 1u));
+    hits += __popc(zacc & hm);
+    n01 += __popc(~prev & zacc & tm);
+    n10 += __popc(prev & ~zacc & tm);
+    zlast = zacc & 1u;
+    zacc = 0u;
+    tacc += nacc;
+    nacc = 0u;
+  };
+
   const uint32_t tend = a.step0 + a.nsteps;
   while (t < tend) {
-    const uint32_t scount = small_jobs ? min(fill, tend - t) : 1u;
+    const uint32_t scount = small_jobs ? min(bsteps, tend - t) : 1u;
+    if (nacc + scount > 32u) fold();
     if (small_jobs) {
       if (lane < scount * njobs) ring[lane] = philox(traj, t + my_s, my_c2, my_c3, k0, k1);
     } else {
@@ -324,12 +510,14 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
     wave_sync();
     for (uint32_t s = 0; s < scount; ++s, ++t) {
       const uint8_t* rs = reinterpret_cast<const uint8_t*>(ring + s * njobs);
-      const uint4 pr = *reinterpret_cast<const uint4*>(rs);
-      unsigned long long u = (static_cast<unsigned long long>(uniform(pr.y)) << 32) | uniform(pr.x);
-      uint32_t* cs = cur ? sbuf1 : sbuf0;
-      if (u >= Qn) {
-        // perturbation-only step: walk the skip chain over all n original nodes
-        uint8_t* csb = reinterpret_cast<uint8_t*>(cs);
+      const uint2 pr = *reinterpret_cast<const uint2*>(rs);
+      const uint32_t ulo = uniform(pr.x), uhi = uniform(pr.y);
+      uint8_t* csb = reinterpret_cast<uint8_t*>(cur ? sbuf1 : sbuf0);
+      bool z = false;
+      if (uhi > qn_hi || (uhi == qn_hi && ulo >= qn_lo)) {
+        // u >= Q[n]: perturbation-only step; walk the skip chain over all n
+        // original nodes, flipping kept nodes in place
+        unsigned long long u = (static_cast<unsigned long long>(uhi) << 32) | ulo;
         uint32_t j0 = 0;
         for (;;) {
           uint32_t base = 0;
@@ -350,35 +538,42 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
           u = (static_cast<unsigned long long>(uniform(x.y)) << 32) | uniform(x.x);
         }
         wave_sync();
+        z = target_z(csb);
       } else {
-        const uint8_t* csb = reinterpret_cast<const uint8_t*>(cs);
-        uint32_t* ns = cur ? sbuf0 : sbuf1;
+        uint8_t* nsb = reinterpret_cast<uint8_t*>(cur ? sbuf0 : sbuf1);
         if constexpr (NREG > 0) {
+          // every pass reads s(t) before any writes s(t+1)
+          uint32_t out[NREG];
 #pragma unroll
-          for (int p = 0; p < NREG; ++p) {
-            if (cached[p].info & PBN_SLOT_VALID)
-              store_slot(ns, uint32_t(p) * 64u + lane, ntab, fnb, eval_slot<PM, UM>(cached[p], img, csb, rs));
+          for (int p = 0; p < NREG; ++p) out[p] = eval_slot<PM, UM, MIXED>(cached[p], &nthr[p], img, csb, rs, fm);
+#pragma unroll
+          for (int p = 0; p < NREG; ++p) store_slot<UM>(nsb, cached[p].info, cached[p].spos, out[p]);
+          if constexpr (kBallotTargets) {
+            uint32_t mism = 0u;
+#pragma unroll
+            for (int p = 0; p < NREG; ++p) {
+              const unsigned long long b = __ballot(out[p] != 0u);
+              mism |= masked_xor(uint32_t(b), care_lo[p], want_lo[p]) | masked_xor(uint32_t(b >> 32), care_hi[p], want_hi[p]);
+            }
+            z = !never && mism == 0u;
           }
         } else {
           for (uint32_t p = 0; p < npass; ++p) {
             Regs r;
-            load_slot<PM, UM>(r, img, p * 64u + lane);
-            if (r.info & PBN_SLOT_VALID) store_slot(ns, p * 64u + lane, ntab, fnb, eval_slot<PM, UM>(r, img, csb, rs));
+            load_slot<PM, UM, MIXED>(r, img, p * 64u + lane, fm);
+            store_slot<UM>(nsb, r.info, r.spos, eval_slot<PM, UM, MIXED>(r, nullptr, img, csb, rs, fm));
           }
         }
         cur ^= 1u;
         wave_sync();
+        if constexpr (!kBallotTargets) z = target_z(nsb);
       }
-      const bool z = target_z(reinterpret_cast<const uint8_t*>(cur ? sbuf1 : sbuf0));
-      if (t >= a.count_from) hits += z;
-      if (uint64_t(t) >= uint64_t(a.count_from) + 1u) {
-        n01 += (!zp && z);
-        n10 += (zp && !z);
-      }
-      zp = z;
+      zacc = zacc + zacc + (z ? 1u : 0u);
+      ++nacc;
     }
     wave_sync();
   }
+  fold();
 
   if (lane < ntg) {
     unsigned long long* c = a.counts + (size_t(lane) * a.ntraj + a.tl) * 3u;
@@ -434,7 +629,7 @@ __global__ void __launch_bounds__(1024) k_simulate(SimParams a) {
   t.state = a.state;
   t.counts = a.counts;
   t.tg = &a.tg;
-  run_traj<PM, UM, NREG>(t);
+  run_traj<PM, UM, NREG, false>(t);
 }
 
 // ---------------------------------------------------------------- batches
@@ -486,7 +681,7 @@ __global__ void __launch_bounds__(1024) k_batch(BatchParams a) {
       t.state = it.d_state;
       t.counts = reinterpret_cast<unsigned long long*>(it.d_counts);
       t.tg = it.d_targets;
-      run_traj<PM, UM, 0>(t);
+      run_traj<PM, UM, 0, PM == 7>(t);
     }
   }
 }
@@ -562,6 +757,14 @@ uint32_t grid_for(size_t work, uint32_t block) {
 
 constexpr uint32_t kLdsMax = 160u * 1024u;
 
+// LDS of one wave: the two state buffers and the Philox ring (one fill:
+// min(fill, 32) steps of n_jobs calls when the calls of a step fit in a wave,
+// else one step).
+uint32_t wave_lds_bytes(const pbn_plan* plan) {
+  const uint32_t ring = plan->n_jobs <= 64 ? std::min(plan->fill_steps, 32u) * plan->n_jobs : plan->n_jobs;
+  return 8u * ((plan->state_dwords + 3u) & ~3u) + 16u * ring;
+}
+
 template <bool IMG_LDS, int PM, int UM, int NREG>
 pbn_status launch_sim(const SimParams& p, uint32_t blocks, uint32_t lds, hipStream_t stream) {
   auto* fn = k_simulate<IMG_LDS, PM, UM, NREG>;
@@ -579,7 +782,8 @@ pbn_status launch_sim(const SimParams& p, uint32_t blocks, uint32_t lds, hipStre
 // Instantiation choice: the smallest gather widths that cover the plan.
 template <bool IMG_LDS, int PM, int UM>
 pbn_status dispatch_nreg(const SimParams& p, uint32_t npass, uint32_t blocks, uint32_t lds, hipStream_t s) {
-  if (npass <= 2) return launch_sim<IMG_LDS, PM, UM, 2>(p, blocks, lds, s);
+  if (npass == 1) return launch_sim<IMG_LDS, PM, UM, 1>(p, blocks, lds, s);
+  if (npass == 2) return launch_sim<IMG_LDS, PM, UM, 2>(p, blocks, lds, s);
   return launch_sim<IMG_LDS, PM, UM, 0>(p, blocks, lds, s);
 }
 
@@ -613,8 +817,7 @@ pbn_status simulate_common(bool plain, const pbn_plan* plan, const void* d_plan,
   if (plain && plan->has_table) return fail(PBN_EINVAL, "the plain kernel needs a plan without table slots");
   if (ntraj == 0 || nsteps == 0) return PBN_OK;
 
-  const uint32_t ring_entries = plan->n_jobs <= 64 ? plan->fill_steps * plan->n_jobs : plan->n_jobs;
-  const uint32_t wave_bytes = 8u * ((plan->state_dwords + 3u) & ~3u) + 16u * ring_entries;
+  const uint32_t wave_bytes = wave_lds_bytes(plan);
   const bool img_lds = plan->info.image_in_lds != 0;
   const uint32_t img = img_lds ? ((plan->info.image_bytes + 15u) & ~15u) : 0u;
   uint32_t wpb = launch && launch->waves_per_block ? launch->waves_per_block : 4u;
@@ -641,6 +844,8 @@ pbn_status simulate_common(bool plain, const pbn_plan* plan, const void* d_plan,
   const uint32_t pmax = plan->info.max_fn_parents, umax = plan->info.max_union_bits;
   const uint32_t npass = plan->info.n_passes;
   if (pmax > 7 || umax > 16) return fail(PBN_ELDS, "plan exceeds the kernel's gather widths");
+  const uint32_t units = reinterpret_cast<const pbn_plan_header*>(plan->blob.data())->fn_units;
+  if (units != (pmax > 5 ? 2u : 1u)) return fail(PBN_EINVAL, "plan FN record format does not match its parent count");
   return img_lds ? dispatch_pm<true>(p, pmax, umax, npass, blocks, lds, s)
                  : dispatch_pm<false>(p, pmax, umax, npass, blocks, lds, s);
 }
@@ -707,8 +912,7 @@ pbn_status batch_shape(const pbn_plan* const* plans, uint32_t nitems, BatchShape
       return fail(PBN_ELDS, "plan exceeds the kernel's gather widths");
     if (p->info.max_fn_parents > 5) sh.pm = 7;
     sh.um = std::max(sh.um, p->info.max_union_bits);
-    const uint32_t ring = p->n_jobs <= 64 ? p->fill_steps * p->n_jobs : p->n_jobs;
-    sh.wave_bytes = std::max(sh.wave_bytes, 8u * ((p->state_dwords + 3u) & ~3u) + 16u * ring);
+    sh.wave_bytes = std::max(sh.wave_bytes, wave_lds_bytes(p));
   }
   sh.um = sh.um == 0 ? 0 : sh.um <= 8 ? 8 : 16;
   return PBN_OK;

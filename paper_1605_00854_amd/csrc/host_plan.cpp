@@ -302,13 +302,16 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
                     (unsigned long long)table_entries(s.members), o.max_table_entries);
     }
   }
-  // order: table slots first (by union size, descending), then FN slots
-  // (multi-predictor first, then by parent count, descending)
+  // order: table slots first (by union size, descending), then FN slots:
+  // multi-predictor nodes by selection rank (neighbouring lanes then read
+  // neighbouring words of a step's drawn numbers), then one-predictor nodes
+  // by parent count, descending
   std::stable_sort(slots.begin(), slots.end(), [&](const Slot& a, const Slot& b) {
     if (a.table != b.table) return a.table;
     if (!a.table) {
       const bool ma = g.nfn(a.members[0]) > 1, mb = g.nfn(b.members[0]) > 1;
       if (ma != mb) return ma;
+      if (ma) return g.rank[a.members[0]] < g.rank[b.members[0]];
       return max_phi(a.members[0]) > max_phi(b.members[0]);
     }
     return a.uni.size() > b.uni.size();
@@ -318,14 +321,16 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   if (ns == 0) return fail(PBN_EINVAL, "plan has no nodes");
   const uint32_t npass = (ns + PBN_WAVE - 1) / PBN_WAVE;
   // state bytes: table slot s (s < n_table) owns the word at 4 s (member k at
-  // byte k); FN slot s owns one byte at 4 n_table + (s - n_table); padded lanes
-  // of the last pass own the bytes after it; then the zero word read by unused
-  // parent entries
+  // byte k); FN slot s owns one byte at 4 n_table + (s - n_table); then the
+  // zero word read by unused parent entries; then one byte per padded lane of
+  // the last pass (written with zeros, never read).  Every byte a lookup reads
+  // lies below zero_pos + 4, so small states use distinct LDS banks.
   const uint32_t ntab = uint32_t(std::count_if(slots.begin(), slots.end(), [](const Slot& s) { return s.table; }));
   const uint32_t fn_pos0 = 4 * ntab;
-  const uint32_t fn_end = fn_pos0 + (npass * PBN_WAVE - ntab);
+  const uint32_t fn_end = fn_pos0 + (ns - ntab);
   const uint32_t zero_pos = (fn_end + 3) & ~3u;
-  const uint32_t state_words = (zero_pos + 4 + 31) / 32;
+  const uint32_t pad_pos0 = zero_pos + 4;
+  const uint32_t state_words = (pad_pos0 + (npass * PBN_WAVE - ns) + 31) / 32;
   if (32ull * state_words > 65535) return fail(PBN_ELDS, "too many slots (%u) for 16-bit state positions", ns);
   auto slot_pos = [&](uint32_t s, uint32_t k) { return s < ntab ? 4 * s + k : fn_pos0 + (s - ntab); };
 
@@ -354,31 +359,78 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   };
 
   // ---- image layout
+  // FN records: 16 bytes when every FN slot reads at most 5 parents (one
+  // 16-byte unit: 5 positions and a 32-entry table), else 32 bytes (two units:
+  // 7 positions, then a 128-entry table).  An image that goes to LDS puts the
+  // units in 128-byte rows (one row spans all LDS banks): slot s always uses
+  // the unit at 16 (s mod 8) of its rows, so the 8 lanes a 16-byte read serves
+  // at once never share a bank; a group of 8 slots takes units x (largest l
+  // among its FN slots) rows, predictor j of slot s sits 128 units j bytes
+  // after predictor 0, a record's second unit 128 bytes after its first.  An
+  // image read from global memory packs records densely instead (fewer cache
+  // lines): predictor j at 16 units j, second unit at +16.
   const size_t slot_bytes = size_t(npass) * PBN_WAVE * 16;
-  size_t nchoice = 0, nfnrec = 0, tab_bytes = 0;
+  size_t nchoice = 0, tab_bytes = 0, nfnrec = 0;
+  uint32_t fn_phi = 0;
   for (const auto& s : slots) {
     for (uint32_t v : s.members)
       if (g.nfn(v) > 1) ++nchoice;
-    if (s.table)
+    if (s.table) {
       tab_bytes += align16(32 + size_t(table_entries(s.members)));
-    else
+    } else {
+      fn_phi = std::max(fn_phi, max_phi(s.members[0]));
       nfnrec += g.nfn(s.members[0]);
+    }
   }
-  ++nfnrec;   // the dummy record read by padded lanes
+  ++nchoice;  // the default choice record of one-predictor FN slots and padded lanes
+  const uint32_t units = fn_phi <= 5 ? 1u : 2u;
+  const uint32_t ngroups = npass * PBN_WAVE / 8;
+  std::vector<uint32_t> row0(ngroups, 0);
+  uint32_t rows = units;   // the dummy records (all 8 units) come first
+  for (uint32_t gi = 0; gi < ngroups; ++gi) {
+    uint32_t lmax = 0;
+    for (uint32_t s = 8 * gi; s < std::min(ns, 8 * gi + 8); ++s)
+      if (!slots[s].table) lmax = std::max(lmax, g.nfn(slots[s].members[0]));
+    row0[gi] = rows;
+    rows += units * lmax;
+  }
   const size_t choice_base = slot_bytes;
-  const size_t fn_base = choice_base + 16 * nchoice;
-  const size_t tab_base = fn_base + 32 * nfnrec;
+  const size_t fn_base = (choice_base + 16 * nchoice + 127) & ~size_t(127);
+  const size_t swz_bytes = fn_base + 128 * size_t(rows) + tab_bytes;
+  const bool swz = swz_bytes <= o.lds_budget_bytes;
+  const size_t tab_base = fn_base + (swz ? 128 * size_t(rows) : 16 * size_t(units) * (nfnrec + 1));
   const size_t image_bytes = tab_base + tab_bytes;
   if (image_bytes > 0xFFFFFFF0ull) return fail(PBN_ELDS, "plan image too large");
+  const uint32_t jstride = swz ? 128 * units : 16 * units, hoff = swz ? 128 : 16;
+  std::vector<size_t> rec0(ns, 0);   // dense layout: record of predictor 0
+  for (size_t s = 0, cur = fn_base + 16 * units; s < ns; ++s)
+    if (!slots[s].table) {
+      rec0[s] = cur;
+      cur += 16 * size_t(units) * g.nfn(slots[s].members[0]);
+    }
+  auto fn_rec = [&](uint32_t s, uint32_t j) {
+    return swz ? fn_base + 128 * size_t(row0[s / 8] + j * units) + 16 * (s % 8) : rec0[s] + size_t(jstride) * j;
+  };
+  auto dummy_of = [&](size_t s) { return swz ? fn_base + 16 * (s % 8) : fn_base; };
 
   std::vector<uint8_t> img(image_bytes, 0);
   auto put32 = [&](size_t off, uint32_t v) { std::memcpy(&img[off], &v, 4); };
   auto put16 = [&](size_t off, uint16_t v) { std::memcpy(&img[off], &v, 2); };
-  // dummy FN record first: every parent is the zero position, truth table 0
+  // dummy FN records first (one per unit position of a row): every parent is
+  // the zero position, truth table 0
   const size_t dummy_fn = fn_base;
-  for (uint32_t b = 0; b < 8; ++b) put16(dummy_fn + 2 * b, uint16_t(zero_pos));
-  for (size_t s = ns; s < size_t(npass) * PBN_WAVE; ++s) put32(s * 16 + 4, uint32_t(dummy_fn));
-  size_t choice_cur = choice_base, fn_cur = fn_base + 32, tab_cur = tab_base;
+  for (uint32_t q = 0; q < (swz ? 8u : 1u); ++q)
+    for (uint32_t b = 0; b < (units == 1 ? 6u : 8u); ++b) put16(dummy_fn + 16 * q + 2 * b, uint16_t(zero_pos));
+  // default choice record first: ring offset 0, l = 1, no thresholds (selects predictor 0)
+  const size_t default_choice = choice_base;
+  put32(default_choice, 1u << 24);
+  for (int m = 0; m < 3; ++m) put32(default_choice + 4 + 4 * m, 0xFFFFFFFFu);
+  for (size_t s = ns; s < size_t(npass) * PBN_WAVE; ++s) {
+    put32(s * 16 + 4, uint32_t(dummy_of(s)));
+    put32(s * 16 + 8, uint32_t(default_choice));
+    put32(s * 16 + 12, uint32_t(pad_pos0 + (s - ns)));
+  }
+  size_t choice_cur = choice_base + 16, tab_cur = tab_base;
   std::vector<pbn_pass_info> passes(npass, pbn_pass_info{0, 0, 0, 0});
   uint32_t max_fn_parents = 0, max_union = 0, multi_groups = 0;
   for (uint32_t s = 0; s < ns; ++s) {
@@ -401,15 +453,18 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
       const uint32_t v = sl.members[0];
       const uint32_t pm = max_phi(v);
       info |= pm << 6;
-      y = uint32_t(fn_cur);
+      y = uint32_t(fn_rec(s, 0));
+      w = fn_pos0 + (s - ntab);   // the slot's state byte
       for (uint32_t f = g.fn_off[v]; f < g.fn_off[v + 1]; ++f) {
+        const size_t r = fn_rec(s, f - g.fn_off[v]);
         const uint32_t k = g.nparents(f);
-        for (uint32_t b = 0; b < 8; ++b)
-          put16(fn_cur + 2 * b, uint16_t(b < k ? plan.node_pos[g.parents[g.par_off[f] + b]] : zero_pos));
+        const uint32_t npos = units == 1 ? 6u : 8u;   // position slots (unused: the zero position)
+        for (uint32_t b = 0; b < npos; ++b)
+          put16(r + 2 * b, uint16_t(b < k ? plan.node_pos[g.parents[g.par_off[f] + b]] : zero_pos));
+        const size_t tt = units == 1 ? r + 12 : r + hoff;   // truth table: bit x = f(x)
         const uint32_t ebits = 1u << k;
         for (uint32_t x = 0; x < ebits && x < 128; ++x)
-          if (g.eval(f, x)) img[fn_cur + 16 + (x >> 3)] |= uint8_t(1u << (x & 7));
-        fn_cur += 32;
+          if (g.eval(f, x)) img[tt + (x >> 3)] |= uint8_t(1u << (x & 7));
       }
       pi.flags |= PBN_PASS_FN;
       pi.pmax = std::max(pi.pmax, pm);
@@ -461,7 +516,7 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
     if (nmulti) pi.flags |= PBN_PASS_MULTI;
     put32(rec + 0, info);
     put32(rec + 4, y);
-    put32(rec + 8, nmulti ? uint32_t(first_choice) : 0u);
+    put32(rec + 8, nmulti ? uint32_t(first_choice) : sl.table ? 0u : uint32_t(default_choice));
     put32(rec + 12, w);
   }
 
@@ -503,6 +558,9 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   h.image_in_lds = image_bytes <= o.lds_budget_bytes ? 1u : 0u;
   h.has_table = max_union > 0 || std::any_of(slots.begin(), slots.end(), [](const Slot& s) { return s.table; });
   h.dummy_fn = uint32_t(dummy_fn);
+  h.fn_units = units;
+  h.fn_jshift = uint32_t(__builtin_ctz(jstride));
+  h.fn_hoff = hoff;
   std::memcpy(&plan.blob[0], &h, sizeof h);
   std::memcpy(&plan.blob[pass_off], passes.data(), sizeof(pbn_pass_info) * npass);
   std::memcpy(&plan.blob[q_off], g.Q.data(), 8 * size_t(n + 1));

@@ -9,9 +9,10 @@
 // lane s % 64 in pass s / 64; table slots come first.  The trajectory state
 // lives in LDS as one byte per node value (0/1): table slot s (s < n_table)
 // owns the word at byte 4 s (member k at byte k), FN slot s owns the byte at
-// fn_base + (s - n_table); padded lanes own the bytes after the last FN slot
-// and only ever hold zeros; the zero word read by unused parent entries follows
-// at zero_pos.  Packed states in HBM use bit b for state byte b.
+// fn_base + (s - n_table); the zero word read by unused parent entries
+// follows at zero_pos (the first 4-aligned byte after the last FN slot);
+// padded lanes own bytes after it that only ever hold zeros.  Packed states in
+// HBM use bit b for state byte b.
 #pragma once
 #include <stdint.h>
 
@@ -62,7 +63,10 @@ struct pbn_plan_header {
   uint32_t dummy_fn;       // image offset of an all-zero-position FN record (padded lanes)
   uint32_t n_table;        // table slots (slots 0 .. n_table - 1)
   uint32_t fn_base;        // byte position of the first FN slot (4 n_table)
-  uint32_t pad[6];
+  uint32_t fn_units;       // 16-byte units per FN record: 1 (<= 5 parents) or 2 (<= 7)
+  uint32_t fn_jshift;      // log2 of the bytes from an FN slot's record of predictor j to j + 1
+  uint32_t fn_hoff;        // bytes from a two-unit record's first unit to its second
+  uint32_t pad[3];
 };
 
 struct pbn_pass_info {
@@ -76,19 +80,33 @@ struct pbn_pass_info {
 //   [0, 16 * 64 * n_passes)  slot records (uint4 each)
 //   choice records (uint4):   x = draw byte offset within a step's ring segment
 //                                 | (l << 24);  y, z, w = thresholds CUM[0..2]
-//                                 (unused = 0xFFFFFFFF)
-//   fn records (32 bytes):    parent byte positions as 8 uint16 (unused = zero
-//                             position), then the 128-bit truth table
+//                                 (unused = 0xFFFFFFFF); the first one is the
+//                                 default record {0 | 1 << 24, unused x 3}
+//   fn records (from a 128-byte aligned offset): fn_units 16-byte units each.
+//     one unit  (every FN slot <= 5 parents): parent byte positions as 6
+//               uint16 (unused = zero position), then the 32-bit truth table
+//     two units (<= 7 parents): 8 uint16 positions; the second unit, fn_hoff
+//               bytes later, holds the 128-bit truth table
+//     Predictor j of a slot sits j << fn_jshift bytes after predictor 0.  An
+//     image staged in LDS keeps slot s in unit 16 (s mod 8) of 128-byte rows
+//     (stride 128 fn_units, fn_hoff = 128: lanes of one 16-byte read
+//     hit distinct banks); otherwise records are packed (16 fn_units, 16).
+//     The dummy records (all positions the zero word, table 0) come first.
 //   tables:                   TABLE slot: 16 uint16 union-parent positions
 //                             (unused = zero position), then the byte table
 //                             T[c * 2^nu + x]
-// Padded lanes (slot index >= n_slots) have info = 0 and y = dummy_fn, an FN
-// record whose parents are all the zero position and whose truth table is 0.
+// Padded lanes (slot index >= n_slots) have info = 0, y = a dummy FN record,
+// z = the default choice record and w = a state byte of their own above the
+// zero word: they evaluate to 0 and write only that byte.
 // Slot record (uint4):
 //   x = info word (PBN_SLOT_*)
 //   y = FN: image offset of the fn record of predictor 0 (predictor j at +32 j)
 //       TABLE: image offset of the union-parent list (table follows at +32)
-//   z = image offset of the first choice record (multi-predictor members, in
-//       member order), or 0
+//   z = FN: image offset of the slot's choice record (one-predictor nodes and
+//       padded lanes: the default record {ring offset 0, l = 1, no thresholds},
+//       the first choice record of the image);
+//       TABLE: offset of the first choice record of its multi-predictor members
+//       (in member order), or 0
 //   w = TABLE: mixed-radix weights of the multi-predictor members, one byte
-//       each (first member most significant digit); FN: 0
+//       each (first member most significant digit); FN / padded lane: the
+//       state byte the slot writes

@@ -207,3 +207,74 @@ def test_two_state_sample_size_reduces_to_binomial():
     z = st.norm.ppf(0.975)
     assert abs(got["n_required"] - pi * (1 - pi) * (z / r) ** 2) < 1e-6 * got["n_required"]
     assert np.isnan(got["half_width"])
+
+
+HEADER_FIELDS = ("magic version blob_bytes plan_id n n_kept n_slots n_passes state_dwords state_words n_jobs "
+                 "fill_steps image_bytes image_off q_off o2p_off p2o_off blk_off pass_off zero_pos max_pmax "
+                 "image_in_lds has_table dummy_fn n_table fn_base fn_units fn_jshift fn_hoff").split()
+
+
+def _header(blob):
+    words = np.frombuffer(blob[:4 * len(HEADER_FIELDS)].tobytes(), dtype="<u4")
+    return dict(zip(HEADER_FIELDS, (int(w) for w in words)))
+
+
+@pytest.mark.parametrize("budget", [65536, 0])
+@pytest.mark.parametrize("which", ["dense5", "wide7"])
+def test_fn_records_decode_to_the_network(which, budget):
+    """Plan image format: every FN slot's records hold the byte positions of
+    its parents and its truth table -- for an image that goes to LDS in 16-byte
+    units of 128-byte rows (lane s at unit s % 8, predictors 128 x units bytes
+    apart), else packed densely; slot records carry the slot's state byte; the
+    zero word follows the last FN byte; padded lanes write bytes of their own
+    above it."""
+    if which == "dense5":
+        net = ps.medium_c2(n=90, p=1e-3, seed=11)
+    else:
+        rng = np.random.default_rng(12)
+        fns = []
+        for i in range(70):
+            l = int(rng.integers(1, 4))
+            probs = rng.dirichlet(np.ones(l))
+            ks = [int(rng.integers(1, 8)) for _ in range(l)]
+            fns.append([(probs[j], list(rng.choice(70, size=ks[j], replace=False)), rng.integers(0, 2, 1 << ks[j]))
+                        for j in range(l)])
+        net = ps.assemble(70, 1e-3, fns)
+    plan = api.Plan(net, interest=[0, 1], reduce=1, group=0, lds_budget_bytes=budget)
+    blob = plan.blob()
+    h = _header(blob)
+    units = h["fn_units"]
+    assert units == (1 if which == "dense5" else 2)
+    swz = budget > 0
+    assert h["image_in_lds"] == int(swz)
+    jstride = 1 << h["fn_jshift"]
+    assert (jstride, h["fn_hoff"]) == ((128 * units, 128) if swz else (16 * units, 16))
+    img = blob[h["image_off"]:h["image_off"] + h["image_bytes"]]
+    rec = np.frombuffer(img[:16 * 64 * h["n_passes"]].tobytes(), dtype="<u4").reshape(-1, 4)
+    pos = plan.node_pos()
+    slot, is_table = plan.slots()
+    ns, ntab = h["n_slots"], int(is_table.sum())
+    assert ntab == 0
+    assert h["zero_pos"] == (ns + 3) // 4 * 4
+    zp = h["zero_pos"]
+    u16 = lambda off: int(img[off]) | int(img[off + 1]) << 8
+    for s in range(64 * h["n_passes"]):
+        info, y, z, w = (int(v) for v in rec[s])
+        if swz:
+            assert y % 128 == 16 * (s % 8)                 # bank-swizzled unit
+        if s >= ns:
+            assert info == 0 and y == h["dummy_fn"] + (16 * (s % 8) if swz else 0)
+            assert zp + 4 <= w < 32 * h["state_words"]
+            continue
+        (v,) = np.nonzero(slot == s)[0]
+        assert w == pos[v]
+        for j, f in enumerate(range(net["fn_off"][v], net["fn_off"][v + 1])):
+            r = y + jstride * j
+            pars = net["parents"][net["par_off"][f]:net["par_off"][f + 1]]
+            npos = 6 if units == 1 else 8
+            got = [u16(r + 2 * b) for b in range(npos)]
+            assert got == [int(pos[q]) for q in pars] + [zp] * (npos - len(pars))
+            tt = r + 12 if units == 1 else r + h["fn_hoff"]
+            bits = [(int(img[tt + (x >> 3)]) >> (x & 7)) & 1 for x in range(1 << len(pars))]
+            want = [int(net["tt"][net["tt_off"][f] + x // 64]) >> (x % 64) & 1 for x in range(1 << len(pars))]
+            assert bits == want
