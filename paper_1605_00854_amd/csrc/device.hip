@@ -77,6 +77,13 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 __device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ unsigned long long uniform64(unsigned long long x) {
+  return (static_cast<unsigned long long>(uniform(uint32_t(x >> 32))) << 32) | uniform(uint32_t(x));
+}
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  return reinterpret_cast<T*>(uniform64(reinterpret_cast<unsigned long long>(p)));
+}
 
 // (b ^ want) & care in one VALU instruction (three-input bitwise op); the
 // table is symmetric in its first and third inputs.
@@ -197,7 +204,8 @@ __device__ __forceinline__ FnRec<Shape<PM, UM>::PW, Shape<PM, UM>::TTW> load_fn(
                                                                                uint32_t j, const FnFmt& fm) {
   constexpr int TTW = Shape<PM, UM>::TTW;
   FnRec<Shape<PM, UM>::PW, TTW> r;
-  const uint8_t* rp = img + base + (j << fm.jshift);
+  // records and units are 16-byte aligned: one 16-byte read per unit
+  const uint8_t* rp = static_cast<const uint8_t*>(__builtin_assume_aligned(img + base + (j << fm.jshift), 16));
   const uint4 a = *reinterpret_cast<const uint4*>(rp);
   r.pw[0] = a.x;
   r.pw[1] = a.y;
@@ -600,7 +608,7 @@ template <bool IMG_LDS, int PM, int UM, int NREG>
 __global__ void __launch_bounds__(1024) k_simulate(SimParams a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   const pbn_plan_header* H = reinterpret_cast<const pbn_plan_header*>(a.blob);
-  const uint32_t wave = threadIdx.x >> 6;
+  const uint32_t wave = uniform(threadIdx.x >> 6);   // wave-uniform: keeps per-trajectory data scalar
   const uint32_t img_bytes = H->image_bytes;
   const uint8_t* gimg = a.blob + H->image_off;
   uint32_t img_lds = 0;
@@ -651,33 +659,35 @@ struct BatchParams {
 };
 
 template <int PM, int UM>
-__global__ void __launch_bounds__(1024) k_batch(BatchParams a) {
+__global__ void __launch_bounds__(1024) k_batch(BatchParams a, const pbn_work* __restrict__ items) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   uint32_t& claimed = *reinterpret_cast<uint32_t*>(smem);   // first 16 bytes: the claimed task
-  const uint32_t wave = threadIdx.x >> 6;
+  const uint32_t wave = uniform(threadIdx.x >> 6);   // wave-uniform: keeps per-trajectory data scalar
   const uint32_t wstep0 = a.ctl->step0, nsteps = a.ctl->nsteps;
   for (;;) {
     if (threadIdx.x == 0) claimed = atomicAdd(&a.ctl->next_task, 1u);
     __syncthreads();
-    const uint32_t task = claimed;
+    const uint32_t task = uniform(claimed);   // the same for the workgroup: scalar loads of the task's item
     __syncthreads();
     if (task >= a.ntasks) return;        // uniform across the workgroup
-    const pbn_work& it = a.items[a.tasks[task]];
-    const uint32_t tl = a.task_first[task] + wave;
-    if (tl < it.ntraj) {
+    // the task's work item, read into wave-uniform values (scalar registers)
+    const pbn_work& it = items[uniform(a.tasks[task])];
+    const uint32_t tl = uniform(a.task_first[task]) + wave;
+    const uint32_t ntraj = uniform(it.ntraj);
+    if (tl < ntraj) {
       const uint8_t* blob = static_cast<const uint8_t*>(it.d_plan);
       const pbn_plan_header* H = reinterpret_cast<const pbn_plan_header*>(blob);
       TrajArgs t;
       t.blob = blob;
       t.img = blob + H->image_off;
       t.wb = smem + 16u + wave * a.wave_bytes;
-      t.seed = it.seed;
-      t.traj = it.traj0 + tl;
+      t.seed = uniform64(it.seed);
+      t.traj = uniform(it.traj0) + tl;
       t.tl = tl;
-      t.ntraj = it.ntraj;
-      t.step0 = it.step0 + wstep0;
+      t.ntraj = ntraj;
+      t.step0 = uniform(it.step0) + wstep0;
       t.nsteps = nsteps;
-      t.count_from = it.count_from;
+      t.count_from = uniform(it.count_from);
       t.state = it.d_state;
       t.counts = reinterpret_cast<unsigned long long*>(it.d_counts);
       t.tg = it.d_targets;
@@ -931,7 +941,7 @@ pbn_status launch_batch_t(const BatchParams& p, uint32_t lds, hipStream_t s) {
   const uint32_t resident = uint32_t(std::max(1, per_cu) * std::max(1, ncu));
   const uint32_t blocks = std::max(1u, std::min(p.ntasks, resident));
   hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(1), 0, s, p.ctl);
-  hipLaunchKernelGGL(fn, dim3(blocks), dim3(64u * p.wpb), lds, s, p);
+  hipLaunchKernelGGL(fn, dim3(blocks), dim3(64u * p.wpb), lds, s, p, p.items);
   hipLaunchKernelGGL(k_batch_end, dim3(1), dim3(1), 0, s, p.ctl);
   return hip_check(hipGetLastError(), "k_batch launch");
 }
