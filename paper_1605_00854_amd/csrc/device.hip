@@ -77,6 +77,50 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 __device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// Reads of a plan image.  G: the image is global memory reached through a
+// pointer loaded at run time (a batch's work item), read through a pointer of
+// the global address space so that the loads are global, not flat, loads
+// (flat loads would also wait on outstanding LDS traffic).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+#define PBN_GLOBAL_AS __attribute__((address_space(1)))
+template <bool G>
+__device__ __forceinline__ uint4 img_u4(const uint8_t* p) {
+  if constexpr (G) {
+    const u32x4 v = *(const PBN_GLOBAL_AS u32x4*)(p);
+    return make_uint4(v.x, v.y, v.z, v.w);
+  } else {
+    return *reinterpret_cast<const uint4*>(p);
+  }
+}
+template <bool G>
+__device__ __forceinline__ uint32_t img_u32(const uint8_t* p) {
+  if constexpr (G)
+    return *(const PBN_GLOBAL_AS uint32_t*)(p);
+  else
+    return *reinterpret_cast<const uint32_t*>(p);
+}
+template <bool G>
+__device__ __forceinline__ unsigned long long blob_u64(const unsigned long long* p) {
+  if constexpr (G)
+    return *(const PBN_GLOBAL_AS unsigned long long*)(p);
+  else
+    return *p;
+}
+template <bool G>
+__device__ __forceinline__ uint32_t blob_u32(const uint32_t* p) {
+  if constexpr (G)
+    return *(const PBN_GLOBAL_AS uint32_t*)(p);
+  else
+    return *p;
+}
+template <bool G>
+__device__ __forceinline__ uint32_t img_u8(const uint8_t* p) {
+  if constexpr (G)
+    return *(const PBN_GLOBAL_AS uint8_t*)(p);
+  else
+    return *p;
+}
 __device__ __forceinline__ unsigned long long uniform64(unsigned long long x) {
   return (static_cast<unsigned long long>(uniform(uint32_t(x >> 32))) << 32) | uniform(uint32_t(x));
 }
@@ -199,14 +243,16 @@ struct FnFmt {
 // positions; 128-entry table).  A gather-width-7 kernel reads two-unit plans;
 // with MIXED (batches of plans of both kinds) it also reads one-unit plans
 // (positions 5-7 = the zero position, table words 1-3 never selected).
-template <int PM, int UM, bool MIXED>
+// MODE: bit 0 MIXED, bit 1 image reads through global-address-space pointers.
+template <int PM, int UM, int MODE>
 __device__ __forceinline__ FnRec<Shape<PM, UM>::PW, Shape<PM, UM>::TTW> load_fn(const uint8_t* img, uint32_t base,
                                                                                uint32_t j, const FnFmt& fm) {
   constexpr int TTW = Shape<PM, UM>::TTW;
+  constexpr bool MIXED = (MODE & 1) != 0, G = (MODE & 2) != 0;
   FnRec<Shape<PM, UM>::PW, TTW> r;
   // records and units are 16-byte aligned: one 16-byte read per unit
   const uint8_t* rp = static_cast<const uint8_t*>(__builtin_assume_aligned(img + base + (j << fm.jshift), 16));
-  const uint4 a = *reinterpret_cast<const uint4*>(rp);
+  const uint4 a = img_u4<G>(rp);
   r.pw[0] = a.x;
   r.pw[1] = a.y;
   r.pw[2] = a.z;
@@ -214,7 +260,7 @@ __device__ __forceinline__ FnRec<Shape<PM, UM>::PW, Shape<PM, UM>::TTW> load_fn(
     r.tt[0] = a.w;
   } else {
     if (!MIXED || fm.units == 2u) {
-      const uint4 b = *reinterpret_cast<const uint4*>(rp + fm.hoff);
+      const uint4 b = img_u4<G>(rp + fm.hoff);
       r.pw[3] = a.w;
       r.tt[0] = b.x;
       r.tt[1] = b.y;
@@ -248,11 +294,12 @@ __device__ __forceinline__ uint32_t eval_fn(const FnRec<Shape<PM, UM>::PW, Shape
 // Slot record of `slot` (lane slot % 64 of pass slot / 64) and what it points
 // at: a table slot's union parents, a multi-predictor node's choice record, a
 // one-predictor node's own FN record.
-template <int PM, int UM, bool MIXED>
+template <int PM, int UM, int MODE>
 __device__ __forceinline__ void load_slot(SlotRegs<Shape<PM, UM>::XW, Shape<PM, UM>::TTW>& r, const uint8_t* img,
                                           uint32_t slot, const FnFmt& fm) {
   constexpr int XW = Shape<PM, UM>::XW, TTW = Shape<PM, UM>::TTW, PW = Shape<PM, UM>::PW, UW = Shape<PM, UM>::UW;
-  uint4 rec = reinterpret_cast<const uint4*>(img)[slot];
+  constexpr bool G = (MODE & 2) != 0;
+  uint4 rec = img_u4<G>(img + 16u * slot);
   // all four words are taken here: keeps the record one 16-byte read instead
   // of pieces re-read inside the branches below
   asm volatile("" : "+v"(rec.x), "+v"(rec.y), "+v"(rec.z), "+v"(rec.w));
@@ -268,20 +315,19 @@ __device__ __forceinline__ void load_slot(SlotRegs<Shape<PM, UM>::XW, Shape<PM, 
   for (int k = 0; k < TTW; ++k) r.tt[k] = 0;
   if (UM > 0 && (rec.x & PBN_SLOT_TABLE)) {
     r.spos = 4u * slot;
-    const uint32_t* up = reinterpret_cast<const uint32_t*>(img + rec.y);
 #pragma unroll
-    for (int k = 0; k < UW; ++k) r.pw[k] = up[k];
+    for (int k = 0; k < UW; ++k) r.pw[k] = img_u32<G>(img + rec.y + 4u * k);
   } else {
     r.spos = rec.w;   // FN slot or padded lane: its state byte
     if (PBN_SLOT_NMULTI(rec.x)) {
-      const uint4 ch = *reinterpret_cast<const uint4*>(img + rec.z);
+      const uint4 ch = img_u4<G>(img + rec.z);
       r.draw = ch.x;
       r.thr0 = ch.y;
       r.thr1 = ch.z;
       r.thr2 = ch.w;
     } else {
       // one-predictor node or padded lane (a dummy record)
-      const auto f = load_fn<PM, UM, MIXED>(img, rec.y, 0u, fm);
+      const auto f = load_fn<PM, UM, MODE>(img, rec.y, 0u, fm);
 #pragma unroll
       for (int k = 0; k < PW; ++k) r.pw[k] = f.pw[k];
 #pragma unroll
@@ -293,30 +339,31 @@ __device__ __forceinline__ void load_slot(SlotRegs<Shape<PM, UM>::XW, Shape<PM, 
 // TABLE slot: combined-function index from its multi-predictor members'
 // choices (mixed radix), union parents, one table byte expanded to one byte
 // per member (Section 3.3).
-template <int PM, int UM>
+template <int PM, int UM, int MODE>
 __device__ __forceinline__ uint32_t eval_table(const SlotRegs<Shape<PM, UM>::XW, Shape<PM, UM>::TTW>& r,
                                                const uint8_t* img, const uint8_t* cs, const uint8_t* rs) {
+  constexpr bool G = (MODE & 2) != 0;
   uint32_t c = 0;
   const uint32_t nm = PBN_SLOT_NMULTI(r.info);
   for (uint32_t m = 0; m < nm; ++m) {
-    const uint4 ch = *reinterpret_cast<const uint4*>(img + r.choice + 16u * m);
+    const uint4 ch = img_u4<G>(img + r.choice + 16u * m);
     const uint32_t w = *reinterpret_cast<const uint32_t*>(rs + (ch.x & 0xFFFFFFu));
     c += choose(w, ch.y, ch.z, ch.w, ch.x >> 24) * ((r.radix >> (8u * m)) & 0xFFu);
   }
   const uint32_t x = gather<(UM > 0 ? UM : 1)>(cs, r.pw);
-  const uint32_t v = img[r.base + 32u + (c << PBN_SLOT_NU(r.info)) + x];
+  const uint32_t v = img_u8<G>(img + r.base + 32u + (c << PBN_SLOT_NU(r.info)) + x);
   return (v * 0x204081u) & 0x01010101u;
 }
 
 // One slot: a table slot, a multi-predictor node (select from its drawn word,
 // then read the chosen record) or a one-predictor node (record already held).
 // `nt`: the slot's negated thresholds when held for the launch, else null.
-template <int PM, int UM, bool MIXED>
+template <int PM, int UM, int MODE>
 __device__ __forceinline__ uint32_t eval_slot(const SlotRegs<Shape<PM, UM>::XW, Shape<PM, UM>::TTW>& r,
                                               const NegThr* nt, const uint8_t* img, const uint8_t* cs,
                                               const uint8_t* rs, const FnFmt& fm) {
   constexpr int PW = Shape<PM, UM>::PW, TTW = Shape<PM, UM>::TTW;
-  if (UM > 0 && (r.info & PBN_SLOT_TABLE)) return eval_table<PM, UM>(r, img, cs, rs);
+  if (UM > 0 && (r.info & PBN_SLOT_TABLE)) return eval_table<PM, UM, MODE>(r, img, cs, rs);
   FnRec<PW, TTW> f;
 #pragma unroll
   for (int k = 0; k < PW; ++k) f.pw[k] = r.pw[k];
@@ -325,7 +372,7 @@ __device__ __forceinline__ uint32_t eval_slot(const SlotRegs<Shape<PM, UM>::XW, 
   if (PBN_SLOT_NMULTI(r.info)) {
     const uint32_t w = *reinterpret_cast<const uint32_t*>(rs + (r.draw & 0xFFFFFFu));
     const uint32_t j = nt ? choose_neg(w, *nt) : choose(w, r.thr0, r.thr1, r.thr2, r.draw >> 24);
-    f = load_fn<PM, UM, MIXED>(img, r.base, j, fm);
+    f = load_fn<PM, UM, MODE>(img, r.base, j, fm);
   }
   return eval_fn<PM, UM>(f, cs);
 }
@@ -358,8 +405,9 @@ struct TrajArgs {
 // PM: parent bytes gathered per FN slot (>= the plan's largest predictor);
 // UM: union bits gathered per TABLE slot (0: no table slots);
 // NREG: lane passes whose slot data stay in registers (0: reload every pass);
-// MIXED: FN records of one or two units (batches of plans of both kinds).
-template <int PM, int UM, int NREG, bool MIXED>
+// MODE: bit 0, FN records of one or two units (batches of plans of both
+// kinds); bit 1, image reads through global-address-space pointers.
+template <int PM, int UM, int NREG, int MODE>
 __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   constexpr int XW = Shape<PM, UM>::XW, TTW = Shape<PM, UM>::TTW;
   constexpr int NR = NREG > 0 ? NREG : 1;
@@ -406,7 +454,7 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
 #pragma unroll
     for (int p = 0; p < NREG; ++p) {
       if (uint32_t(p) < npass) {
-        load_slot<PM, UM, MIXED>(cached[p], img, uint32_t(p) * 64u + lane, fm);
+        load_slot<PM, UM, MODE>(cached[p], img, uint32_t(p) * 64u + lane, fm);
       } else {
         // no such pass: a one-predictor lane whose parents are all the zero
         // position and whose table is 0, writing 0 into the zero word
@@ -531,14 +579,14 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
           uint32_t base = 0;
           for (uint32_t st = stride0;; st /= 64u) {
             const uint32_t h = base + st * (lane + 1u);
-            const bool gt = h <= n && Q[h] > u;
+            const bool gt = h <= n && blob_u64<(MODE & 2) != 0>(Q + h) > u;
             base += st * uint32_t(__popcll(__ballot(gt)));
             if (st == 1u) break;
           }
           const uint32_t C = uniform(base);
           if (C >= n - j0) break;
           const uint32_t i = j0 + C;
-          const uint32_t pos = o2p[i];
+          const uint32_t pos = blob_u32<(MODE & 2) != 0>(o2p + i);
           if (pos != PBN_NONE && lane == 0) csb[pos] ^= 1u;
           j0 = i + 1u;
           if (j0 >= n) break;
@@ -553,7 +601,7 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
           // every pass reads s(t) before any writes s(t+1)
           uint32_t out[NREG];
 #pragma unroll
-          for (int p = 0; p < NREG; ++p) out[p] = eval_slot<PM, UM, MIXED>(cached[p], &nthr[p], img, csb, rs, fm);
+          for (int p = 0; p < NREG; ++p) out[p] = eval_slot<PM, UM, MODE>(cached[p], &nthr[p], img, csb, rs, fm);
 #pragma unroll
           for (int p = 0; p < NREG; ++p) store_slot<UM>(nsb, cached[p].info, cached[p].spos, out[p]);
           if constexpr (kBallotTargets) {
@@ -568,8 +616,8 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
         } else {
           for (uint32_t p = 0; p < npass; ++p) {
             Regs r;
-            load_slot<PM, UM, MIXED>(r, img, p * 64u + lane, fm);
-            store_slot<UM>(nsb, r.info, r.spos, eval_slot<PM, UM, MIXED>(r, nullptr, img, csb, rs, fm));
+            load_slot<PM, UM, MODE>(r, img, p * 64u + lane, fm);
+            store_slot<UM>(nsb, r.info, r.spos, eval_slot<PM, UM, MODE>(r, nullptr, img, csb, rs, fm));
           }
         }
         cur ^= 1u;
@@ -637,7 +685,7 @@ __global__ void __launch_bounds__(1024) k_simulate(SimParams a) {
   t.state = a.state;
   t.counts = a.counts;
   t.tg = &a.tg;
-  run_traj<PM, UM, NREG, false>(t);
+  run_traj<PM, UM, NREG, 0>(t);
 }
 
 // ---------------------------------------------------------------- batches
@@ -691,7 +739,7 @@ __global__ void __launch_bounds__(1024) k_batch(BatchParams a, const pbn_work* _
       t.state = it.d_state;
       t.counts = reinterpret_cast<unsigned long long*>(it.d_counts);
       t.tg = it.d_targets;
-      run_traj<PM, UM, 0, PM == 7>(t);
+      run_traj<PM, UM, 0, (PM == 7 ? 1 : 0) | 2>(t);
     }
   }
 }
