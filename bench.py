@@ -62,6 +62,7 @@ def measured_traffic(cfg_name):
 PLANS = {
     "grouped": dict(reduce=1, group=1),
     "reduction": dict(reduce=1, group=0),
+    "cone": dict(reduce=2, group=0),
     "plain": dict(reduce=0, group=0),
 }
 
@@ -278,7 +279,7 @@ def main():
     ap.add_argument("--wpb", type=int, default=0)
     ap.add_argument("--quick-tune", action="store_true")
     ap.add_argument("--queries", type=int, default=2000, help="C5: number of served queries")
-    ap.add_argument("--plan", default="auto", choices=["auto", "plain", "reduction", "grouped"],
+    ap.add_argument("--plan", default="auto", choices=["auto", "plain", "reduction", "cone", "grouped"],
                     help="product plan: autotuned, or a fixed preparation (profiling runs)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB copied once by a plain device copy (HBM counter calibration in profiles)")
@@ -298,7 +299,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         # before any GPU initialisation: the pool forks
-        sample = {"C1": (1, 20000), "C2": (512, 400), "C3": (32, 40)}[args.config]
+        sample = {"C1": (1, 20000), "C2": (512, 400), "C2X": (256, 400), "C3": (32, 40)}[args.config]
         cpu = cpu_baseline(args.config, *sample)
 
     import torch
@@ -354,7 +355,7 @@ def main():
     compare = {}
     if not args.no_compare:
         variants = {"plain": (PLANS["plain"], True, 0), "reduction": (PLANS["reduction"], True, 0),
-                    "grouped_default": (PLANS["grouped"], False, 0)}
+                    "cone": (PLANS["cone"], True, 0), "grouped_default": (PLANS["grouped"], False, 0)}
         if best_grouped:
             variants["grouped_tuned"] = (best_grouped["opts"], False, best_grouped["wpb"])
         for name, (opts, plain, wpb) in variants.items():
@@ -371,6 +372,8 @@ def main():
         compare["product_over_plain"] = value / compare["plain"]["node_updates_per_s"]
         compare["reduction_over_plain"] = (compare["reduction"]["node_updates_per_s"]
                                            / compare["plain"]["node_updates_per_s"])
+        compare["cone_over_reduction"] = (compare["cone"]["node_updates_per_s"]
+                                          / compare["reduction"]["node_updates_per_s"])
         for name in ("grouped_default", "grouped_tuned"):
             if name in compare:
                 compare[name + "_over_plain"] = (compare[name]["node_updates_per_s"]

@@ -119,8 +119,12 @@ pbn_status pbn_net_tables(const pbn_net* net, uint64_t* q, uint32_t* cum, int32_
  * will read); they are never removed.
  *
  * Options:
- *   reduce             1: remove leaf nodes (their perturbations still force a
- *                      perturbation-only step, as Algorithm 1 requires)
+ *   reduce             1: remove leaf nodes (Definition 1; their
+ *                      perturbations still force a perturbation-only step, as
+ *                      Algorithm 1 requires); 2: remove every node from which
+ *                      no node of interest is reachable (the same argument
+ *                      applied to whole regions, cycles included; a superset
+ *                      of the leaves, same perturbation handling); 0: none
  *   group              1: group nodes into combined tables; 0: one predictor
  *                      evaluation per node
  *   weight_mode        weight of a multi-predictor node in Algorithms 3-4:

@@ -3,6 +3,8 @@
 Plain Python (sets, lists, big integers) written from the text:
 
 * leaf_nodes        Definition 1 (Section 3.1), iterated removal of sinks
+* cone_removed      the stronger reduction the same section's argument allows:
+                    every node from which no node of interest can be reached
 * eq2_lower_bound   Equation 2 and Theorem 2 (Section 3.3)
 * find_partitions   the greedy multi-way partition of Algorithm 3
 * partition_multi   Algorithm 4 on the multi-predictor nodes
@@ -60,6 +62,32 @@ def leaf_nodes(net, interest):
                 removed.add(v)
                 changed = True
     return removed
+
+
+def cone_removed(net, interest):
+    """Set of nodes from which no node of interest is reachable along
+    parent -> child edges (the complement of the interest nodes' ancestors).
+
+    Section 3.1 removes leaves because nothing of interest depends on them; the
+    same argument removes every node outside the ancestor set of the nodes of
+    interest, cycles included.  The ancestor set is closed under taking
+    parents, so the kept nodes evolve exactly as in the full network.
+    """
+    n = int(net["n"])
+    ch = children(net)
+    parents = [set() for _ in range(n)]
+    for v in range(n):
+        for c in ch[v]:
+            parents[c].add(v)
+    keep = set(int(x) for x in interest)
+    frontier = list(keep)
+    while frontier:
+        v = frontier.pop()
+        for u in parents[v]:
+            if u not in keep:
+                keep.add(u)
+                frontier.append(u)
+    return set(range(n)) - keep
 
 
 def sat_mul(a, b):

@@ -20,15 +20,26 @@ PLAIN = dict(reduce=0, group=0)
 REDUCTION = dict(reduce=1, group=0)
 
 
-def candidates(quick=False):
-    out = [PLAIN, REDUCTION]
+def candidates(quick=False, reduce=1):
+    """Plan options to probe.  `reduce` is the reduction the reduced
+    candidates use: 1 (Definition 1's leaves) or 2 (the cone of influence of
+    the nodes of interest, which removes a superset of the leaves)."""
+    out = [PLAIN, dict(reduce=reduce, group=0)]
     bits = (4, 6, 8) if quick else (4, 5, 6, 8, 10, 12)
     nodes = (2, 4) if quick else (2, 3, 4)
     for b in bits:
         for g in nodes:
-            out.append(dict(reduce=1, group=1, max_parent_bits=b, max_group_nodes=g))
-    out.append(dict(reduce=1, group=1, weight_mode=0, theta=1 << 20, max_parent_bits=8, max_group_nodes=4))
+            out.append(dict(reduce=reduce, group=1, max_parent_bits=b, max_group_nodes=g))
+    out.append(dict(reduce=reduce, group=1, weight_mode=0, theta=1 << 20, max_parent_bits=8, max_group_nodes=4))
     return out
+
+
+def best_reduction(net, interest):
+    """2 when the cone-of-influence reduction removes more nodes than
+    Definition 1 does (a subset of the kept nodes: never more work), else 1."""
+    leaf = api.Plan(net, interest=interest, reduce=1, group=0).info["n_kept"]
+    cone = api.Plan(net, interest=interest, reduce=2, group=0).info["n_kept"]
+    return 2 if cone < leaf else 1
 
 
 _CACHE = {}
@@ -62,7 +73,7 @@ def tune(net, interest, target_sets, ntraj, seed=1, probe_steps=2000, wpbs=(2, 4
     n = int(net["n"])
     trials = []
     seen = set()
-    for opts in candidates(quick):
+    for opts in candidates(quick, best_reduction(net, interest)):
         try:
             plan = api.Plan(net, interest=interest, **opts)
         except api._lib.PbnError as e:      # a cap the network cannot meet

@@ -91,6 +91,33 @@ std::vector<uint8_t> leaf_nodes(const pbn_net& g, const std::vector<uint8_t>& in
   return removed;
 }
 
+// Every node from which no node of interest is reachable (the complement of
+// the interest nodes' ancestors): Section 3.1's argument for removing leaves
+// applied to whole unreachable regions, cycles included.
+std::vector<uint8_t> cone_removed(const pbn_net& g, const std::vector<uint8_t>& interest,
+                                  const std::vector<std::vector<uint32_t>>& P) {
+  const uint32_t n = g.n;
+  std::vector<uint8_t> keep(n, 0);
+  std::vector<uint32_t> stack;
+  for (uint32_t v = 0; v < n; ++v)
+    if (interest[v]) {
+      keep[v] = 1;
+      stack.push_back(v);
+    }
+  while (!stack.empty()) {
+    const uint32_t v = stack.back();
+    stack.pop_back();
+    for (uint32_t p : P[v])
+      if (!keep[p]) {
+        keep[p] = 1;
+        stack.push_back(p);
+      }
+  }
+  std::vector<uint8_t> removed(n, 0);
+  for (uint32_t v = 0; v < n; ++v) removed[v] = keep[v] ? 0 : 1;
+  return removed;
+}
+
 // Algorithm 3 (greedy multi-way partition on products).
 std::vector<std::vector<uint32_t>> find_partitions(std::vector<std::pair<uint32_t, uint64_t>> items, uint32_t m) {
   std::stable_sort(items.begin(), items.end(), [](const auto& a, const auto& b) {
@@ -236,7 +263,8 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
 
   // ---- Step 1: leaf-node reduction (Definition 1)
   std::vector<uint8_t> removed(n, 0);
-  if (o.reduce) removed = leaf_nodes(g, interest, P);
+  if (o.reduce == 1) removed = leaf_nodes(g, interest, P);
+  if (o.reduce == 2) removed = cone_removed(g, interest, P);
   std::vector<uint32_t> kept;
   for (uint32_t i = 0; i < n; ++i)
     if (!removed[i]) kept.push_back(i);
@@ -606,6 +634,7 @@ extern "C" pbn_status pbn_plan_build(const pbn_net* g, const uint32_t* interest,
     o = *opts;
   else
     pbn_plan_opts_default(&o);
+  if (o.reduce > 2) return fail(PBN_EINVAL, "reduce must be 0, 1 or 2");
   if (o.max_group_nodes < 1 || o.max_group_nodes > PBN_MAX_GROUP_NODES)
     return fail(PBN_EINVAL, "max_group_nodes must be 1..%d", PBN_MAX_GROUP_NODES);
   if (o.max_parent_bits > PBN_MAX_GROUP_PARENTS)

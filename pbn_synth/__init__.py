@@ -137,6 +137,41 @@ def large_c3(n=2000, p=1e-4, seed=1003):
     return random_pbn(n, p, seed, nfn=one, nparents=_trunc_geometric(0.30999, 6))
 
 
+def with_detached_modules(core, modules, size, seed, nparents=(2, 4)):
+    """The core network plus `modules` extra regions of `size` nodes each.
+
+    A module node reads 2-4 parents drawn from its own module and the core, so
+    every module contains feedback cycles (its nodes are parents of one
+    another) while no core node ever reads a module node: nothing in the core
+    depends on the modules.  Each extra node has one predictor (probability 1)
+    with an iid Bernoulli(0.5) truth table.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n0 = int(core["n"])
+    fo, po, par, sel = core["fn_off"], core["par_off"], core["parents"], core["sel_prob"]
+    to, tt = core["tt_off"], core["tt"]
+    functions = []
+    for i in range(n0):
+        fl = []
+        for f in range(int(fo[i]), int(fo[i + 1])):
+            k = int(po[f + 1] - po[f])
+            words = tt[int(to[f]):int(to[f + 1])]
+            bits = [(int(words[x // 64]) >> (x % 64)) & 1 for x in range(1 << k)]
+            fl.append((float(sel[f]), [int(v) for v in par[int(po[f]):int(po[f + 1])]], bits))
+        functions.append(fl)
+    for m in range(modules):
+        base = n0 + m * size
+        pool = np.concatenate([np.arange(n0), np.arange(base, base + size)])
+        for i in range(size):
+            k = int(rng.integers(nparents[0], nparents[1] + 1))
+            own = int(rng.integers(base, base + size))          # at least one parent inside the module
+            rest = rng.choice(pool[pool != own], size=k - 1, replace=False)
+            functions.append([(1.0, [own] + rest.tolist(), _draw_table(rng, k))])
+    net = assemble(n0 + modules * size, core["p"], functions)
+    net["designated_leaves"] = np.asarray(core.get("designated_leaves", []), dtype=np.uint32)
+    return net
+
+
 def batch_c4(count=512, seed=1004):
     """Uneven batch: n ~ U[20, 1500] with the medium generator, p in {1e-3, 1e-4}."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -199,7 +234,8 @@ class RunConfig:
 
 
 def config(name):
-    """The workloads of the build plan (C1 tiny, C2 medium, C3 large)."""
+    """The workloads of the build plan (C1 tiny, C2 medium, C3 large; C2X the
+    medium network with detached modules)."""
     if name == "C1":
         net = tiny_c1()
         return RunConfig("C1", net, ntraj=1, steps=10**6, burn_in=0, targets=[[(0, 1), (1, 1)]], seed=1)
@@ -211,4 +247,11 @@ def config(name):
         net = large_c3()
         return RunConfig("C3", net, ntraj=65536, steps=10**5, burn_in=10**4,
                          targets=[non_leaf_targets(net)], seed=3)
+    if name == "C2X":
+        # the medium network plus four detached 25-node feedback modules that
+        # no core node reads (the workload of the cone-of-influence reduction)
+        core = medium_c2()
+        net = with_detached_modules(core, 4, 25, seed=1006)
+        return RunConfig("C2X", net, ntraj=4096, steps=10**6, burn_in=0,
+                         targets=[non_leaf_targets(core)], seed=6)
     raise KeyError(name)

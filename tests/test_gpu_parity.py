@@ -62,6 +62,7 @@ NETS = {
     "single200": lambda: all_single(200, 13),
     "sparse120": lambda: sparse_multi(120, 14),
     "c3_slice": lambda: ps.large_c3(n=1500, p=2e-4, seed=15),
+    "modules": lambda: ps.with_detached_modules(ps.medium_c2(n=60, p=3e-3, seed=16), 3, 20, seed=17),
 }
 
 
@@ -122,6 +123,8 @@ GROUPED = dict(reduce=1, group=1)
 MULTI_GROUPS = dict(reduce=1, group=1, weight_mode=0, theta=10**6, max_table_entries=1 << 14,
                     max_parent_bits=12)
 GLOBAL_IMAGE = dict(reduce=1, group=1, lds_budget_bytes=0)
+CONE = dict(reduce=2, group=0)
+CONE_GROUPED = dict(reduce=2, group=1)
 
 CASES = [
     # name, opts, seed, traj0, ntraj, chunks, count_from, plain, wpb
@@ -139,6 +142,8 @@ CASES = [
     ("single200", GROUPED, 6, 0, 8, (200,), 0, False, 0),
     ("sparse120", MULTI_GROUPS, 7, 0, 12, (150,), 0, False, 0),
     ("c3_slice", GROUPED, 8, 0, 3, (25,), 0, False, 0),
+    ("modules", CONE, 18, 0, 20, (400,), 0, True, 0),
+    ("modules", CONE_GROUPED, 18, 0, 20, (250, 150), 100, False, 2),
 ]
 
 
@@ -150,6 +155,11 @@ def test_trajectories_bit_exact(case):
         assert plan.info["n_multi_groups"] > 0, "case must exercise multi-member tables"
     if opts is GLOBAL_IMAGE:
         assert plan.info["image_in_lds"] == 0
+    if opts is CONE:
+        # the cone reduction removes the detached modules, which Definition 1 keeps
+        leaf = api.Plan(net_of(name), interest=sorted({a for tg in targets_of(net_of(name)) for a, _ in tg}),
+                        **REDUCED)
+        assert plan.info["n_kept"] < leaf.info["n_kept"]
 
 
 @pytest.mark.parametrize("name,opts", [("c2", GROUPED), ("c3_slice", REDUCED), ("c1", PLAIN)])

@@ -59,6 +59,27 @@ def test_leaf_reduction_matches_definition_1(name, interest):
     assert removed == structure.leaf_nodes(net, interest)
 
 
+@pytest.mark.parametrize("name", sorted(NETS))
+@pytest.mark.parametrize("interest", [(0,), (0, 1, 2, 5)])
+def test_cone_reduction_matches_oracle(name, interest):
+    net = NETS[name]
+    plan = api.Plan(net, interest=interest, reduce=2, group=0)
+    removed = set(np.nonzero(plan.node_pos() == 0xFFFFFFFF)[0].tolist())
+    assert removed == structure.cone_removed(net, interest)
+
+
+def test_cone_reduction_removes_detached_modules():
+    cfg = ps.config("C2X")
+    interest = sorted({a for tg in cfg.targets for a, _ in tg})
+    plan = api.Plan(cfg.net, interest=interest, reduce=2, group=0)
+    removed = set(np.nonzero(plan.node_pos() == 0xFFFFFFFF)[0].tolist())
+    assert removed == structure.cone_removed(cfg.net, interest)
+    assert set(range(100, 200)) <= removed                       # every module node
+    assert structure.leaf_nodes(cfg.net, interest) < removed     # strictly more than Definition 1
+    with pytest.raises(_lib.PbnError):
+        api.Plan(cfg.net, interest=interest, reduce=3, group=0)
+
+
 def test_designated_leaves_are_removed():
     net = NETS["c2"]
     plan = api.Plan(net, interest=[a for a, _ in ps.non_leaf_targets(net)], reduce=1, group=0)

@@ -1,6 +1,9 @@
 """Pins for the oracle's structure analysis (Section 3).
 
 * Definition 1 on hand-built graphs whose leaf sets are worked out by hand.
+* The cone-of-influence reduction: hand-built graphs, and on random graphs a
+  brute-force reachability check of every node, closure of the kept set under
+  parents, and that it contains Definition 1's leaves.
 * Equation 2 / Theorem 2: the bound never exceeds the true minimum number of
   groups found by brute force over all set partitions of small item lists.
 * Algorithm 3 on a hand-traced example; Algorithm 4 meets its bound.
@@ -42,6 +45,51 @@ def test_leaf_self_loop_and_cycle_are_kept():
     net = graph(5, [(0, 1), (1, 0), (0, 2), (3, 4)], self_loops=[3])
     # 2 and 4 are sinks; 0-1 is a cycle; 3 reads itself
     assert so.leaf_nodes(net, []) == {2, 4}
+
+
+def test_cone_removes_unreachable_cycles_and_self_loops():
+    # 0 -> 1 -> 2 (interest); 0 -> 3 <-> 4 (a cycle nobody reads); 5 reads itself
+    # and 0; 6 is a sink
+    net = graph(7, [(0, 1), (1, 2), (0, 3), (3, 4), (4, 3), (5, 6), (0, 5)], self_loops=[5])
+    assert so.cone_removed(net, [2]) == {3, 4, 5, 6}
+    assert so.leaf_nodes(net, [2]) == {6}               # Definition 1 keeps the cycle and the self-loop
+    assert so.cone_removed(net, [4]) == {1, 2, 5, 6}    # 0 reaches 4 through 3
+    assert so.cone_removed(net, [2, 6]) == {3, 4}
+    assert so.cone_removed(net, []) == set(range(7))
+
+
+def _reaches(net, v, targets):
+    ch = so.children(net)
+    seen, stack = {v}, [v]
+    while stack:
+        u = stack.pop()
+        if u in targets:
+            return True
+        for c in ch[u]:
+            if c not in seen:
+                seen.add(c)
+                stack.append(c)
+    return False
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_cone_is_the_complement_of_the_ancestors(seed):
+    rng = np.random.default_rng(seed)
+    n = 24
+    fns = []
+    for v in range(n):
+        k = int(rng.integers(0, 3))
+        fns.append([(1.0, list(rng.choice(n, size=k, replace=False)), [0] * (1 << k))])
+    net = ps.assemble(n, 0.1, fns)
+    interest = sorted(rng.choice(n, size=2, replace=False).tolist())
+    removed = so.cone_removed(net, interest)
+    for v in range(n):                                   # brute force, node by node
+        assert (v in removed) == (not _reaches(net, v, set(interest)))
+    kept = set(range(n)) - removed
+    for v in kept:                                       # closed under parents
+        for f in range(int(net["fn_off"][v]), int(net["fn_off"][v + 1])):
+            assert set(int(u) for u in net["parents"][net["par_off"][f]:net["par_off"][f + 1]]) <= kept
+    assert so.leaf_nodes(net, interest) <= removed
 
 
 def test_leaf_interest_sink_is_kept():
