@@ -246,10 +246,20 @@ pbn_status pbn_targets_build(const pbn_plan* plan, const uint32_t* node, const u
 pbn_status pbn_state_init(const pbn_plan* plan, const void* d_plan, uint64_t seed, uint32_t traj0,
                           uint32_t ntraj, uint32_t* d_state, void* stream);
 
-/* Launch tunables (0 = library choice). */
+/* Launch tunables (0 = library choice) and optional recording of the hit
+ * indicator of target 0 for the Raftery-Lewis diagnosis:
+ *   d_record      device [record_traj][record_words] uint32, caller-owned and
+ *                 zeroed by the caller; trajectory tl < record_traj of the
+ *                 launch ORs bit (t - count_from) with z(t) = [s(t+1) in target
+ *                 0] for steps count_from <= t < count_from + 32 record_words
+ *                 (word w bit b = step count_from + 32 w + b).  NULL: none.
+ * Errors: PBN_EINVAL when d_record is set and record_words is 0. */
 typedef struct pbn_launch_opts {
   uint32_t waves_per_block;       /* trajectories per workgroup, 1 .. 16      */
-  uint32_t reserved[3];
+  uint32_t record_traj;
+  uint32_t record_words;
+  uint32_t reserved;
+  uint32_t* d_record;
 } pbn_launch_opts;
 
 /* pbn_simulate: advance every trajectory by nsteps transitions of Eq. 1,
@@ -307,6 +317,54 @@ typedef struct pbn_estimate_out {
 
 pbn_status pbn_estimate(const uint64_t* counts, uint32_t units, uint64_t steps_per_unit, double conf,
                         double precision, pbn_estimate_out* out);
+
+/* Raftery-Lewis single-chain diagnosis (the two-state Markov chain approach
+ * the paper uses for its steady-state estimates, Section 4.2; Raftery and
+ * Lewis, 1992) of one recorded hit-indicator sequence: bits[t >> 5] bit
+ * (t & 31) = z_t for t = 0 .. nbits-1 (host array, caller-owned).
+ *   k           thinning: the smallest k <= kmax whose k-thinned sequence
+ *               z_0, z_k, ... prefers a first-order to a second-order Markov
+ *               chain, BIC = G^2 - 2 log(L - 2) < 0 (kmax when none does)
+ *   g2, bic     the statistic and BIC at that k
+ *   alpha, beta 0->1 and 1->0 probabilities of the k-thinned chain
+ *   burn_in     m* k original steps, m* = log(eps (alpha+beta) / max(alpha,
+ *               beta)) / log|1 - alpha - beta|  (1 when alpha + beta = 1)
+ *   n_required  N* k original steps, N* = alpha beta (2 - alpha - beta) /
+ *               (alpha + beta)^3 (Phi^-1((1 + conf) / 2) / precision)^2
+ *   p_hat       mean of z_t for t >= ceil(burn_in) (NaN if none)
+ * burn_in and n_required are +inf when the thinned chain never changes state.
+ * Errors: PBN_EINVAL (nbits < 3, kmax = 0, precision/eps <= 0, conf outside
+ * (0, 1)). */
+typedef struct pbn_rl_out {
+  uint32_t k;
+  uint32_t reserved;
+  double g2, bic;
+  double alpha, beta;
+  double burn_in;
+  double n_required;
+  double p_hat;
+  uint64_t steps;      /* nbits of the diagnosed sequence */
+} pbn_rl_out;
+
+pbn_status pbn_rl_diagnose(const uint32_t* bits, uint64_t nbits, double precision, double conf, double eps,
+                           uint32_t kmax, pbn_rl_out* out);
+
+/* Blocking driver of the two-state Markov chain approach on one trajectory
+ * (id `traj`): s(0) from the INIT stream, then simulate from step 0 while
+ * recording target 0's indicator, diagnose (pbn_rl_diagnose), and extend the
+ * same trajectory to burn_in + n_required steps until the run is at least that
+ * long.  The first diagnosis runs after initial_steps (at least 64).
+ *   d_state [state_words], d_counts [ntargets][1][3], d_record [record_words]:
+ *   caller-owned device buffers (zeroed or initialised here); the run is
+ *   limited to min(max_steps, 32 record_words) < 2^32 steps.
+ * `out` holds the last diagnosis.  Synchronises `stream`.  Errors: PBN_EINVAL,
+ * PBN_ERANGE (the diagnosis asks for more steps than the limit; `out` is
+ * filled), PBN_EHIP, and the errors of pbn_simulate. */
+pbn_status pbn_rl_run(const pbn_plan* plan, const void* d_plan, uint64_t seed, uint32_t traj,
+                      const pbn_targets* targets, uint32_t* d_state, uint64_t* d_counts, uint32_t* d_record,
+                      uint32_t record_words, double precision, double conf, double eps, uint32_t kmax,
+                      uint64_t initial_steps, uint64_t max_steps, const pbn_launch_opts* launch, pbn_rl_out* out,
+                      void* stream);
 
 /* Quantiles used by pbn_estimate: Student t with nu degrees of freedom, and the
  * standard normal.  p in (0, 1). */

@@ -115,13 +115,15 @@ def target_hit(s, target):
 
 
 def run(net, seed, traj, steps, *, step0=0, count_from=0, targets=(), state=None,
-        nw=None, record=()):
+        nw=None, record=(), indicators=False):
     """Simulate `steps` transitions starting at global step `step0`.
 
     Returns a dict with the final state, per-target counters per trajectory
     (hits over transitions t >= count_from, and 0->1 / 1->0 transitions of the
     hit indicator between consecutive counted samples), the number of
-    perturbed steps, and the states after the transitions listed in `record`.
+    perturbed steps, and the states after the transitions listed in `record`;
+    with `indicators`, also "z": the indicator of the first target after every
+    transition, [trajectory][step - step0].
     """
     nw = nw or Network(net)
     traj = np.asarray(traj, dtype=np.uint64)
@@ -133,11 +135,14 @@ def run(net, seed, traj, steps, *, step0=0, count_from=0, targets=(), state=None
     zprev = [target_hit(s, tg) for tg in targets]
     npert = np.zeros(traj.size, dtype=np.int64)
     snaps = {}
+    zs = np.zeros((traj.size, steps), dtype=np.uint8) if indicators else None
     for t in range(step0, step0 + steps):
         s, pert = step(nw, seed, traj, t, s)
         npert += pert
         for q, tg in enumerate(targets):
             z = target_hit(s, tg)
+            if indicators and q == 0:
+                zs[:, t - step0] = z
             if t >= count_from:
                 hits[q] += z
             if t >= count_from + 1:
@@ -146,5 +151,7 @@ def run(net, seed, traj, steps, *, step0=0, count_from=0, targets=(), state=None
             zprev[q] = z
         if t + 1 in record:
             snaps[t + 1] = s.copy()
-    return {"state": s, "hits": hits, "n01": n01, "n10": n10, "perturbed": npert,
-            "snapshots": snaps}
+    out = {"state": s, "hits": hits, "n01": n01, "n10": n10, "perturbed": npert, "snapshots": snaps}
+    if indicators:
+        out["z"] = zs
+    return out

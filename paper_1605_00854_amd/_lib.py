@@ -46,7 +46,14 @@ class pbn_targets(C.Structure):
 
 
 class pbn_launch_opts(C.Structure):
-    _fields_ = [("waves_per_block", C.c_uint32), ("reserved", C.c_uint32 * 3)]
+    _fields_ = [("waves_per_block", C.c_uint32), ("record_traj", C.c_uint32), ("record_words", C.c_uint32),
+                ("reserved", C.c_uint32), ("d_record", C.c_void_p)]
+
+
+class pbn_rl_out(C.Structure):
+    _fields_ = [("k", C.c_uint32), ("reserved", C.c_uint32), ("g2", C.c_double), ("bic", C.c_double),
+                ("alpha", C.c_double), ("beta", C.c_double), ("burn_in", C.c_double),
+                ("n_required", C.c_double), ("p_hat", C.c_double), ("steps", C.c_uint64)]
 
 
 class pbn_work(C.Structure):
@@ -96,6 +103,11 @@ SIGNATURES = {
     "pbn_graph_launch": (C.c_int32, [_P, _P]),
     "pbn_graph_destroy": (C.c_int32, [_P]),
     "pbn_estimate": (C.c_int32, [_pU64, _U32, _U64, C.c_double, C.c_double, C.POINTER(pbn_estimate_out)]),
+    "pbn_rl_diagnose": (C.c_int32, [_pU32, _U64, C.c_double, C.c_double, C.c_double, _U32,
+                                    C.POINTER(pbn_rl_out)]),
+    "pbn_rl_run": (C.c_int32, [_P, _P, _U64, _U32, C.POINTER(pbn_targets), _P, _P, _P, _U32, C.c_double,
+                               C.c_double, C.c_double, _U32, _U64, _U64, C.POINTER(pbn_launch_opts),
+                               C.POINTER(pbn_rl_out), _P]),
     "pbn_t_quantile": (C.c_double, [C.c_double, C.c_double]),
     "pbn_normal_quantile": (C.c_double, [C.c_double]),
 }

@@ -174,6 +174,47 @@ def estimate(counts, steps_per_unit, conf=0.95, precision=0.01):
     return {name: getattr(out, name) for name, _ in out._fields_ if name != "reserved"}
 
 
+def rl_diagnose(bits, nbits, precision, conf=0.95, eps=1e-3, kmax=100):
+    """pbn_rl_diagnose on a host bit array (uint32 words, bit t = z_t)."""
+    w = np.ascontiguousarray(np.asarray(bits).view(np.uint32) if np.asarray(bits).dtype == np.int32
+                             else np.asarray(bits, dtype=np.uint32))
+    out = _lib.pbn_rl_out()
+    check(lib().pbn_rl_diagnose(_ptr(w, C.c_uint32), int(nbits), float(precision), float(conf), float(eps),
+                                int(kmax), C.byref(out)))
+    return {name: getattr(out, name) for name, _ in out._fields_ if name != "reserved"}
+
+
+def unpack_record(words, nbits):
+    """0/1 array of the first nbits bits of recorded words (bit t of word t // 32)."""
+    w = np.asarray(words).view(np.uint32).reshape(-1)
+    bits = ((w[:, None] >> np.arange(32, dtype=np.uint32)[None, :]) & 1).reshape(-1)
+    return bits[:nbits].astype(np.uint8)
+
+
+def rl_run(plan, seed, target_sets, precision, *, traj=0, conf=0.95, eps=1e-3, kmax=100,
+           initial_steps=100000, max_steps=1 << 28, waves_per_block=0, stream=None):
+    """Two-state Markov chain approach on one trajectory (pbn_rl_run, blocking).
+
+    Returns (diagnosis dict, recorded indicator words as a device tensor)."""
+    import torch
+    tg = plan.targets(target_sets)
+    words = (int(max_steps) + 31) // 32
+    state = new_state(plan, 1)
+    counts = new_counts(tg.ntargets, 1)
+    record = torch.zeros(words, dtype=torch.int32, device="cuda")
+    lo = _lib.pbn_launch_opts(int(waves_per_block))
+    out = _lib.pbn_rl_out()
+    rc = lib().pbn_rl_run(plan.handle, _dptr(plan.device()), int(seed), int(traj), C.byref(tg), _dptr(state),
+                          _dptr(counts), _dptr(record), words, float(precision), float(conf), float(eps),
+                          int(kmax), int(initial_steps), int(max_steps), C.byref(lo), C.byref(out),
+                          _stream(stream))
+    res = {name: getattr(out, name) for name, _ in out._fields_ if name != "reserved"}
+    res["status"] = int(rc)
+    if rc not in (0, _lib.ERANGE):
+        check(rc)
+    return res, record
+
+
 # ------------------------------------------------------------------ device
 
 def _stream(stream):
@@ -204,10 +245,17 @@ def state_init(plan, seed, ntraj, traj0=0, state=None, stream=None):
 
 
 def simulate(plan, seed, state, counts, targets, step0, nsteps, *, traj0=0, count_from=0, plain=False,
-             waves_per_block=0, stream=None):
-    """Advance trajectories traj0 .. traj0+ntraj-1 by nsteps (global steps step0..)."""
+             waves_per_block=0, stream=None, record=None):
+    """Advance trajectories traj0 .. traj0+ntraj-1 by nsteps (global steps step0..).
+
+    record: optional int32 device tensor [r][words]: trajectories 0 .. r-1 of
+    the launch OR target 0's indicator bits into it (bit t - count_from)."""
     ntraj = state.shape[0]
     lo = _lib.pbn_launch_opts(int(waves_per_block))
+    if record is not None:
+        lo.record_traj = int(record.shape[0])
+        lo.record_words = int(record.shape[1])
+        lo.d_record = record.data_ptr()
     fn = lib().pbn_simulate_plain if plain else lib().pbn_simulate
     check(fn(plan.handle, _dptr(plan.device()), int(seed), int(traj0), int(ntraj), int(step0), int(nsteps),
              int(count_from), C.byref(targets), _dptr(state), _dptr(counts), C.byref(lo), _stream(stream)))

@@ -25,8 +25,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "internal.h"
 
@@ -161,7 +163,10 @@ struct SimParams {
   uint32_t traj0, ntraj, step0, nsteps, count_from;
   uint32_t wpb;
   uint32_t wave_bytes;   // LDS bytes per wave: two state buffers + ring
+  uint32_t record_traj;  // trajectories 0 .. record_traj-1 record target 0's indicator bits
+  uint32_t record_words; // words per recording trajectory
   uint32_t pad;
+  uint32_t* record;      // [record_traj][record_words] or null
   pbn_targets tg;
 };
 
@@ -400,6 +405,8 @@ struct TrajArgs {
   uint32_t* state;                  // [ntraj][state_words]
   unsigned long long* counts;       // [ntargets][ntraj][3]
   const pbn_targets* tg;
+  uint32_t* record;                 // this trajectory's indicator bits (target 0), or null
+  uint32_t record_words;
 };
 
 // PM: parent bytes gathered per FN slot (>= the plan's largest predictor);
@@ -537,8 +544,32 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   uint32_t t = a.step0;
   uint32_t tacc = t;   // step of the oldest accumulated bit
   auto low_bits = [](long long m) -> uint32_t { return m <= 0 ? 0u : m >= 32 ? 0xFFFFFFFFu : (1u << m) - 1u; };
+  // recorded indicator of target 0 (lane 0): bit (t - count_from) = z for the
+  // transition of step t, steps count_from .. count_from + 32 record_words - 1
+  auto record_bits = [&]() {
+    uint64_t v = __builtin_bitreverse32(zacc) >> (32u - nacc);   // bit b: step tacc + b
+    long long pos = (long long)tacc - (long long)a.count_from;
+    long long cnt = nacc;
+    if (pos < 0) {
+      if (-pos >= cnt) return;
+      v >>= -pos;
+      cnt += pos;
+      pos = 0;
+    }
+    const long long limit = 32ll * a.record_words;
+    if (pos >= limit) return;
+    if (pos + cnt > limit) {
+      cnt = limit - pos;
+      v &= (1ull << cnt) - 1ull;
+    }
+    const uint32_t w = uint32_t(pos >> 5);
+    const uint64_t x = v << (pos & 31);
+    a.record[w] |= uint32_t(x);
+    if ((x >> 32) != 0ull && w + 1u < a.record_words) a.record[w + 1u] |= uint32_t(x >> 32);
+  };
   auto fold = [&]() {
     if (nacc == 0u) return;
+    if (a.record != nullptr && lane == 0u) record_bits();
     const long long newest = (long long)tacc + nacc - 1;   // step of bit 0
     const uint32_t keep = low_bits(nacc);
     const uint32_t hm = low_bits(newest - (long long)a.count_from + 1) & keep;
@@ -685,6 +716,8 @@ __global__ void __launch_bounds__(1024) k_simulate(SimParams a) {
   t.state = a.state;
   t.counts = a.counts;
   t.tg = &a.tg;
+  t.record = a.record && tl < a.record_traj ? a.record + size_t(tl) * a.record_words : nullptr;
+  t.record_words = a.record_words;
   run_traj<PM, UM, NREG, 0>(t);
 }
 
@@ -739,6 +772,8 @@ __global__ void __launch_bounds__(1024) k_batch(BatchParams a, const pbn_work* _
       t.state = it.d_state;
       t.counts = reinterpret_cast<unsigned long long*>(it.d_counts);
       t.tg = it.d_targets;
+      t.record = nullptr;
+      t.record_words = 0;
       run_traj<PM, UM, 0, (PM == 7 ? 1 : 0) | 2>(t);
     }
   }
@@ -879,6 +914,8 @@ pbn_status simulate_common(bool plain, const pbn_plan* plan, const void* d_plan,
   const bool img_lds = plan->info.image_in_lds != 0;
   const uint32_t img = img_lds ? ((plan->info.image_bytes + 15u) & ~15u) : 0u;
   uint32_t wpb = launch && launch->waves_per_block ? launch->waves_per_block : 4u;
+  if (launch && launch->d_record && launch->record_words == 0)
+    return fail(PBN_EINVAL, "record_words must be positive when recording");
   if (wpb > 16) return fail(PBN_EINVAL, "waves_per_block must be 1..16");
   while (wpb > 1 && img + wpb * wave_bytes > kLdsMax) --wpb;
   if (img + wpb * wave_bytes > kLdsMax)
@@ -896,6 +933,11 @@ pbn_status simulate_common(bool plain, const pbn_plan* plan, const void* d_plan,
   p.wpb = wpb;
   p.wave_bytes = wave_bytes;
   p.tg = *targets;
+  if (launch && launch->d_record) {
+    p.record = launch->d_record;
+    p.record_traj = launch->record_traj;
+    p.record_words = launch->record_words;
+  }
   const uint32_t blocks = (ntraj + wpb - 1) / wpb;
   const uint32_t lds = img + wpb * wave_bytes;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -936,6 +978,54 @@ extern "C" pbn_status pbn_simulate_plain(const pbn_plan* plan, const void* d_pla
                                          const pbn_launch_opts* launch, void* stream) {
   return simulate_common(true, plan, d_plan, seed, traj0, ntraj, step0, nsteps, count_from, targets, d_state,
                          d_counts, launch, stream);
+}
+
+extern "C" pbn_status pbn_rl_run(const pbn_plan* plan, const void* d_plan, uint64_t seed, uint32_t traj,
+                                  const pbn_targets* targets, uint32_t* d_state, uint64_t* d_counts,
+                                  uint32_t* d_record, uint32_t record_words, double precision, double conf,
+                                  double eps, uint32_t kmax, uint64_t initial_steps, uint64_t max_steps,
+                                  const pbn_launch_opts* launch, pbn_rl_out* out, void* stream) {
+  pbn::clear_error();
+  if (!plan || !d_plan || !targets || !d_state || !d_counts || !d_record || !out || record_words == 0)
+    return fail(PBN_EINVAL, "null argument");
+  const uint64_t cap = std::min<uint64_t>(32ull * record_words, max_steps);
+  if (cap >= 0xFFFFFFFFull) return fail(PBN_ERANGE, "max_steps must stay below 2^32");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  pbn_status st = hip_check(hipMemsetAsync(d_record, 0, 4ull * record_words, s), "hipMemsetAsync");
+  if (st == PBN_OK)
+    st = hip_check(hipMemsetAsync(d_counts, 0, 24ull * targets->ntargets, s), "hipMemsetAsync");
+  if (st == PBN_OK) st = pbn_state_init(plan, d_plan, seed, traj, 1, d_state, stream);
+  if (st != PBN_OK) return st;
+  pbn_launch_opts lo{};
+  if (launch) lo = *launch;
+  lo.record_traj = 1;
+  lo.record_words = record_words;
+  lo.d_record = d_record;
+  std::vector<uint32_t> host;
+  uint64_t done = 0, want = std::max<uint64_t>(std::min(initial_steps, cap), 64);
+  for (;;) {
+    want = std::min(want, cap);
+    while (done < want) {   // launches of at most 2^24 steps
+      const uint32_t chunk = uint32_t(std::min<uint64_t>(want - done, 1ull << 24));
+      st = simulate_common(plan->has_table == 0, plan, d_plan, seed, traj, 1, uint32_t(done), chunk, 0, targets,
+                           d_state, d_counts, &lo, stream);
+      if (st != PBN_OK) return st;
+      done += chunk;
+    }
+    const size_t words = size_t((done + 31) / 32);
+    host.resize(words);
+    st = hip_check(hipMemcpyAsync(host.data(), d_record, 4 * words, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    if (st == PBN_OK) st = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (st == PBN_OK) st = pbn_rl_diagnose(host.data(), done, precision, conf, eps, kmax, out);
+    if (st != PBN_OK) return st;
+    const double need = out->burn_in + out->n_required;
+    if (std::isfinite(need) && double(done) >= need) return PBN_OK;
+    if (done >= cap)
+      return fail(PBN_ERANGE, "the sample size the diagnosis asks for exceeds max_steps or the record buffer");
+    // extend to the diagnosed burn-in + sample size (doubling while the chain
+    // has not changed state yet)
+    want = std::isfinite(need) ? std::max<uint64_t>(uint64_t(std::ceil(need)), done + 1) : 2 * done;
+  }
 }
 
 extern "C" pbn_status pbn_state_to_original(const pbn_plan* plan, const void* d_plan, const uint32_t* d_state,

@@ -145,3 +145,99 @@ extern "C" pbn_status pbn_estimate(const uint64_t* counts, uint32_t units, uint6
   }
   return PBN_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Raftery and Lewis (1992), single chain, on a recorded hit-indicator sequence
+// (bit t of the words = z_t).  Thinning k: the smallest k whose k-thinned
+// sequence z_0, z_k, z_2k, ... prefers a first-order to a second-order Markov
+// chain: BIC = G^2 - 2 log(L - 2) < 0, G^2 the likelihood-ratio statistic of
+// the two models (two degrees of freedom), L the thinned length.  alpha and
+// beta are estimated on the k-thinned sequence; burn-in = m* k and required
+// sample size = N* k original steps (m*, N* as in pbn_estimate).
+
+namespace {
+
+inline uint32_t bit_at(const uint32_t* w, uint64_t t) { return (w[t >> 5] >> (t & 31u)) & 1u; }
+
+double g2_second_vs_first(const uint64_t n[2][2][2]) {
+  double g2 = 0.0;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      const double nij = double(n[i][j][0] + n[i][j][1]);
+      for (int l = 0; l < 2; ++l) {
+        const double nijl = double(n[i][j][l]);
+        if (nijl == 0) continue;
+        const double njl = double(n[0][j][l] + n[1][j][l]);
+        const double nj = double(n[0][j][0] + n[0][j][1] + n[1][j][0] + n[1][j][1]);
+        g2 += 2.0 * nijl * std::log((nijl / nij) / (njl / nj));
+      }
+    }
+  return g2;
+}
+
+}  // namespace
+
+extern "C" pbn_status pbn_rl_diagnose(const uint32_t* bits, uint64_t nbits, double precision, double conf,
+                                      double eps, uint32_t kmax, pbn_rl_out* out) {
+  pbn::clear_error();
+  if (!bits || !out || nbits < 3 || kmax < 1) return fail(PBN_EINVAL, "bad argument");
+  if (!(conf > 0 && conf < 1) || !(precision > 0) || !(eps > 0)) return fail(PBN_EINVAL, "bad precision/confidence");
+  uint32_t k = kmax;
+  double g2 = std::numeric_limits<double>::quiet_NaN(), bic = g2;
+  for (uint32_t kk = 1; kk <= kmax; ++kk) {
+    const uint64_t L = (nbits + kk - 1) / kk;   // thinned length
+    if (L < 3) break;
+    uint64_t n[2][2][2] = {};
+    uint32_t a = bit_at(bits, 0), b = bit_at(bits, kk);
+    for (uint64_t s = 2; s < L; ++s) {
+      const uint32_t c = bit_at(bits, s * kk);
+      ++n[a][b][c];
+      a = b;
+      b = c;
+    }
+    g2 = g2_second_vs_first(n);
+    bic = g2 - 2.0 * std::log(double(L - 2));
+    if (bic < 0) {
+      k = kk;
+      break;
+    }
+  }
+  const uint64_t L = (nbits + k - 1) / k;
+  uint64_t n01 = 0, n10 = 0, n0 = 0, n1 = 0;
+  for (uint64_t s = 0; s + 1 < L; ++s) {
+    const uint32_t a = bit_at(bits, s * k), b = bit_at(bits, (s + 1) * k);
+    if (a == 0) {
+      ++n0;
+      n01 += b;
+    } else {
+      ++n1;
+      n10 += 1u - b;
+    }
+  }
+  const double alpha = n0 ? double(n01) / double(n0) : 0.0, beta = n1 ? double(n10) / double(n1) : 0.0;
+  out->k = k;
+  out->reserved = 0;
+  out->g2 = g2;
+  out->bic = bic;
+  out->alpha = alpha;
+  out->beta = beta;
+  out->n_required = std::numeric_limits<double>::infinity();
+  out->burn_in = std::numeric_limits<double>::infinity();
+  out->p_hat = std::numeric_limits<double>::quiet_NaN();
+  out->steps = nbits;
+  if (alpha + beta > 0) {
+    const double z = normal_quantile(0.5 + conf / 2);
+    const double nstar = alpha * beta * (2 - alpha - beta) / std::pow(alpha + beta, 3) * (z / precision) * (z / precision);
+    const double lam = std::fabs(1 - alpha - beta);
+    const double mstar = lam == 0 ? 1.0 : std::log(eps * (alpha + beta) / std::fmax(alpha, beta)) / std::log(lam);
+    out->n_required = nstar * k;
+    out->burn_in = mstar * k;
+    const uint64_t first = uint64_t(std::ceil(out->burn_in));
+    if (first < nbits) {
+      uint64_t ones = 0;
+      for (uint64_t t = first; t < nbits; ++t) ones += bit_at(bits, t);
+      out->p_hat = double(ones) / double(nbits - first);
+    }
+  }
+  return PBN_OK;
+}

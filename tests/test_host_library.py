@@ -1,6 +1,7 @@
 """CPU tests of the C-ABI library: it loads, exports every declared symbol, and
 its host-side preparation agrees with the oracle (integer work: bit-exact)."""
 import ctypes
+import math
 import os
 import re
 
@@ -299,3 +300,48 @@ def test_fn_records_decode_to_the_network(which, budget):
             bits = [(int(img[tt + (x >> 3)]) >> (x & 7)) & 1 for x in range(1 << len(pars))]
             want = [int(net["tt"][net["tt_off"][f] + x // 64]) >> (x % 64) & 1 for x in range(1 << len(pars))]
             assert bits == want
+
+
+def _pack_bits(z):
+    z = np.asarray(z, dtype=np.uint32)
+    words = np.zeros((z.size + 31) // 32, dtype=np.uint32)
+    for b in range(32):
+        part = z[b::32]
+        words[: part.size] |= part << np.uint32(b)
+    return words
+
+
+@pytest.mark.parametrize("kind", ["first", "second", "iid", "constant", "short"])
+def test_rl_diagnosis_matches_oracle(kind):
+    from oracle import stats as ost
+    rng = np.random.default_rng(21)
+    if kind == "first":
+        z = np.zeros(60001, dtype=int)
+        u = rng.random(z.size)
+        for t in range(1, z.size):
+            z[t] = (u[t] < 0.03) if z[t - 1] == 0 else (u[t] >= 0.1)
+    elif kind == "second":
+        z = [0, 0]
+        for _ in range(80000):
+            p = 0.9 if (z[-1] == 1 and z[-2] == 1) else (0.5 if z[-1] == 1 else 0.02)
+            z.append(int(rng.random() < p))
+        z = np.asarray(z)
+    elif kind == "iid":
+        z = (rng.random(33333) < 0.2).astype(int)
+    elif kind == "constant":
+        z = np.ones(5000, dtype=int)
+    else:
+        z = np.array([0, 1, 1, 0, 1])
+    got = api.rl_diagnose(_pack_bits(z), z.size, 1e-3, conf=0.95, eps=1e-3, kmax=50)
+    want = ost.rl92_diagnose(z, 1e-3, conf=0.95, eps=1e-3, kmax=50)
+    assert got["k"] == want["k"] and got["steps"] == z.size
+    for key in ("g2", "bic", "alpha", "beta", "burn_in", "n_required", "p_hat"):
+        a, b = got[key], want[key]
+        if math.isnan(b):
+            assert math.isnan(a), key
+        elif math.isinf(b):
+            assert a == b, key
+        else:
+            assert a == pytest.approx(b, rel=1e-9, abs=1e-12), key
+    with pytest.raises(_lib.PbnError):
+        api.rl_diagnose(_pack_bits(z), 2, 1e-3)
