@@ -266,6 +266,39 @@ def bench_serve(args):
     print(json.dumps(out))
 
 
+def bench_rl(args):
+    """The paper's estimation procedure end to end on one trajectory: simulate,
+    record the target indicator, diagnose (thinning, burn-in, sample size) and
+    extend until the run is long enough (pbn_rl_run)."""
+    cfg = ps.config(args.config)
+    n = cfg.net["n"]
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(args.config, 1, 20000)
+    import torch
+    from paper_1605_00854_amd import api
+    torch.cuda.set_device(0)
+    interest = sorted({a for tg in cfg.targets for a, _ in tg})
+    plan = api.Plan(cfg.net, interest=interest, reduce=1, group=0)
+    api.rl_run(plan, cfg.seed + 1, cfg.targets, 0.05, initial_steps=1000, max_steps=1 << 20)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, _ = api.rl_run(plan, cfg.seed, cfg.targets, args.rl, initial_steps=100000, max_steps=(1 << 32) - 2)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = {"metric": "two-state Markov chain estimate on 1 MI355X: simulated steps/s of the driver",
+           "value": res["steps"] / dt, "unit": "steps/s (one trajectory)", "n_gpus": 1, "steps": 1, "warmup": 1,
+           "ms_per_step": 1e3 * dt, "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
+           "dtype": "u32", "data": "synthetic",
+           "config": {"workload": f"{args.config}: one trajectory to precision {args.rl} at confidence 0.95 "
+                                  f"(n = {n})", "plan": {"reduce": 1, "group": 0}},
+           "result": {k: res[k] for k in ("status", "k", "alpha", "beta", "burn_in", "n_required", "p_hat",
+                                          "steps")},
+           "node_updates_per_s": res["steps"] * n / dt, "seconds": dt,
+           "cpu_baseline": cpu}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -283,12 +316,17 @@ def main():
                     help="product plan: autotuned, or a fixed preparation (profiling runs)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB copied once by a plain device copy (HBM counter calibration in profiles)")
+    ap.add_argument("--rl", type=float, default=0.0,
+                    help="run the two-state Markov chain (Raftery-Lewis) driver on one trajectory of the "
+                         "config to this precision instead of the fixed-length workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is design-only "
                                    "(trajectories shard by id, counters reduce with one integer all-reduce)"}))
         sys.exit(2)
 
+    if args.rl:
+        return bench_rl(args)
     if args.config == "C4":
         return bench_batch(args)
     if args.config == "C5":
