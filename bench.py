@@ -266,6 +266,51 @@ def bench_serve(args):
     print(json.dumps(out))
 
 
+def bench_planner_fit(args):
+    """Speedup of the autotuned plan over the plain kernel on synthetic networks
+    spread over the paper's leaf-fraction and density ranges; Equation 7's
+    form fit to them (R^2, 10-fold cross-validated R^2, held-out R^2)."""
+    import torch
+    from paper_1605_00854_amd import api, autotune, planner
+    torch.cuda.set_device(0)
+    ntraj, probe = 2048, 1000
+    rows = {}
+    for label, nets in (("fit", ps.planner_population(args.planner_fit, 2007)),
+                        ("held_out", ps.planner_population(max(3, args.planner_fit // 3), 2008))):
+        xs1, xs2, ys = [], [], []
+        for k, net in enumerate(nets):
+            tg = [ps.non_leaf_targets(net, 3)]
+            interest = [a for a, _ in tg[0]]
+            x1, x2, _ = planner.features(net, interest)
+            plain = api.Plan(net, interest=interest, reduce=0, group=0)
+            dt = autotune._probe(torch, plain, plain.targets(tg), 7, ntraj, probe, 4, True)
+            r_plain = ntraj * probe * net["n"] / dt
+            _, _, trials = autotune.tune(net, interest, tg, ntraj, seed=7, probe_steps=probe, quick=True,
+                                         key=(label, k))
+            r_best = max(t["node_updates_per_s"] for t in trials if "node_updates_per_s" in t)
+            xs1.append(x1)
+            xs2.append(x2)
+            ys.append(max(r_best, r_plain) / r_plain)
+            print(f"[planner] {label} {k} n={net['n']} leaf={x1:.3f} D={x2:.2f} speedup={ys[-1]:.3f}",
+                  file=sys.stderr, flush=True)
+        rows[label] = (np.array(xs1), np.array(xs2), np.array(ys))
+    x1, x2, y = rows["fit"]
+    coeffs, r2 = planner.fit(x1, x2, y)
+    cv = planner.cross_validated_r2(x1, x2, y)
+    h1, h2, hy = rows["held_out"]
+    hp = planner.predict(h1, h2, coeffs)
+    hr2 = 1.0 - float(((hy - hp) ** 2).sum()) / float(((hy - hy.mean()) ** 2).sum())
+    out = {"metric": "planner speedup model (Equation 7 form) refit on MI355X", "value": r2, "unit": "R^2",
+           "n_gpus": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{args.planner_fit} + {h1.size} synthetic networks, {ntraj} trajectories, "
+                                  f"{probe}-step probes"},
+           "coeffs": coeffs, "r2": r2, "cv10_r2": cv, "held_out_r2": hr2,
+           "held_out_mean_abs_error": float(np.abs(hy - hp).mean()),
+           "speedup_range": [float(y.min()), float(y.max())],
+           "rows": {k: [list(map(float, v)) for v in r] for k, r in rows.items()}}
+    print(json.dumps(out))
+
+
 def bench_rl(args):
     """The paper's estimation procedure end to end on one trajectory: simulate,
     record the target indicator, diagnose (thinning, burn-in, sample size) and
@@ -316,6 +361,9 @@ def main():
                     help="product plan: autotuned, or a fixed preparation (profiling runs)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB copied once by a plain device copy (HBM counter calibration in profiles)")
+    ap.add_argument("--planner-fit", type=int, default=0,
+                    help="refit the planner's speedup model on this many synthetic networks (plus a third "
+                         "as many held out) and report the fit")
     ap.add_argument("--rl", type=float, default=0.0,
                     help="run the two-state Markov chain (Raftery-Lewis) driver on one trajectory of the "
                          "config to this precision instead of the fixed-length workload")
@@ -325,6 +373,8 @@ def main():
                                    "(trajectories shard by id, counters reduce with one integer all-reduce)"}))
         sys.exit(2)
 
+    if args.planner_fit:
+        return bench_planner_fit(args)
     if args.rl:
         return bench_rl(args)
     if args.config == "C4":

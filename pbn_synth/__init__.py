@@ -172,6 +172,21 @@ def with_detached_modules(core, modules, size, seed, nparents=(2, 4)):
     return net
 
 
+def planner_population(count, seed):
+    """Networks spread over the ranges of the paper's experiments (Section
+    4.1): n ~ U[100, 1500], leaf fraction ~ U[0, 0.9], 1..lmax predictors of
+    1..kmax parents (lmax ~ U{1..4}, kmax ~ U{1..6}), p = 1e-3."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k in range(count):
+        n = int(rng.integers(100, 1501))
+        leaf = float(rng.uniform(0.0, 0.9))
+        lmax, kmax = int(rng.integers(1, 5)), int(rng.integers(1, 7))
+        out.append(random_pbn(n, 1e-3, seed * 1000 + k, nfn=_uniform_int(1, lmax), nparents=_uniform_int(1, kmax),
+                              leaf_frac=leaf))
+    return out
+
+
 def batch_c4(count=512, seed=1004):
     """Uneven batch: n ~ U[20, 1500] with the medium generator, p in {1e-3, 1e-4}."""
     rng = np.random.Generator(np.random.PCG64(seed))
