@@ -138,6 +138,15 @@ pbn_status pbn_net_tables(const pbn_net* net, uint64_t* q, uint32_t* cum, int32_
  *   max_table_entries  cap on (product of l) * 2^|union parents| per group
  *   max_parent_bits    cap on |union parents| per group (<= PBN_MAX_GROUP_PARENTS)
  *   max_group_nodes    cap on nodes per group (<= PBN_MAX_GROUP_NODES)
+ *   sampling           0: the keyed draws (perturbation chain over all n
+ *                      nodes, one selection word per multi-predictor node:
+ *                      trajectories bit-identical whatever the reduction and
+ *                      grouping); 1: the paper's sampling (Algorithm 1's leaf
+ *                      draw, Algorithm 2's group perturbation through one alias
+ *                      table of 2^k patterns, k <= 16, and one alias draw per
+ *                      selecting slot over its (combined) predictor functions,
+ *                      Sections 2.2, 3.2, 3.3): same distribution, different
+ *                      draws; not supported by the batch entry points
  * Errors: PBN_EINVAL (bad node id, bad option), PBN_ELIMIT (a node needs a
  * table larger than max_table_entries), PBN_ELDS (layout exceeds device
  * limits), PBN_ENOMEM.
@@ -151,7 +160,7 @@ typedef struct pbn_plan_opts {
   uint32_t max_table_entries;
   uint32_t max_parent_bits;
   uint32_t max_group_nodes;
-  uint32_t reserved;
+  uint32_t sampling;
 } pbn_plan_opts;
 
 /* Defaults: reduce = 1, group = 1, weight_mode = 1, theta = 65536,

@@ -176,11 +176,16 @@ def combined_probs(net, members):
     return out
 
 
-def alias_plan(net, interest, reduce=1, group=0, theta=65536, weight_mode=1):
+def alias_plan(net, interest, reduce=1, group=0, theta=65536, weight_mode=1, caps=None):
     """What the draws of alias sampling depend on: the kept nodes (Definition 1
     for reduce=1, the interest nodes' ancestors for reduce=2, all for 0), the
     selecting groups (Algorithm 4 over the kept multi-predictor nodes when
-    grouping, else one per node) and the tables."""
+    grouping, else one per node) and the tables.
+
+    caps = (max_nodes, max_bits, max_entries): a simulator's limits on a
+    group's members, union parents and combined-table entries; a group of
+    Algorithm 4 beyond them gives up its first (heaviest) member as a group of
+    its own until it fits."""
     n = int(net["n"])
     if reduce == 1:
         removed = structure.leaf_nodes(net, interest)
@@ -198,6 +203,22 @@ def alias_plan(net, interest, reduce=1, group=0, theta=65536, weight_mode=1):
             w = int(nfn[v]) * (2 ** len(par) if weight_mode == 1 else 1)
             items.append((v, min(w, structure.SATURATE)))
         groups = [g for g in structure.partition_multi(items, theta) if g]
+        if caps is not None:
+            max_nodes, max_bits, max_entries = caps
+
+            def fits(members):
+                union = set(p for v in members for pa, _ in structure.node_functions(net, v) for p in pa)
+                entries = int(np.prod([int(nfn[v]) for v in members])) << len(union)
+                return len(members) <= max_nodes and len(union) <= max_bits and entries <= max_entries
+
+            capped = []
+            for members in groups:
+                members = list(members)
+                while len(members) > 1 and not fits(members):
+                    capped.append([members[0]])
+                    members = members[1:]
+                capped.append(members)
+            groups = capped
     else:
         groups = [[v] for v in multi]
     groups.sort(key=min)

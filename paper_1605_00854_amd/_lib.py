@@ -29,7 +29,7 @@ class pbn_plan_opts(C.Structure):
     _fields_ = [("reduce", C.c_uint32), ("group", C.c_uint32), ("weight_mode", C.c_uint32),
                 ("lds_budget_bytes", C.c_uint32), ("theta", C.c_uint64),
                 ("max_table_entries", C.c_uint32), ("max_parent_bits", C.c_uint32),
-                ("max_group_nodes", C.c_uint32), ("reserved", C.c_uint32)]
+                ("max_group_nodes", C.c_uint32), ("sampling", C.c_uint32)]
 
 
 class pbn_plan_info(C.Structure):

@@ -85,6 +85,7 @@ __device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgc
 // the global address space so that the loads are global, not flat, loads
 // (flat loads would also wait on outstanding LDS traffic).
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 #define PBN_GLOBAL_AS __attribute__((address_space(1)))
 template <bool G>
 __device__ __forceinline__ uint4 img_u4(const uint8_t* p) {
@@ -115,6 +116,15 @@ __device__ __forceinline__ uint32_t blob_u32(const uint32_t* p) {
     return *(const PBN_GLOBAL_AS uint32_t*)(p);
   else
     return *p;
+}
+template <bool G>
+__device__ __forceinline__ uint2 img_u2(const uint8_t* p) {
+  if constexpr (G) {
+    const u32x2 v = *(const PBN_GLOBAL_AS u32x2*)(p);
+    return make_uint2(v.x, v.y);
+  } else {
+    return *reinterpret_cast<const uint2*>(p);
+  }
 }
 template <bool G>
 __device__ __forceinline__ uint32_t img_u8(const uint8_t* p) {
@@ -235,6 +245,17 @@ __device__ __forceinline__ uint32_t choose_neg(uint32_t w, const NegThr& n) {
   return 3u + borrow_hi(w, n.c0) + borrow_hi(w, n.c1) + borrow_hi(w, n.c2);
 }
 
+// Alias draw (Walker's method, Section 2.2) from one 32-bit word w over a
+// table of L columns at `tab` (8-byte entries {threshold, alias}): the column
+// is the high word of w * L, kept when the low word is below its threshold.
+template <bool G>
+__device__ __forceinline__ uint32_t alias_pick(const uint8_t* tab, uint32_t w, uint32_t L) {
+  const unsigned long long prod = (unsigned long long)w * L;
+  const uint32_t col = uint32_t(prod >> 32);
+  const uint2 e = img_u2<G>(tab + 8u * col);
+  return uint32_t(prod) < e.x ? col : e.y;
+}
+
 // Layout of a plan's FN records (header fields) and the zero-position pair.
 struct FnFmt {
   uint32_t units;     // 16-byte units per record
@@ -347,10 +368,16 @@ __device__ __forceinline__ void load_slot(SlotRegs<Shape<PM, UM>::XW, Shape<PM, 
 template <int PM, int UM, int MODE>
 __device__ __forceinline__ uint32_t eval_table(const SlotRegs<Shape<PM, UM>::XW, Shape<PM, UM>::TTW>& r,
                                                const uint8_t* img, const uint8_t* cs, const uint8_t* rs) {
-  constexpr bool G = (MODE & 2) != 0;
+  constexpr bool G = (MODE & 2) != 0, ALIAS = (MODE & 4) != 0;
   uint32_t c = 0;
   const uint32_t nm = PBN_SLOT_NMULTI(r.info);
-  for (uint32_t m = 0; m < nm; ++m) {
+  if constexpr (ALIAS) {
+    // one draw over the group's combined functions: record {word offset, L, ...}
+    if (nm) {
+      const uint2 hd = img_u2<G>(img + r.choice);
+      c = alias_pick<G>(img + r.choice + 16u, *reinterpret_cast<const uint32_t*>(rs + hd.x), hd.y);
+    }
+  } else for (uint32_t m = 0; m < nm; ++m) {
     const uint4 ch = img_u4<G>(img + r.choice + 16u * m);
     const uint32_t w = *reinterpret_cast<const uint32_t*>(rs + (ch.x & 0xFFFFFFu));
     c += choose(w, ch.y, ch.z, ch.w, ch.x >> 24) * ((r.radix >> (8u * m)) & 0xFFu);
@@ -376,7 +403,11 @@ __device__ __forceinline__ uint32_t eval_slot(const SlotRegs<Shape<PM, UM>::XW, 
   for (int k = 0; k < TTW; ++k) f.tt[k] = r.tt[k];
   if (PBN_SLOT_NMULTI(r.info)) {
     const uint32_t w = *reinterpret_cast<const uint32_t*>(rs + (r.draw & 0xFFFFFFu));
-    const uint32_t j = nt ? choose_neg(w, *nt) : choose(w, r.thr0, r.thr1, r.thr2, r.draw >> 24);
+    uint32_t j;
+    if constexpr ((MODE & 4) != 0)
+      j = alias_pick<(MODE & 2) != 0>(img + r.choice + 16u, w, r.thr0);   // alias record: {offset, L, ...}
+    else
+      j = nt ? choose_neg(w, *nt) : choose(w, r.thr0, r.thr1, r.thr2, r.draw >> 24);
     f = load_fn<PM, UM, MODE>(img, r.base, j, fm);
   }
   return eval_fn<PM, UM>(f, cs);
@@ -413,10 +444,13 @@ struct TrajArgs {
 // UM: union bits gathered per TABLE slot (0: no table slots);
 // NREG: lane passes whose slot data stay in registers (0: reload every pass);
 // MODE: bit 0, FN records of one or two units (batches of plans of both
-// kinds); bit 1, image reads through global-address-space pointers.
+// kinds); bit 1, image reads through global-address-space pointers; bit 2,
+// alias sampling (Algorithms 1, 2 and 5's per-group draws) instead of the
+// keyed draws.
 template <int PM, int UM, int NREG, int MODE>
 __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   constexpr int XW = Shape<PM, UM>::XW, TTW = Shape<PM, UM>::TTW;
+  constexpr bool ALIAS = (MODE & 4) != 0;
   constexpr int NR = NREG > 0 ? NREG : 1;
   // FN-only plans with register-held slots read target values from the pass
   // ballots (state byte b = bit b % 64 of pass b / 64's ballot)
@@ -525,9 +559,15 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   if (small_jobs) {
     const uint32_t j = lane % njobs;
     my_s = lane / njobs;
-    my_c2 = j ? blk[j - 1] : 0u;
-    my_c3 = j ? PBN_STREAM_SEL : PBN_STREAM_PERT;
+    my_c2 = ALIAS ? j : j ? blk[j - 1] : 0u;
+    my_c3 = ALIAS ? PBN_STREAM_ALIAS : j ? PBN_STREAM_SEL : PBN_STREAM_PERT;
   }
+  // alias sampling: Algorithm 2's groups, the pattern table, kept-node positions
+  const uint32_t ag = ALIAS ? H->alias_g : 0u, ak = ALIAS ? H->alias_k : 1u;
+  const uint32_t kmask_last = ALIAS ? (H->alias_kp >= 32u ? 0xFFFFFFFFu : (1u << H->alias_kp) - 1u) : 0u;
+  const uint32_t leaf_thr = ALIAS ? H->leaf_thr : 0u;
+  const uint8_t* pat = a.blob + (ALIAS ? H->pert_off : 0u);
+  const uint32_t* kpos = reinterpret_cast<const uint32_t*>(a.blob + (ALIAS ? H->kpos_off : 0u));
   uint32_t stride0 = 1;
   while (stride0 * 64u < n) stride0 *= 64u;
   const unsigned long long Qn = Q[n];
@@ -592,16 +632,51 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
       if (lane < scount * njobs) ring[lane] = philox(traj, t + my_s, my_c2, my_c3, k0, k1);
     } else {
       for (uint32_t j = lane; j < njobs; j += 64u)
-        ring[j] = philox(traj, t, j ? blk[j - 1] : 0u, j ? PBN_STREAM_SEL : PBN_STREAM_PERT, k0, k1);
+        ring[j] = ALIAS ? philox(traj, t, j, PBN_STREAM_ALIAS, k0, k1)
+                        : philox(traj, t, j ? blk[j - 1] : 0u, j ? PBN_STREAM_SEL : PBN_STREAM_PERT, k0, k1);
     }
     wave_sync();
+    if constexpr (ALIAS) {
+      // Resolve the fill's perturbation draws ahead of the steps (they do not
+      // depend on the state): word 1 of a step becomes its perturbed flag
+      // (Algorithm 1's leaf draw, then any nonzero group pattern), words
+      // 2 + 2q the patterns of Algorithm 2 (the last one masked to k' nodes).
+      uint32_t* rw = reinterpret_cast<uint32_t*>(ring);
+      const uint32_t spw = 4u * njobs;
+      for (uint32_t s = lane; s < scount; s += 64u) rw[s * spw + 1u] = rw[s * spw] > leaf_thr ? 1u : 0u;
+      wave_sync();
+      for (uint32_t i = lane; i < scount * ag; i += 64u) {
+        const uint32_t s = i / ag, q = i - s * ag;
+        uint32_t* sw = rw + s * spw;
+        const uint2 d = *reinterpret_cast<const uint2*>(sw + 2u + 2u * q);
+        const uint32_t col = d.x >> (32u - ak);
+        const uint2 e = img_u2<true>(pat + 8u * col);
+        uint32_t c = d.y < e.x ? col : e.y;
+        if (q == ag - 1u) c &= kmask_last;
+        sw[2u + 2u * q] = c;
+        if (c) sw[1] = 1u;
+      }
+      wave_sync();
+    }
     for (uint32_t s = 0; s < scount; ++s, ++t) {
       const uint8_t* rs = reinterpret_cast<const uint8_t*>(ring + s * njobs);
       const uint2 pr = *reinterpret_cast<const uint2*>(rs);
       const uint32_t ulo = uniform(pr.x), uhi = uniform(pr.y);
       uint8_t* csb = reinterpret_cast<uint8_t*>(cur ? sbuf1 : sbuf0);
       bool z = false;
-      if (uhi > qn_hi || (uhi == qn_hi && ulo >= qn_lo)) {
+      if (ALIAS && uhi != 0u) {
+        // perturbation-only step (Algorithm 5): flip the nodes of every
+        // group's pattern in place; pattern bit b of group q is kept node q k + b
+        const uint32_t* rw = reinterpret_cast<const uint32_t*>(rs);
+        for (uint32_t q = lane; q < ag; q += 64u) {
+          for (uint32_t c = rw[2u + 2u * q]; c; c &= c - 1u) {
+            const uint32_t pos = blob_u32<true>(kpos + q * ak + uint32_t(__builtin_ctz(c)));
+            csb[pos] ^= 1u;
+          }
+        }
+        wave_sync();
+        z = target_z(csb);
+      } else if (!ALIAS && (uhi > qn_hi || (uhi == qn_hi && ulo >= qn_lo))) {
         // u >= Q[n]: perturbation-only step; walk the skip chain over all n
         // original nodes, flipping kept nodes in place
         unsigned long long u = (static_cast<unsigned long long>(uhi) << 32) | ulo;
@@ -682,8 +757,9 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
 }
 
 // One network: one wavefront per trajectory, the plan image staged in LDS when
-// it fits (IMG_LDS), shared by the workgroup's waves.
-template <bool IMG_LDS, int PM, int UM, int NREG>
+// it fits (IMG_LDS), shared by the workgroup's waves.  ALIAS: the plan's alias
+// sampling draws.
+template <bool IMG_LDS, int PM, int UM, int NREG, bool ALIAS>
 __global__ void __launch_bounds__(1024) k_simulate(SimParams a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   const pbn_plan_header* H = reinterpret_cast<const pbn_plan_header*>(a.blob);
@@ -718,7 +794,7 @@ __global__ void __launch_bounds__(1024) k_simulate(SimParams a) {
   t.tg = &a.tg;
   t.record = a.record && tl < a.record_traj ? a.record + size_t(tl) * a.record_words : nullptr;
   t.record_words = a.record_words;
-  run_traj<PM, UM, NREG, 0>(t);
+  run_traj<PM, UM, NREG, ALIAS ? 4 : 0>(t);
 }
 
 // ---------------------------------------------------------------- batches
@@ -858,9 +934,9 @@ uint32_t wave_lds_bytes(const pbn_plan* plan) {
   return 8u * ((plan->state_dwords + 3u) & ~3u) + 16u * ring;
 }
 
-template <bool IMG_LDS, int PM, int UM, int NREG>
+template <bool IMG_LDS, int PM, int UM, int NREG, bool ALIAS>
 pbn_status launch_sim(const SimParams& p, uint32_t blocks, uint32_t lds, hipStream_t stream) {
-  auto* fn = k_simulate<IMG_LDS, PM, UM, NREG>;
+  auto* fn = k_simulate<IMG_LDS, PM, UM, NREG, ALIAS>;
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -873,25 +949,25 @@ pbn_status launch_sim(const SimParams& p, uint32_t blocks, uint32_t lds, hipStre
 }
 
 // Instantiation choice: the smallest gather widths that cover the plan.
-template <bool IMG_LDS, int PM, int UM>
+template <bool IMG_LDS, int PM, int UM, bool ALIAS>
 pbn_status dispatch_nreg(const SimParams& p, uint32_t npass, uint32_t blocks, uint32_t lds, hipStream_t s) {
-  if (npass == 1) return launch_sim<IMG_LDS, PM, UM, 1>(p, blocks, lds, s);
-  if (npass == 2) return launch_sim<IMG_LDS, PM, UM, 2>(p, blocks, lds, s);
-  return launch_sim<IMG_LDS, PM, UM, 0>(p, blocks, lds, s);
+  if (npass == 1) return launch_sim<IMG_LDS, PM, UM, 1, ALIAS>(p, blocks, lds, s);
+  if (npass == 2) return launch_sim<IMG_LDS, PM, UM, 2, ALIAS>(p, blocks, lds, s);
+  return launch_sim<IMG_LDS, PM, UM, 0, ALIAS>(p, blocks, lds, s);
 }
 
-template <bool IMG_LDS, int PM>
+template <bool IMG_LDS, int PM, bool ALIAS>
 pbn_status dispatch_um(const SimParams& p, uint32_t umax, uint32_t npass, uint32_t blocks, uint32_t lds, hipStream_t s) {
-  if (umax == 0) return dispatch_nreg<IMG_LDS, PM, 0>(p, npass, blocks, lds, s);
-  if (umax <= 8) return dispatch_nreg<IMG_LDS, PM, 8>(p, npass, blocks, lds, s);
-  return dispatch_nreg<IMG_LDS, PM, 16>(p, npass, blocks, lds, s);
+  if (umax == 0) return dispatch_nreg<IMG_LDS, PM, 0, ALIAS>(p, npass, blocks, lds, s);
+  if (umax <= 8) return dispatch_nreg<IMG_LDS, PM, 8, ALIAS>(p, npass, blocks, lds, s);
+  return dispatch_nreg<IMG_LDS, PM, 16, ALIAS>(p, npass, blocks, lds, s);
 }
 
-template <bool IMG_LDS>
+template <bool IMG_LDS, bool ALIAS>
 pbn_status dispatch_pm(const SimParams& p, uint32_t pmax, uint32_t umax, uint32_t npass, uint32_t blocks, uint32_t lds,
                        hipStream_t s) {
-  if (pmax <= 5) return dispatch_um<IMG_LDS, 5>(p, umax, npass, blocks, lds, s);
-  return dispatch_um<IMG_LDS, 7>(p, umax, npass, blocks, lds, s);
+  if (pmax <= 5) return dispatch_um<IMG_LDS, 5, ALIAS>(p, umax, npass, blocks, lds, s);
+  return dispatch_um<IMG_LDS, 7, ALIAS>(p, umax, npass, blocks, lds, s);
 }
 
 pbn_status simulate_common(bool plain, const pbn_plan* plan, const void* d_plan, uint64_t seed, uint32_t traj0,
@@ -946,8 +1022,11 @@ pbn_status simulate_common(bool plain, const pbn_plan* plan, const void* d_plan,
   if (pmax > 7 || umax > 16) return fail(PBN_ELDS, "plan exceeds the kernel's gather widths");
   const uint32_t units = reinterpret_cast<const pbn_plan_header*>(plan->blob.data())->fn_units;
   if (units != (pmax > 5 ? 2u : 1u)) return fail(PBN_EINVAL, "plan FN record format does not match its parent count");
-  return img_lds ? dispatch_pm<true>(p, pmax, umax, npass, blocks, lds, s)
-                 : dispatch_pm<false>(p, pmax, umax, npass, blocks, lds, s);
+  if (plan->sampling)
+    return img_lds ? dispatch_pm<true, true>(p, pmax, umax, npass, blocks, lds, s)
+                   : dispatch_pm<false, true>(p, pmax, umax, npass, blocks, lds, s);
+  return img_lds ? dispatch_pm<true, false>(p, pmax, umax, npass, blocks, lds, s)
+                 : dispatch_pm<false, false>(p, pmax, umax, npass, blocks, lds, s);
 }
 
 }  // namespace
@@ -1056,6 +1135,7 @@ pbn_status batch_shape(const pbn_plan* const* plans, uint32_t nitems, BatchShape
   for (uint32_t k = 0; k < nitems; ++k) {
     const pbn_plan* p = plans[k];
     if (!p) return fail(PBN_EINVAL, "null plan in batch");
+    if (p->sampling) return fail(PBN_EINVAL, "alias-sampling plans are not supported by the batch entry points");
     if (p->info.max_fn_parents > 7 || p->info.max_union_bits > 16)
       return fail(PBN_ELDS, "plan exceeds the kernel's gather widths");
     if (p->info.max_fn_parents > 5) sh.pm = 7;
@@ -1124,6 +1204,7 @@ extern "C" pbn_status pbn_batch_tasks(const pbn_plan* const* plans, const uint32
   std::vector<uint32_t> order(nitems);
   for (uint32_t k = 0; k < nitems; ++k) {
     if (!plans[k]) return fail(PBN_EINVAL, "null plan in batch");
+    if (plans[k]->sampling) return fail(PBN_EINVAL, "alias-sampling plans are not supported by the batch entry points");
     order[k] = k;
   }
   std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {

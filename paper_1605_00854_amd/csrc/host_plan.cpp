@@ -68,6 +68,38 @@ std::vector<uint32_t> union_of(const std::vector<std::vector<uint32_t>>& P, cons
   return u;
 }
 
+// Walker's alias method by Vose's construction (Section 2.2): column i of a
+// uniformly drawn column is kept with probability keep[i], else it yields
+// alias[i].  Stacks in ascending index order, popped from the back; the keep
+// probability is stored as the 32-bit threshold floor(keep 2^32) (at most
+// 2^32 - 1) that a drawn 32-bit coin must stay below.
+void vose_table(const std::vector<double>& probs, std::vector<uint32_t>& thr, std::vector<uint32_t>& alias) {
+  const size_t L = probs.size();
+  std::vector<double> scaled(L), keep(L, 0.0);
+  alias.assign(L, 0);
+  std::vector<uint32_t> small, large;
+  for (size_t i = 0; i < L; ++i) {
+    scaled[i] = probs[i] * double(L);
+    (scaled[i] < 1.0 ? small : large).push_back(uint32_t(i));
+  }
+  while (!small.empty() && !large.empty()) {
+    const uint32_t sm = small.back(), lg = large.back();
+    small.pop_back();
+    large.pop_back();
+    keep[sm] = scaled[sm];
+    alias[sm] = lg;
+    scaled[lg] = scaled[lg] + scaled[sm] - 1.0;
+    (scaled[lg] < 1.0 ? small : large).push_back(lg);
+  }
+  for (uint32_t i : large) keep[i] = 1.0, alias[i] = i;
+  for (uint32_t i : small) keep[i] = 1.0, alias[i] = i;
+  thr.resize(L);
+  for (size_t i = 0; i < L; ++i) {
+    const double x = std::floor(keep[i] * 4294967296.0);
+    thr[i] = x >= 4294967295.0 ? 0xFFFFFFFFu : uint32_t(x);
+  }
+}
+
 // Definition 1: iterated removal of nodes that are not of interest and have no
 // remaining children.  Returns removed[v].
 std::vector<uint8_t> leaf_nodes(const pbn_net& g, const std::vector<uint8_t>& interest,
@@ -386,6 +418,32 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
     return (1 + bi) * 16 + (r & 3) * 4;
   };
 
+  // ---- alias sampling (Algorithms 1, 2 and 5's per-group draws): selecting
+  // slots numbered by their smallest member id; their draw words follow the
+  // leaf word, an unused word and the 2 g pattern words
+  const bool alias_mode = o.sampling == 1;
+  const uint32_t nk = uint32_t(kept.size());
+  const uint32_t ag = (nk + 15) / 16, ak = (nk + ag - 1) / ag, akp = nk - ak * (ag - 1);
+  std::vector<uint32_t> sel_index(ns, PBN_NONE), sel_L(ns, 0);
+  uint32_t n_sel = 0;
+  size_t alias_bytes = 0;
+  if (alias_mode) {
+    std::vector<std::pair<uint32_t, uint32_t>> order;   // (smallest member id, slot)
+    for (uint32_t s = 0; s < ns; ++s) {
+      uint64_t L = 1;
+      bool multi = false;
+      for (uint32_t v : slots[s].members)
+        if (g.nfn(v) > 1) multi = true, L *= g.nfn(v);
+      if (!multi) continue;
+      if (L > (1u << 20)) return fail(PBN_ELIMIT, "slot %u draws among %llu combined functions", s, (unsigned long long)L);
+      sel_L[s] = uint32_t(L);
+      order.emplace_back(*std::min_element(slots[s].members.begin(), slots[s].members.end()), s);
+      alias_bytes += align16(16 + 8 * size_t(L));
+    }
+    std::sort(order.begin(), order.end());
+    for (const auto& it : order) sel_index[it.second] = n_sel++;
+  }
+
   // ---- image layout
   // FN records: 16 bytes when every FN slot reads at most 5 parents (one
   // 16-byte unit: 5 positions and a 32-entry table), else 32 bytes (two units:
@@ -424,10 +482,11 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   }
   const size_t choice_base = slot_bytes;
   const size_t fn_base = (choice_base + 16 * nchoice + 127) & ~size_t(127);
-  const size_t swz_bytes = fn_base + 128 * size_t(rows) + tab_bytes;
+  const size_t swz_bytes = fn_base + 128 * size_t(rows) + tab_bytes + alias_bytes;
   const bool swz = swz_bytes <= o.lds_budget_bytes;
   const size_t tab_base = fn_base + (swz ? 128 * size_t(rows) : 16 * size_t(units) * (nfnrec + 1));
-  const size_t image_bytes = tab_base + tab_bytes;
+  const size_t alias_base = tab_base + tab_bytes;
+  const size_t image_bytes = alias_base + alias_bytes;
   if (image_bytes > 0xFFFFFFF0ull) return fail(PBN_ELDS, "plan image too large");
   const uint32_t jstride = swz ? 128 * units : 16 * units, hoff = swz ? 128 : 16;
   std::vector<size_t> rec0(ns, 0);   // dense layout: record of predictor 0
@@ -547,6 +606,42 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
     put32(rec + 8, nmulti ? uint32_t(first_choice) : sl.table ? 0u : uint32_t(default_choice));
     put32(rec + 12, w);
   }
+  if (alias_mode) {
+    // alias records {draw byte offset, L, s, 0} + L x {threshold, alias}; the
+    // outcome is the combined index over the multi-predictor members, first
+    // member most significant (single-predictor members only have digit 0)
+    size_t cur = alias_base;
+    for (uint32_t s = 0; s < ns; ++s) {
+      if (sel_index[s] == PBN_NONE) continue;
+      const uint32_t L = sel_L[s];
+      std::vector<uint32_t> mem;
+      for (uint32_t v : slots[s].members)
+        if (g.nfn(v) > 1) mem.push_back(v);
+      std::vector<double> probs(L);
+      std::vector<uint32_t> digits(mem.size());
+      for (uint32_t c = 0; c < L; ++c) {
+        uint32_t rest = c;
+        for (int k = int(mem.size()) - 1; k >= 0; --k) {
+          digits[k] = rest % g.nfn(mem[k]);
+          rest /= g.nfn(mem[k]);
+        }
+        double q = 1.0;
+        for (size_t k = 0; k < mem.size(); ++k) q = q * g.sel[g.fn_off[mem[k]] + digits[k]];
+        probs[c] = q;
+      }
+      std::vector<uint32_t> thr, al;
+      vose_table(probs, thr, al);
+      put32(cur + 0, 4u * (2u + 2u * ag + sel_index[s]));
+      put32(cur + 4, L);
+      put32(cur + 8, sel_index[s]);
+      for (uint32_t c = 0; c < L; ++c) {
+        put32(cur + 16 + 8 * size_t(c), thr[c]);
+        put32(cur + 20 + 8 * size_t(c), al[c]);
+      }
+      put32(size_t(s) * 16 + 8, uint32_t(cur));
+      cur += align16(16 + 8 * size_t(L));
+    }
+  }
 
   // ---- blob
   const size_t hdr = align16(sizeof(pbn_plan_header));
@@ -555,7 +650,10 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   const size_t o2p_off = align16(q_off + 8 * size_t(n + 1));
   const size_t p2o_off = align16(o2p_off + 4 * size_t(n));
   const size_t blk_off = align16(p2o_off + 4 * size_t(32 * state_words));
-  const size_t image_off = align16(blk_off + 4 * blocks.size() + 4);
+  const size_t pert_off = align16(blk_off + 4 * blocks.size() + 4);
+  const size_t pert_bytes = alias_mode ? 8 * (size_t(1) << ak) : 0;
+  const size_t kpos_off = align16(pert_off + pert_bytes);
+  const size_t image_off = align16(kpos_off + (alias_mode ? 4 * size_t(nk) : 0));
   const size_t total = align16(image_off + image_bytes);
   if (total > 0xFFFFFFF0ull) return fail(PBN_ELDS, "plan blob too large");
   plan.blob.assign(total, 0);
@@ -589,6 +687,42 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   h.fn_units = units;
   h.fn_jshift = uint32_t(__builtin_ctz(jstride));
   h.fn_hoff = hoff;
+  if (alias_mode) {
+    const uint32_t nw = 2 + 2 * ag + n_sel;
+    h.sampling = 1;
+    h.n_jobs = (nw + 3) / 4;
+    h.fill_steps = h.n_jobs <= PBN_WAVE ? PBN_WAVE / h.n_jobs : 1;
+    h.pert_off = uint32_t(pert_off);
+    h.kpos_off = uint32_t(kpos_off);
+    h.alias_k = ak;
+    h.alias_g = ag;
+    h.alias_kp = akp;
+    h.n_sel = n_sel;
+    // Algorithm 1: t = (1 - p)^l for the l removed nodes, a left-to-right
+    // product; a leaf is perturbed when the drawn word exceeds ceil(t 2^32) - 1
+    const uint32_t nl = n - nk;
+    double t = 1.0;
+    for (uint32_t i = 0; i < nl; ++i) t = t * (1.0 - g.p);
+    const double c = std::ceil(t * 4294967296.0) - 1.0;
+    h.leaf_thr = nl == 0 ? 0xFFFFFFFFu : c <= 0.0 ? 0u : c >= 4294967295.0 ? 0xFFFFFFFFu : uint32_t(c);
+    // Algorithm 2's table over the 2^k patterns of one group: pattern c has
+    // probability prod_b (p if bit b of c is set else 1 - p), left to right
+    const uint32_t L = 1u << ak;
+    std::vector<double> probs(L);
+    const double q = 1.0 - g.p;
+    for (uint32_t c2 = 0; c2 < L; ++c2) {
+      double v = 1.0;
+      for (uint32_t b = 0; b < ak; ++b) v = v * (((c2 >> b) & 1u) ? g.p : q);
+      probs[c2] = v;
+    }
+    std::vector<uint32_t> thr, al;
+    vose_table(probs, thr, al);
+    for (uint32_t c2 = 0; c2 < L; ++c2) {
+      std::memcpy(&plan.blob[pert_off + 8 * size_t(c2)], &thr[c2], 4);
+      std::memcpy(&plan.blob[pert_off + 8 * size_t(c2) + 4], &al[c2], 4);
+    }
+    for (uint32_t i = 0; i < nk; ++i) std::memcpy(&plan.blob[kpos_off + 4 * size_t(i)], &plan.node_pos[kept[i]], 4);
+  }
   std::memcpy(&plan.blob[0], &h, sizeof h);
   std::memcpy(&plan.blob[pass_off], passes.data(), sizeof(pbn_pass_info) * npass);
   std::memcpy(&plan.blob[q_off], g.Q.data(), 8 * size_t(n + 1));
@@ -602,7 +736,8 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
 
   plan.state_dwords = h.state_dwords;
   plan.fill_steps = h.fill_steps;
-  plan.n_jobs = njobs;
+  plan.n_jobs = h.n_jobs;
+  plan.sampling = h.sampling;
   plan.has_table = h.has_table;
   pbn_plan_info& in = plan.info;
   std::memset(&in, 0, sizeof in);
@@ -613,7 +748,7 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   in.n_passes = npass;
   in.state_words = h.state_words;
   in.state_bytes = 32 * state_words;
-  in.n_jobs = njobs;
+  in.n_jobs = h.n_jobs;
   in.image_bytes = uint32_t(image_bytes);
   in.table_bytes = uint32_t(tab_bytes);
   in.image_in_lds = h.image_in_lds;
@@ -635,6 +770,7 @@ extern "C" pbn_status pbn_plan_build(const pbn_net* g, const uint32_t* interest,
   else
     pbn_plan_opts_default(&o);
   if (o.reduce > 2) return fail(PBN_EINVAL, "reduce must be 0, 1 or 2");
+  if (o.sampling > 1) return fail(PBN_EINVAL, "sampling must be 0 (keyed) or 1 (alias)");
   if (o.max_group_nodes < 1 || o.max_group_nodes > PBN_MAX_GROUP_NODES)
     return fail(PBN_EINVAL, "max_group_nodes must be 1..%d", PBN_MAX_GROUP_NODES);
   if (o.max_parent_bits > PBN_MAX_GROUP_PARENTS)

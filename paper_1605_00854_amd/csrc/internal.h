@@ -39,6 +39,7 @@ struct pbn_plan {
   uint32_t fill_steps = 1;
   uint32_t n_jobs = 1;
   uint32_t has_table = 0;
+  uint32_t sampling = 0;     // 1: alias sampling (draw contract of the plan format)
 };
 
 namespace pbn {

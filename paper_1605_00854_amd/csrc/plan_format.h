@@ -47,7 +47,8 @@ struct pbn_plan_header {
   uint32_t n_passes;
   uint32_t state_dwords;   // LDS state buffer in words = 8 * state_words
   uint32_t state_words;    // packed words per trajectory = ceil((zero_pos + 4) / 32)
-  uint32_t n_jobs;         // 1 + number of SEL blocks with a kept member
+  uint32_t n_jobs;         // Philox calls per step: 1 + SEL blocks with a kept member
+                           // (alias sampling: ceil((2 + 2 alias_g + n_sel) / 4))
   uint32_t fill_steps;     // steps whose jobs are computed per fill (njobs <= 64)
   uint32_t image_bytes;    // bytes of the image (slot, choice, fn records, tables)
   uint32_t image_off;      // blob offset of the image
@@ -66,8 +67,33 @@ struct pbn_plan_header {
   uint32_t fn_units;       // 16-byte units per FN record: 1 (<= 5 parents) or 2 (<= 7)
   uint32_t fn_jshift;      // log2 of the bytes from an FN slot's record of predictor j to j + 1
   uint32_t fn_hoff;        // bytes from a two-unit record's first unit to its second
-  uint32_t pad[3];
+  uint32_t sampling;       // 0 keyed draws; 1 alias sampling (the fields below)
+  uint32_t pad[2];
+  // alias sampling (Algorithms 1-2, Sections 2.2 / 3.2 / 3.3)
+  uint32_t pert_off;       // blob offset of the pattern table: 2^alias_k entries {keep threshold, alias}
+  uint32_t kpos_off;       // blob offset of kept-node byte positions (original-id order), n_kept entries
+  uint32_t alias_k;        // nodes per perturbation group (Algorithm 2's k)
+  uint32_t alias_g;        // groups
+  uint32_t alias_kp;       // nodes of the last group (k')
+  uint32_t leaf_thr;       // Algorithm 1: a leaf is perturbed when the drawn word exceeds this
+  uint32_t n_sel;          // slots that draw a (combined) predictor function
+  uint32_t pad2;
 };
+// Alias sampling draws, per step t: Philox(traj, t, c, PBN_STREAM_ALIAS) for
+// c = 0 .. n_jobs-1 give words w[0 .. 4 n_jobs) (word e of call c is w[4c+e]):
+//   w[0]               Algorithm 1: a removed leaf is perturbed when w[0] > leaf_thr
+//   w[1]               not drawn from (the kernel keeps the step's perturbed flag here)
+//   w[2+2q], w[3+2q]   group q's pattern (Algorithm 2): column = the top alias_k
+//                      bits of the first word, kept when the second word is below
+//                      the column's threshold, else its alias; the last group's
+//                      pattern is ANDed with the mask of its alias_kp low bits;
+//                      bit b flips kept node q alias_k + b (original-id order)
+//   w[2+2g+s]          selecting slot s (numbered by smallest member id): column =
+//                      high word of w * L, kept when the low word is below the
+//                      column's threshold, else its alias
+// Tables come from Vose's construction in double; threshold = floor(keep 2^32),
+// at most 2^32 - 1.
+#define PBN_STREAM_ALIAS 4u
 
 struct pbn_pass_info {
   uint32_t flags;   // PBN_PASS_*
@@ -107,6 +133,11 @@ struct pbn_pass_info {
 //       the first choice record of the image);
 //       TABLE: offset of the first choice record of its multi-predictor members
 //       (in member order), or 0
+// With alias sampling, z of a selecting slot (a multi-predictor FN slot or a
+// TABLE slot with multi-predictor members) is the image offset of its alias
+// record: {byte offset of its word w[2+2g+s] in a step's draws, L, s, 0}, then
+// L entries {threshold, alias} of 8 bytes; the outcome is the predictor j (FN)
+// or the combined index c (TABLE).  Other slots keep the keyed-mode z.
 //   w = TABLE: mixed-radix weights of the multi-predictor members, one byte
 //       each (first member most significant digit); FN / padded lane: the
 //       state byte the slot writes

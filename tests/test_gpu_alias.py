@@ -1,0 +1,176 @@
+"""GPU parity of the alias sampling mode (Algorithms 1, 2 and 5's per-group
+draws; Sections 2.2, 3.2-3.4) through the C ABI.
+
+* Bit-exact trajectories and counters against the oracle's reduced-network
+  simulator under the same draw contract: unreduced and reduced networks,
+  combined tables with several multi-predictor members, LDS- and
+  global-resident images, two-unit FN records, plans of more than two lane
+  passes, more than 64 Philox calls per step, chunked launches.
+* The law: long-run target frequencies match the exact steady state (Eq. 1,
+  power method) within statistical error, and agree with the keyed mode's
+  estimates on a network too large for the exact chain.
+"""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+import pbn_synth as ps
+from oracle import alias, exact
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_1605_00854_amd import api  # noqa: E402
+
+CAPS = dict(max_group_nodes=4, max_parent_bits=12, max_table_entries=4096)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def wide7(seed=12, n=70):
+    rng = np.random.default_rng(seed)
+    fns = []
+    for _ in range(n):
+        l = int(rng.integers(1, 4))
+        probs = rng.dirichlet(np.ones(l))
+        ks = [int(rng.integers(1, 8)) for _ in range(l)]
+        fns.append([(probs[j], list(rng.choice(n, size=ks[j], replace=False)), rng.integers(0, 2, 1 << ks[j]))
+                    for j in range(l)])
+    return ps.assemble(n, 2e-3, fns)
+
+
+NETS = {
+    "c1": ps.tiny_c1,
+    "c2": ps.medium_c2,
+    "c2_hot": lambda: ps.medium_c2(n=100, p=0.02, seed=31),
+    "multi400": lambda: ps.random_pbn(400, 2e-3, 12, nfn=lambda r: int(r.integers(2, 5)),
+                                      nparents=lambda r: int(r.integers(1, 4))),
+    "sparse120": lambda: ps.random_pbn(120, 3e-3, 14, nfn=lambda r: int(r.integers(1, 4)),
+                                       nparents=lambda r: int(r.integers(0, 3)), leaf_frac=0.2),
+    "wide7": wide7,
+}
+
+
+@functools.lru_cache(maxsize=None)
+def net_of(name):
+    return NETS[name]()
+
+
+def targets_of(net):
+    t1 = ps.non_leaf_targets(net, 3)
+    t2 = [(t1[0][0], 0)]
+    t3 = [(a, (a + 1) % 2) for a, _ in ps.non_leaf_targets(net, 2)]
+    return [t1, t2, t3]
+
+
+def interest_of(net):
+    return sorted({a for tg in targets_of(net) for a, _ in tg})
+
+
+def plan_opts(opts):
+    return dict(CAPS, sampling=1, **opts)
+
+
+def oracle_plan(net, opts):
+    return alias.alias_plan(net, interest_of(net), reduce=opts.get("reduce", 1), group=opts.get("group", 1),
+                            theta=opts.get("theta", 65536), weight_mode=opts.get("weight_mode", 1),
+                            caps=(CAPS["max_group_nodes"], CAPS["max_parent_bits"], CAPS["max_table_entries"]))
+
+
+PLAIN = dict(reduce=0, group=0)
+REDUCED = dict(reduce=1, group=0)
+GROUPED = dict(reduce=1, group=1)
+MULTI_GROUPS = dict(reduce=1, group=1, weight_mode=0, theta=10 ** 6)
+GLOBAL_IMAGE = dict(reduce=1, group=1, weight_mode=0, theta=10 ** 6, lds_budget_bytes=0)
+
+CASES = [
+    # name, opts, seed, traj0, ntraj, chunks, count_from, plain, wpb
+    ("c1", PLAIN, 1, 0, 5, (2000,), 0, True, 0),
+    ("c1", MULTI_GROUPS, 1, 0, 5, (1200, 800), 300, False, 0),
+    ("c2", REDUCED, 2, 0, 24, (300,), 0, True, 0),
+    ("c2", MULTI_GROUPS, 2, 0, 24, (300,), 0, False, 0),
+    ("c2", GLOBAL_IMAGE, 2, 3, 19, (150, 150), 40, False, 3),
+    ("c2_hot", GROUPED, 3, 5, 16, (120, 80), 50, False, 2),
+    ("multi400", GROUPED, 5, 0, 6, (60,), 0, False, 1),
+    ("sparse120", MULTI_GROUPS, 7, 0, 12, (150,), 0, False, 0),
+    ("wide7", REDUCED, 9, 0, 10, (200,), 0, True, 0),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}-{i}" for i, c in enumerate(CASES)])
+def test_alias_trajectories_bit_exact(case):
+    name, opts, seed, traj0, ntraj, chunks, count_from, plain, wpb = case
+    net = net_of(name)
+    tgs = targets_of(net)
+    plan = api.Plan(net, interest=interest_of(net), **plan_opts(opts))
+    ref_plan = oracle_plan(net, opts)
+    say(f"[gpu] alias {name} opts={opts} info={plan.info} traj={traj0}+{ntraj} chunks={chunks} plain={plain}")
+    tg = plan.targets(tgs)
+    state = api.state_init(plan, seed, ntraj, traj0=traj0)
+    counts = api.new_counts(len(tgs), ntraj)
+    step = 0
+    for c in chunks:
+        api.simulate(plan, seed, state, counts, tg, step, c, traj0=traj0, count_from=count_from, plain=plain,
+                     waves_per_block=wpb)
+        step += c
+    orig = api.unpack_bits(api.to_original(plan, state).cpu().numpy(), plan.n)
+    counts = counts.cpu().numpy()
+    say(f"[oracle] alias {name} steps={step}")
+    ref = alias.simulate(net, ref_plan, seed, np.arange(traj0, traj0 + ntraj), step, targets=tgs,
+                         count_from=count_from)
+    kept = ref_plan["kept"]
+    assert plan.info["n_kept"] == len(kept)
+    bad = np.nonzero((orig[:, kept] != ref["state"][:, kept]).any(axis=1))[0]
+    assert bad.size == 0, f"{bad.size} trajectories differ, first {traj0 + bad[0]}"
+    assert np.array_equal(counts[:, :, 0], ref["hits"])
+    assert np.array_equal(counts[:, :, 1], ref["n01"])
+    assert np.array_equal(counts[:, :, 2], ref["n10"])
+    assert ref["perturbed"].sum() > 0
+    if opts is MULTI_GROUPS and name in ("c2", "sparse120"):
+        assert any(len(g) > 1 for g in ref_plan["groups"]), "case must draw combined functions"
+    if name == "multi400":
+        assert plan.info["n_jobs"] > 64 and plan.info["n_passes"] > 2
+    if opts is GLOBAL_IMAGE:
+        assert plan.info["image_in_lds"] == 0
+    if name == "wide7":
+        assert plan.info["max_fn_parents"] > 5
+
+
+def _long_run(net, opts, seed, ntraj, burn, steps, targets):
+    plan = api.Plan(net, interest=sorted({a for tg in targets for a, _ in tg}), **opts)
+    tg = plan.targets(targets)
+    state = api.state_init(plan, seed, ntraj)
+    counts = api.new_counts(len(targets), ntraj)
+    api.simulate(plan, seed, state, counts, tg, 0, burn + steps, count_from=burn)
+    torch.cuda.synchronize()
+    hits = counts.cpu().numpy()[:, :, 0].astype(float) / steps      # (targets, ntraj)
+    return hits.mean(axis=1), hits.std(axis=1, ddof=1) / np.sqrt(ntraj)
+
+
+@pytest.mark.parametrize("opts", [PLAIN, MULTI_GROUPS])
+def test_alias_steady_state_matches_exact_chain(opts):
+    net = ps.random_pbn(9, 0.03, 51, nfn=lambda r: int(r.integers(1, 4)), nparents=lambda r: int(r.integers(1, 4)),
+                        leaf_frac=0.25)
+    targets = targets_of(net)
+    pi = exact.steady_state(net)
+    want = np.array([exact.target_probability(pi, tg) for tg in targets])
+    say(f"[gpu] alias steady state opts={opts}")
+    mean, se = _long_run(net, plan_opts(opts), 21, 4096, 2000, 20000, targets)
+    assert np.all(np.abs(mean - want) < 5 * se + 1e-4), (mean, want, se)
+
+
+def test_alias_and_keyed_modes_estimate_the_same_steady_state():
+    net = net_of("c2_hot")
+    targets = targets_of(net)
+    say("[gpu] alias vs keyed on c2_hot")
+    m_alias, se_a = _long_run(net, plan_opts(GROUPED), 23, 4096, 2000, 20000, targets)
+    m_keyed, se_k = _long_run(net, dict(GROUPED), 24, 4096, 2000, 20000, targets)
+    assert np.all(np.abs(m_alias - m_keyed) < 5 * np.hypot(se_a, se_k) + 1e-4), (m_alias, m_keyed)
