@@ -64,6 +64,7 @@ PLANS = {
     "reduction": dict(reduce=1, group=0),
     "cone": dict(reduce=2, group=0),
     "plain": dict(reduce=0, group=0),
+    "alias": dict(reduce=1, group=0, sampling=1),
 }
 
 
@@ -357,7 +358,7 @@ def main():
     ap.add_argument("--wpb", type=int, default=0)
     ap.add_argument("--quick-tune", action="store_true")
     ap.add_argument("--queries", type=int, default=2000, help="C5: number of served queries")
-    ap.add_argument("--plan", default="auto", choices=["auto", "plain", "reduction", "cone", "grouped"],
+    ap.add_argument("--plan", default="auto", choices=["auto", "plain", "reduction", "cone", "grouped", "alias"],
                     help="product plan: autotuned, or a fixed preparation (profiling runs)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB copied once by a plain device copy (HBM counter calibration in profiles)")
@@ -446,6 +447,9 @@ def main():
                     "cone": (PLANS["cone"], True, 0), "grouped_default": (PLANS["grouped"], False, 0)}
         if best_grouped:
             variants["grouped_tuned"] = (best_grouped["opts"], False, best_grouped["wpb"])
+        # the paper's own sampling (Algorithms 1 and 2, one alias draw per
+        # group) on the product plan: same law, different draws
+        variants["alias_product"] = (dict(best_opts, sampling=1), product_plain, best_wpb)
         for name, (opts, plain, wpb) in variants.items():
             ev = []
             torch.cuda.synchronize()
@@ -462,6 +466,7 @@ def main():
                                            / compare["plain"]["node_updates_per_s"])
         compare["cone_over_reduction"] = (compare["cone"]["node_updates_per_s"]
                                           / compare["reduction"]["node_updates_per_s"])
+        compare["alias_over_product"] = compare["alias_product"]["node_updates_per_s"] / value
         for name in ("grouped_default", "grouped_tuned"):
             if name in compare:
                 compare[name + "_over_plain"] = (compare[name]["node_updates_per_s"]
