@@ -39,6 +39,7 @@ class Net:
         h = C.c_void_p()
         check(lib().pbn_net_create(C.byref(d), C.byref(h)))
         self.handle = h
+        self._libref = lib()
 
     def tables(self):
         """(Q[0..n], cum[n,3], rank[n]) of the random-number contract."""
@@ -50,9 +51,11 @@ class Net:
         return q, cum.reshape(self.n, 3), rank
 
     def __del__(self):
-        h = getattr(self, "handle", None)
-        if h is not None and _lib._lib is not None:
-            _lib._lib.pbn_net_destroy(h)
+        # the library object is held by the instance: module globals may
+        # already be gone when the interpreter shuts down
+        h, L = getattr(self, "handle", None), getattr(self, "_libref", None)
+        if h is not None and L is not None:
+            L.pbn_net_destroy(h)
             self.handle = None
 
 
@@ -82,6 +85,7 @@ class Plan:
         h = C.c_void_p()
         check(lib().pbn_plan_build(self.net.handle, _ptr(ints, C.c_uint32), nint, C.byref(o), C.byref(h)))
         self.handle = h
+        self._libref = lib()
         info = _lib.pbn_plan_info()
         check(lib().pbn_plan_info_get(h, C.byref(info)))
         self.info = {name: getattr(info, name) for name, _ in info._fields_ if name != "reserved"}
@@ -147,9 +151,11 @@ class Plan:
         return out
 
     def __del__(self):
-        h = getattr(self, "handle", None)
-        if h is not None and _lib._lib is not None:
-            _lib._lib.pbn_plan_destroy(h)
+        # the library object is held by the instance: module globals may
+        # already be gone when the interpreter shuts down
+        h, L = getattr(self, "handle", None), getattr(self, "_libref", None)
+        if h is not None and L is not None:
+            L.pbn_plan_destroy(h)
             self.handle = None
 
 
@@ -353,12 +359,15 @@ class Batch:
 class Graph:
     def __init__(self, handle):
         self.handle = handle
+        self._libref = lib()
 
     def launch(self, stream=None):
         check(lib().pbn_graph_launch(self.handle, _stream(stream)))
 
     def __del__(self):
-        h = getattr(self, "handle", None)
-        if h is not None and _lib._lib is not None:
-            _lib._lib.pbn_graph_destroy(h)
+        # the library object is held by the instance: module globals may
+        # already be gone when the interpreter shuts down
+        h, L = getattr(self, "handle", None), getattr(self, "_libref", None)
+        if h is not None and L is not None:
+            L.pbn_graph_destroy(h)
             self.handle = None
