@@ -413,6 +413,19 @@ __device__ __forceinline__ uint32_t eval_slot(const SlotRegs<Shape<PM, UM>::XW, 
   return eval_fn<PM, UM>(f, cs);
 }
 
+// FN-only plans with slot data held in registers: every lane reads the record
+// of its chosen predictor (one-predictor lanes and padded lanes choose 0: their
+// thresholds are never reached), with no branch between lanes that select and
+// lanes that do not, so the loads of several passes can be in flight together.
+template <int PM, int UM, int MODE>
+__device__ __forceinline__ uint32_t eval_fn_all(const SlotRegs<Shape<PM, UM>::XW, Shape<PM, UM>::TTW>& r,
+                                                const NegThr& nt, const uint8_t* img, const uint8_t* cs,
+                                                const uint8_t* rs, const FnFmt& fm) {
+  const uint32_t w = *reinterpret_cast<const uint32_t*>(rs + (r.draw & 0xFFFFFFu));
+  const auto f = load_fn<PM, UM, MODE>(img, r.base, choose_neg(w, nt), fm);
+  return eval_fn<PM, UM>(f, cs);
+}
+
 // Store a slot's result: a table slot writes its word of member bytes, an FN
 // slot (or padded lane) its one byte.
 template <int UM>
@@ -707,7 +720,12 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
           // every pass reads s(t) before any writes s(t+1)
           uint32_t out[NREG];
 #pragma unroll
-          for (int p = 0; p < NREG; ++p) out[p] = eval_slot<PM, UM, MODE>(cached[p], &nthr[p], img, csb, rs, fm);
+          for (int p = 0; p < NREG; ++p) {
+            if constexpr (UM == 0 && !ALIAS)
+              out[p] = eval_fn_all<PM, UM, MODE>(cached[p], nthr[p], img, csb, rs, fm);
+            else
+              out[p] = eval_slot<PM, UM, MODE>(cached[p], &nthr[p], img, csb, rs, fm);
+          }
 #pragma unroll
           for (int p = 0; p < NREG; ++p) store_slot<UM>(nsb, cached[p].info, cached[p].spos, out[p]);
           if constexpr (kBallotTargets) {
