@@ -172,7 +172,7 @@ struct SimParams {
   unsigned long long seed;
   uint32_t traj0, ntraj, step0, nsteps, count_from;
   uint32_t wpb;
-  uint32_t wave_bytes;   // LDS bytes per wave: two state buffers + ring
+  uint32_t wave_bytes;   // LDS bytes per wave: state buffer(s) + ring
   uint32_t record_traj;  // trajectories 0 .. record_traj-1 record target 0's indicator bits
   uint32_t record_words; // words per recording trajectory
   uint32_t pad;
@@ -363,8 +363,8 @@ __device__ __forceinline__ void load_slot(SlotRegs<Shape<PM, UM>::XW, Shape<PM, 
 }
 
 // TABLE slot: combined-function index from its multi-predictor members'
-// choices (mixed radix), union parents, one table byte expanded to one byte
-// per member (Section 3.3).
+// choices (mixed radix), union parents, one table byte: member k's output in
+// bit k (Section 3.3).
 template <int PM, int UM, int MODE>
 __device__ __forceinline__ uint32_t eval_table(const SlotRegs<Shape<PM, UM>::XW, Shape<PM, UM>::TTW>& r,
                                                const uint8_t* img, const uint8_t* cs, const uint8_t* rs) {
@@ -384,7 +384,7 @@ __device__ __forceinline__ uint32_t eval_table(const SlotRegs<Shape<PM, UM>::XW,
   }
   const uint32_t x = gather<(UM > 0 ? UM : 1)>(cs, r.pw);
   const uint32_t v = img_u8<G>(img + r.base + 32u + (c << PBN_SLOT_NU(r.info)) + x);
-  return (v * 0x204081u) & 0x01010101u;
+  return v;   // member k's output in bit k
 }
 
 // One slot: a table slot, a multi-predictor node (select from its drawn word,
@@ -426,12 +426,12 @@ __device__ __forceinline__ uint32_t eval_fn_all(const SlotRegs<Shape<PM, UM>::XW
   return eval_fn<PM, UM>(f, cs);
 }
 
-// Store a slot's result: a table slot writes its word of member bytes, an FN
-// slot (or padded lane) its one byte.
+// Store a slot's result: a table slot writes its word of member bytes (from
+// the table byte's member bits), an FN slot (or padded lane) its one byte.
 template <int UM>
 __device__ __forceinline__ void store_slot(uint8_t* ns, uint32_t info, uint32_t spos, uint32_t out) {
   if (UM > 0 && (info & PBN_SLOT_TABLE))
-    *reinterpret_cast<uint32_t*>(ns + spos) = out;
+    *reinterpret_cast<uint32_t*>(ns + spos) = (out * 0x204081u) & 0x01010101u;   // bit k -> byte k
   else
     ns[spos] = uint8_t(out);
 }
@@ -440,7 +440,7 @@ __device__ __forceinline__ void store_slot(uint8_t* ns, uint32_t info, uint32_t 
 struct TrajArgs {
   const uint8_t* blob;              // plan blob (global memory)
   const uint8_t* img;               // plan image: LDS copy or the blob's own image
-  uint8_t* wb;                      // this wave's LDS: two state buffers + ring
+  uint8_t* wb;                      // this wave's LDS: state buffer(s) + ring
   unsigned long long seed;
   uint32_t traj;                    // global trajectory id (Philox counter word 0)
   uint32_t tl;                      // index within the launch's state/count arrays
@@ -455,7 +455,10 @@ struct TrajArgs {
 
 // PM: parent bytes gathered per FN slot (>= the plan's largest predictor);
 // UM: union bits gathered per TABLE slot (0: no table slots);
-// NREG: lane passes whose slot data stay in registers (0: reload every pass);
+// NREG: 1 or 2, lane passes whose slot data stay in registers; their results
+// are held in registers until all passes have read s(t), so s(t+1) overwrites
+// s(t) in place (one state buffer per wave); 0: slot data reloaded every pass,
+// results written to a second state buffer;
 // MODE: bit 0, FN records of one or two units (batches of plans of both
 // kinds); bit 1, image reads through global-address-space pointers; bit 2,
 // alias sampling (Algorithms 1, 2 and 5's per-group draws) instead of the
@@ -464,10 +467,12 @@ template <int PM, int UM, int NREG, int MODE>
 __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   constexpr int XW = Shape<PM, UM>::XW, TTW = Shape<PM, UM>::TTW;
   constexpr bool ALIAS = (MODE & 4) != 0;
-  constexpr int NR = NREG > 0 ? NREG : 1;
+  constexpr bool kCached = NREG == 1 || NREG == 2;
+  constexpr bool kSingle = NREG != 0;   // one state buffer, updated in place
+  constexpr int NR = kCached ? NREG : 1;
   // FN-only plans with register-held slots read target values from the pass
   // ballots (state byte b = bit b % 64 of pass b / 64's ballot)
-  constexpr bool kBallotTargets = UM == 0 && NREG > 0;
+  constexpr bool kBallotTargets = UM == 0 && kCached;
   using Regs = SlotRegs<XW, TTW>;
   const pbn_plan_header* H = reinterpret_cast<const pbn_plan_header*>(a.blob);
   const uint32_t lane = threadIdx.x & 63u;
@@ -485,8 +490,8 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   const uint32_t* blk = reinterpret_cast<const uint32_t*>(a.blob + H->blk_off);
   const uint8_t* img = a.img;
   uint32_t* sbuf0 = reinterpret_cast<uint32_t*>(a.wb);
-  uint32_t* sbuf1 = reinterpret_cast<uint32_t*>(a.wb + 4u * sdp);
-  uint4* ring = reinterpret_cast<uint4*>(a.wb + 8u * sdp);
+  uint32_t* sbuf1 = kSingle ? sbuf0 : reinterpret_cast<uint32_t*>(a.wb + 4u * sdp);
+  uint4* ring = reinterpret_cast<uint4*>(a.wb + (kSingle ? 4u : 8u) * sdp);   // after the state buffer(s)
   const uint32_t traj = a.traj;
   const uint32_t k0 = uint32_t(a.seed), k1 = uint32_t(a.seed >> 32);
 
@@ -498,13 +503,13 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
 #pragma unroll
     for (uint32_t i = 0; i < 8u; ++i) {
       sbuf0[8u * w + i] = (((word >> (4u * i)) & 0xFu) * 0x204081u) & 0x01010101u;
-      sbuf1[8u * w + i] = 0;
+      if constexpr (!kSingle) sbuf1[8u * w + i] = 0;
     }
   }
 
   Regs cached[NR];
   NegThr nthr[NR];
-  if constexpr (NREG > 0) {
+  if constexpr (kCached) {
 #pragma unroll
     for (int p = 0; p < NREG; ++p) {
       if (uint32_t(p) < npass) {
@@ -716,7 +721,7 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
         z = target_z(csb);
       } else {
         uint8_t* nsb = reinterpret_cast<uint8_t*>(cur ? sbuf0 : sbuf1);
-        if constexpr (NREG > 0) {
+        if constexpr (kCached) {
           // every pass reads s(t) before any writes s(t+1)
           uint32_t out[NREG];
 #pragma unroll
@@ -944,12 +949,13 @@ uint32_t grid_for(size_t work, uint32_t block) {
 
 constexpr uint32_t kLdsMax = 160u * 1024u;
 
-// LDS of one wave: the two state buffers and the Philox ring (one fill:
+// LDS of one wave: the state buffer(s) and the Philox ring (one fill:
 // min(fill, 32) steps of n_jobs calls when the calls of a step fit in a wave,
-// else one step).
-uint32_t wave_lds_bytes(const pbn_plan* plan) {
+// else one step).  `single`: the kernel updates one state buffer in place
+// (plans of one or two lane passes in k_simulate).
+uint32_t wave_lds_bytes(const pbn_plan* plan, bool single) {
   const uint32_t ring = plan->n_jobs <= 64 ? std::min(plan->fill_steps, 32u) * plan->n_jobs : plan->n_jobs;
-  return 8u * ((plan->state_dwords + 3u) & ~3u) + 16u * ring;
+  return (single ? 4u : 8u) * ((plan->state_dwords + 3u) & ~3u) + 16u * ring;
 }
 
 template <bool IMG_LDS, int PM, int UM, int NREG, bool ALIAS>
@@ -1004,7 +1010,7 @@ pbn_status simulate_common(bool plain, const pbn_plan* plan, const void* d_plan,
   if (plain && plan->has_table) return fail(PBN_EINVAL, "the plain kernel needs a plan without table slots");
   if (ntraj == 0 || nsteps == 0) return PBN_OK;
 
-  const uint32_t wave_bytes = wave_lds_bytes(plan);
+  const uint32_t wave_bytes = wave_lds_bytes(plan, plan->info.n_passes <= 2u);
   const bool img_lds = plan->info.image_in_lds != 0;
   const uint32_t img = img_lds ? ((plan->info.image_bytes + 15u) & ~15u) : 0u;
   uint32_t wpb = launch && launch->waves_per_block ? launch->waves_per_block : 4u;
@@ -1158,7 +1164,7 @@ pbn_status batch_shape(const pbn_plan* const* plans, uint32_t nitems, BatchShape
       return fail(PBN_ELDS, "plan exceeds the kernel's gather widths");
     if (p->info.max_fn_parents > 5) sh.pm = 7;
     sh.um = std::max(sh.um, p->info.max_union_bits);
-    sh.wave_bytes = std::max(sh.wave_bytes, wave_lds_bytes(p));
+    sh.wave_bytes = std::max(sh.wave_bytes, wave_lds_bytes(p, false));
   }
   sh.um = sh.um == 0 ? 0 : sh.um <= 8 ? 8 : 16;
   return PBN_OK;
