@@ -485,10 +485,11 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   fm.zp2 = zero_pos | (zero_pos << 16);
   const uint32_t zp2 = fm.zp2;
   const uint32_t sdp = (sd + 3u) & ~3u;   // state buffer, padded to 16 bytes
-  const unsigned long long* Q = reinterpret_cast<const unsigned long long*>(a.blob + H->q_off);
-  const uint32_t* o2p = reinterpret_cast<const uint32_t*>(a.blob + H->o2p_off);
   const uint32_t* blk = reinterpret_cast<const uint32_t*>(a.blob + H->blk_off);
   const uint8_t* img = a.img;
+  // the chain's tables are read from the image (LDS when the image is staged there)
+  const unsigned long long* Q = reinterpret_cast<const unsigned long long*>(img + H->q_img);
+  const uint32_t* o2p = reinterpret_cast<const uint32_t*>(img + H->o2p_img);
   uint32_t* sbuf0 = reinterpret_cast<uint32_t*>(a.wb);
   uint32_t* sbuf1 = kSingle ? sbuf0 : reinterpret_cast<uint32_t*>(a.wb + 4u * sdp);
   uint4* ring = reinterpret_cast<uint4*>(a.wb + (kSingle ? 4u : 8u) * sdp);   // after the state buffer(s)

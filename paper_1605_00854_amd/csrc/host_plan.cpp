@@ -482,11 +482,15 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   }
   const size_t choice_base = slot_bytes;
   const size_t fn_base = (choice_base + 16 * nchoice + 127) & ~size_t(127);
-  const size_t swz_bytes = fn_base + 128 * size_t(rows) + tab_bytes + alias_bytes;
+  // the perturbation chain's tables follow: Q[0..n] and orig -> position
+  const size_t chain_bytes = 16 + 8 * size_t(n + 1) + 16 + 4 * size_t(n);
+  const size_t swz_bytes = fn_base + 128 * size_t(rows) + tab_bytes + alias_bytes + chain_bytes;
   const bool swz = swz_bytes <= o.lds_budget_bytes;
   const size_t tab_base = fn_base + (swz ? 128 * size_t(rows) : 16 * size_t(units) * (nfnrec + 1));
   const size_t alias_base = tab_base + tab_bytes;
-  const size_t image_bytes = alias_base + alias_bytes;
+  const size_t q_img = align16(alias_base + alias_bytes);
+  const size_t o2p_img = align16(q_img + 8 * size_t(n + 1));
+  const size_t image_bytes = align16(o2p_img + 4 * size_t(n));
   if (image_bytes > 0xFFFFFFF0ull) return fail(PBN_ELDS, "plan image too large");
   const uint32_t jstride = swz ? 128 * units : 16 * units, hoff = swz ? 128 : 16;
   std::vector<size_t> rec0(ns, 0);   // dense layout: record of predictor 0
@@ -687,6 +691,8 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   h.fn_units = units;
   h.fn_jshift = uint32_t(__builtin_ctz(jstride));
   h.fn_hoff = hoff;
+  h.q_img = uint32_t(q_img);
+  h.o2p_img = uint32_t(o2p_img);
   if (alias_mode) {
     const uint32_t nw = 2 + 2 * ag + n_sel;
     h.sampling = 1;
@@ -732,6 +738,8 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
     if (plan.node_pos[v] != PBN_NONE) p2o[plan.node_pos[v]] = v;
   std::memcpy(&plan.blob[p2o_off], p2o.data(), 4 * p2o.size());
   if (!blocks.empty()) std::memcpy(&plan.blob[blk_off], blocks.data(), 4 * blocks.size());
+  std::memcpy(&img[q_img], g.Q.data(), 8 * size_t(n + 1));
+  std::memcpy(&img[o2p_img], plan.node_pos.data(), 4 * size_t(n));
   std::memcpy(&plan.blob[image_off], img.data(), image_bytes);
 
   plan.state_dwords = h.state_dwords;

@@ -68,7 +68,9 @@ struct pbn_plan_header {
   uint32_t fn_jshift;      // log2 of the bytes from an FN slot's record of predictor j to j + 1
   uint32_t fn_hoff;        // bytes from a two-unit record's first unit to its second
   uint32_t sampling;       // 0 keyed draws; 1 alias sampling (the fields below)
-  uint32_t pad[2];
+  uint32_t q_img;          // image offset of a copy of Q[0..n] (uint64): read by the
+                           // perturbation chain from wherever the image resides
+  uint32_t o2p_img;        // image offset of a copy of the orig -> position map
   // alias sampling (Algorithms 1-2, Sections 2.2 / 3.2 / 3.3)
   uint32_t pert_off;       // blob offset of the pattern table: 2^alias_k entries {keep threshold, alias}
   uint32_t kpos_off;       // blob offset of kept-node byte positions (original-id order), n_kept entries
@@ -121,6 +123,9 @@ struct pbn_pass_info {
 //   tables:                   TABLE slot: 16 uint16 union-parent positions
 //                             (unused = zero position), then the byte table
 //                             T[c * 2^nu + x]
+//   alias records (alias sampling only, see below)
+//   Q[0..n] (uint64) and the orig -> position map (uint32[n]), copies of the
+//   blob's, at q_img / o2p_img
 // Padded lanes (slot index >= n_slots) have info = 0, y = a dummy FN record,
 // z = the default choice record and w = a state byte of their own above the
 // zero word: they evaluate to 0 and write only that byte.

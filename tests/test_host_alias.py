@@ -16,7 +16,7 @@ from paper_1605_00854_amd import api
 
 FIELDS = ("magic version blob_bytes plan_id n n_kept n_slots n_passes state_dwords state_words n_jobs "
           "fill_steps image_bytes image_off q_off o2p_off p2o_off blk_off pass_off zero_pos max_pmax "
-          "image_in_lds has_table dummy_fn n_table fn_base fn_units fn_jshift fn_hoff sampling pad0 pad1 "
+          "image_in_lds has_table dummy_fn n_table fn_base fn_units fn_jshift fn_hoff sampling q_img o2p_img "
           "pert_off kpos_off alias_k alias_g alias_kp leaf_thr n_sel pad2").split()
 
 CAPS = dict(max_group_nodes=4, max_parent_bits=12, max_table_entries=4096)
@@ -138,3 +138,22 @@ def test_batch_entry_points_reject_alias_plans():
     keyed = api.Plan(NETS["tiny"], interest=[0])
     arr = (C.c_void_p * 1)(keyed.handle.value)
     assert lib().pbn_batch_tasks(arr, ntraj, 1, 4, None, None, C.byref(nt)) == 0 and nt.value == 1
+
+
+@pytest.mark.parametrize("opts", [dict(reduce=1, group=0), dict(reduce=1, group=1, lds_budget_bytes=0),
+                                  dict(reduce=0, group=0, sampling=1)])
+def test_image_carries_the_chain_tables(opts):
+    # the perturbation chain reads Q[0..n] and the orig -> position map from
+    # the image (LDS-resident with it): copies of the blob's own tables
+    net = NETS["c2"]
+    plan = api.Plan(net, interest=interest_of(net), **opts)
+    blob = plan.blob()
+    h = header(blob)
+    n = h["n"]
+    img = h["image_off"]
+    assert h["q_img"] % 16 == 0 and h["o2p_img"] >= h["q_img"] + 8 * (n + 1)
+    assert h["o2p_img"] + 4 * n <= h["image_bytes"]
+    q_blob = np.frombuffer(blob[h["q_off"]:h["q_off"] + 8 * (n + 1)].tobytes(), dtype="<u8")
+    q_img = np.frombuffer(blob[img + h["q_img"]:img + h["q_img"] + 8 * (n + 1)].tobytes(), dtype="<u8")
+    assert np.array_equal(q_blob, q_img)
+    assert u32(blob, img + h["o2p_img"], n).tolist() == [int(x) for x in plan.node_pos()]
