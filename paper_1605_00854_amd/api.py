@@ -127,6 +127,13 @@ class Plan:
         check(lib().pbn_plan_export(self.handle, buf.ctypes.data_as(C.c_void_p), C.byref(size)))
         return buf
 
+    @property
+    def fill_steps(self):
+        """Steps per Philox fill of the step kernel's ring (plan header word 11)."""
+        if getattr(self, "_fill", None) is None:
+            self._fill = int(np.frombuffer(self.blob()[44:48].tobytes(), dtype="<u4")[0])
+        return self._fill
+
     def device(self):
         """Device copy of the blob (torch uint8 tensor on the current device)."""
         if self._dev is None:

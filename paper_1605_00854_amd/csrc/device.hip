@@ -256,6 +256,10 @@ __device__ __forceinline__ uint32_t alias_pick(const uint8_t* tab, uint32_t w, u
   return uint32_t(prod) < e.x ? col : e.y;
 }
 
+// Philox calls per lane in one fill of the ring (the host sizes fills to at
+// most this many rounds of 64 calls; PBN_FILL_ROUNDS in the plan format).
+constexpr int kFillRounds = PBN_FILL_ROUNDS;
+
 // Layout of a plan's FN records (header fields) and the zero-position pair.
 struct FnFmt {
   uint32_t units;     // 16-byte units per record
@@ -574,12 +578,16 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   // fixed Philox job of this lane when one fill covers several steps
   const bool small_jobs = njobs <= 64u;
   const uint32_t bsteps = small_jobs ? min(fill, 32u) : 1u;   // steps per fill
-  uint32_t my_s = 0, my_c2 = 0, my_c3 = PBN_STREAM_PERT;
-  if (small_jobs) {
-    const uint32_t j = lane % njobs;
-    my_s = lane / njobs;
-    my_c2 = ALIAS ? j : j ? blk[j - 1] : 0u;
-    my_c3 = ALIAS ? PBN_STREAM_ALIAS : j ? PBN_STREAM_SEL : PBN_STREAM_PERT;
+  // a fill takes up to kFillRounds calls per lane: call lane + 64 r of a fill
+  // is job (lane + 64 r) mod n_jobs of step (lane + 64 r) / n_jobs
+  uint32_t my_s[kFillRounds], my_c2[kFillRounds], my_c3[kFillRounds];
+#pragma unroll
+  for (int r = 0; r < kFillRounds; ++r) {
+    const uint32_t idx = lane + 64u * uint32_t(r);
+    const uint32_t j = small_jobs ? idx % njobs : 0u;
+    my_s[r] = small_jobs ? idx / njobs : 0u;
+    my_c2[r] = ALIAS ? j : j ? blk[j - 1] : 0u;
+    my_c3[r] = ALIAS ? PBN_STREAM_ALIAS : j ? PBN_STREAM_SEL : PBN_STREAM_PERT;
   }
   // alias sampling: Algorithm 2's groups, the pattern table, kept-node positions
   const uint32_t ag = ALIAS ? H->alias_g : 0u, ak = ALIAS ? H->alias_k : 1u;
@@ -648,7 +656,10 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
     const uint32_t scount = small_jobs ? min(bsteps, tend - t) : 1u;
     if (nacc + scount > 32u) fold();
     if (small_jobs) {
-      if (lane < scount * njobs) ring[lane] = philox(traj, t + my_s, my_c2, my_c3, k0, k1);
+#pragma unroll
+      for (int r = 0; r < kFillRounds; ++r)
+        if (lane + 64u * uint32_t(r) < scount * njobs)
+          ring[lane + 64u * uint32_t(r)] = philox(traj, t + my_s[r], my_c2[r], my_c3[r], k0, k1);
     } else {
       for (uint32_t j = lane; j < njobs; j += 64u)
         ring[j] = ALIAS ? philox(traj, t, j, PBN_STREAM_ALIAS, k0, k1)

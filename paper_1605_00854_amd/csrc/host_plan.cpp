@@ -237,6 +237,27 @@ std::vector<std::vector<uint32_t>> group_single(const std::vector<uint32_t>& nod
 
 std::atomic<uint32_t> g_plan_counter{1};
 
+// Steps per Philox fill: the f <= 32 with f * njobs <= rounds * 64 whose calls
+// use the largest share of their rounds of 64 lanes (ties: the larger f, fewer
+// fills); 1 when a step needs more than 64 calls.  Plans of at most two lane
+// passes (small states) take up to PBN_FILL_ROUNDS rounds; larger plans one,
+// since their ring shares LDS with two large state buffers per wave.
+uint32_t fill_steps_for(uint32_t njobs, uint32_t npass) {
+  if (njobs > PBN_WAVE) return 1;
+  const uint32_t rounds = npass <= 2 ? PBN_FILL_ROUNDS : 1;
+  uint32_t best = 1;
+  double best_use = 0.0;
+  for (uint32_t f = 1; f <= 32 && f * njobs <= rounds * PBN_WAVE; ++f) {
+    const uint32_t calls = f * njobs, rounds = (calls + PBN_WAVE - 1) / PBN_WAVE;
+    const double use = double(calls) / double(rounds * PBN_WAVE);
+    if (use >= best_use - 1e-12) {
+      best = f;
+      best_use = use;
+    }
+  }
+  return best;
+}
+
 struct Slot {
   std::vector<uint32_t> members;   // original node ids
   bool table = false;
@@ -675,7 +696,7 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   h.n_table = ntab;
   h.fn_base = fn_pos0;
   h.n_jobs = njobs;
-  h.fill_steps = njobs <= PBN_WAVE ? PBN_WAVE / njobs : 1;
+  h.fill_steps = fill_steps_for(njobs, npass);
   h.image_bytes = uint32_t(image_bytes);
   h.image_off = uint32_t(image_off);
   h.q_off = uint32_t(q_off);
@@ -697,7 +718,7 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
     const uint32_t nw = 2 + 2 * ag + n_sel;
     h.sampling = 1;
     h.n_jobs = (nw + 3) / 4;
-    h.fill_steps = h.n_jobs <= PBN_WAVE ? PBN_WAVE / h.n_jobs : 1;
+    h.fill_steps = fill_steps_for(h.n_jobs, npass);
     h.pert_off = uint32_t(pert_off);
     h.kpos_off = uint32_t(kpos_off);
     h.alias_k = ak;

@@ -18,6 +18,9 @@
 
 #define PBN_PLAN_MAGIC 0x314E4250u   // "PBN1"
 #define PBN_WAVE 64
+// A fill of the Philox ring computes fill_steps steps' calls in at most this
+// many rounds of PBN_WAVE calls (fill_steps <= 32).
+#define PBN_FILL_ROUNDS 4
 #define PBN_NONE 0xFFFFFFFFu
 
 // streams of the random-number contract
@@ -49,7 +52,10 @@ struct pbn_plan_header {
   uint32_t state_words;    // packed words per trajectory = ceil((zero_pos + 4) / 32)
   uint32_t n_jobs;         // Philox calls per step: 1 + SEL blocks with a kept member
                            // (alias sampling: ceil((2 + 2 alias_g + n_sel) / 4))
-  uint32_t fill_steps;     // steps whose jobs are computed per fill (njobs <= 64)
+  uint32_t fill_steps;     // steps whose jobs are computed per fill (n_jobs <= 64): the f <= 32
+                           // with f n_jobs <= R * 64 that uses the most lanes of its rounds
+                           // (ties: the larger f); R = PBN_FILL_ROUNDS for plans of <= 2
+                           // lane passes, else 1
   uint32_t image_bytes;    // bytes of the image (slot, choice, fn records, tables)
   uint32_t image_off;      // blob offset of the image
   uint32_t q_off;          // blob offset of Q[0..n] (uint64)

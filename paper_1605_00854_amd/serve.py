@@ -111,7 +111,7 @@ class Server:
 
     def footprint(self, plan):
         ring = plan.info["n_jobs"]
-        fill = min(32, max(1, 64 // ring)) if ring <= 64 else 1
+        fill = min(32, plan.fill_steps) if ring <= 64 else 1
         wave_lds = 2 * plan.info["state_bytes"] + 16 * (fill * ring if ring <= 64 else ring)
         hbm = self.ntraj * (4 * plan.info["state_words"] + 24)
         return np.array([self.ntraj, self.ntraj * wave_lds, hbm], dtype=np.float64)
