@@ -174,3 +174,60 @@ def test_alias_and_keyed_modes_estimate_the_same_steady_state():
     m_alias, se_a = _long_run(net, plan_opts(GROUPED), 23, 4096, 2000, 20000, targets)
     m_keyed, se_k = _long_run(net, dict(GROUPED), 24, 4096, 2000, 20000, targets)
     assert np.all(np.abs(m_alias - m_keyed) < 5 * np.hypot(se_a, se_k) + 1e-4), (m_alias, m_keyed)
+
+
+def test_rl_driver_under_alias_sampling():
+    # the two-state driver runs an alias-sampling plan unchanged: its recorded
+    # indicator sequence is the alias oracle's trajectory and its estimate is
+    # within the requested precision of the exact steady state
+    from oracle import stats as ost
+    cfg = ps.config("C1")
+    net = cfg.net
+    plan = api.Plan(net, interest=[0, 1], reduce=0, group=1, weight_mode=0, theta=10 ** 6, sampling=1)
+    ref_plan = alias.alias_plan(net, [0, 1], reduce=0, group=1, theta=10 ** 6, weight_mode=0,
+                                caps=(CAPS["max_group_nodes"], CAPS["max_parent_bits"], CAPS["max_table_entries"]))
+    r = 0.01
+    say("[gpu] rl_run C1 alias r=0.01")
+    res, record = api.rl_run(plan, cfg.seed, cfg.targets, r, initial_steps=20000, max_steps=1 << 22)
+    assert res["status"] == 0, res
+    n = res["steps"]
+    bits = api.unpack_record(record.cpu().numpy(), n)
+    pre = min(n, 3000)
+    z = np.zeros(pre, dtype=np.uint8)
+    s = None
+    for t in range(pre):       # the oracle, one step at a time, reading the target after each step
+        out = alias.simulate(net, ref_plan, cfg.seed, np.arange(1), 1, step0=t, state=s)
+        s = out["reduced"]
+        z[t] = all(out["state"][0, a] == v for a, v in cfg.targets[0])
+    assert np.array_equal(bits[:pre], z)
+    want = ost.rl92_diagnose(bits, r, conf=0.95, eps=1e-3, kmax=100)
+    assert res["k"] == want["k"]
+    assert res["p_hat"] == pytest.approx(want["p_hat"], rel=1e-9)
+    pi = exact.target_probability(exact.steady_state(net), cfg.targets[0])
+    assert abs(res["p_hat"] - pi) < r * 3.29 / 1.96, (res, pi)
+
+
+def test_alias_single_kept_node_and_many_leaves():
+    # edge case: the cone of the node of interest is that node alone (it reads
+    # only itself), so Algorithm 2 has one group of one node (g = k = k' = 1)
+    # and every other node is a removed leaf (Algorithm 1's t = (1-p)^(n-1))
+    n, p = 12, 0.02
+    fns = [[(0.6, [0], np.array([1, 0])), (0.4, [0], np.array([0, 1]))]]           # node 0: not / copy of itself
+    for i in range(1, n):
+        fns.append([(1.0, [0, (i + 1) % n], np.array([0, 1, 1, 0]))])
+    net = ps.assemble(n, p, fns)
+    tgs = [[(0, 1)]]
+    plan = api.Plan(net, interest=[0], **plan_opts(dict(reduce=2, group=0)))
+    ref_plan = alias.alias_plan(net, [0], reduce=2, group=0)
+    assert plan.info["n_kept"] == 1 and (ref_plan["g"], ref_plan["k"], ref_plan["kp"]) == (1, 1, 1)
+    ntraj, steps, seed = 7, 3000, 31
+    say("[gpu] alias single kept node")
+    tg = plan.targets(tgs)
+    state = api.state_init(plan, seed, ntraj)
+    counts = api.new_counts(1, ntraj)
+    api.simulate(plan, seed, state, counts, tg, 0, steps)
+    orig = api.unpack_bits(api.to_original(plan, state).cpu().numpy(), plan.n)
+    ref = alias.simulate(net, ref_plan, seed, np.arange(ntraj), steps, targets=tgs)
+    assert np.array_equal(orig[:, 0], ref["state"][:, 0])
+    assert np.array_equal(counts.cpu().numpy()[0, :, 0], ref["hits"][0])
+    assert ref["perturbed"].sum() > 0
