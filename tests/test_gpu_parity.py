@@ -264,3 +264,46 @@ def test_autotune_candidates_are_bit_identical(name):
         common = kept & ref[1]
         assert np.array_equal(orig[:, common], ref[0][:, common]), opts
         assert np.array_equal(c, ref[2]), opts
+
+
+def test_full_size_c2_product_configuration():
+    """C2's product configuration as timed by the benchmark (leaf reduction,
+    group size 1, every trajectory, 2 and 8 waves per workgroup): 8 sampled
+    trajectories against the oracle over 400 steps; then one 250 000-step
+    launch, the benchmark's chunk, against the unreduced plain kernel run in
+    two chunks with another launch shape -- the keyed draws make every kept
+    node and counter identical at any depth."""
+    cfg = ps.config("C2")
+    net = cfg.net
+    interest = [a for a, _ in cfg.targets[0]]
+    red = api.Plan(net, interest=interest, **REDUCED)
+    plain = api.Plan(net, interest=interest, **PLAIN)
+    kept = red.node_pos() != NONE
+    sample = np.array([0, 3, 511, 1024, 2047, 2600, 3333, 4095])
+    ref = osim.run(net, cfg.seed, sample, 400, targets=cfg.targets)
+    for wpb in (2, 8):
+        say(f"[gpu] C2 product configuration, 400 steps, wpb={wpb}")
+        tg = red.targets(cfg.targets)
+        state = api.state_init(red, cfg.seed, cfg.ntraj)
+        counts = api.new_counts(1, cfg.ntraj)
+        api.simulate(red, cfg.seed, state, counts, tg, 0, 400, waves_per_block=wpb)
+        orig = api.unpack_bits(api.to_original(red, state).cpu().numpy(), red.n)
+        assert np.array_equal(orig[sample][:, kept], ref["state"][:, kept])
+        assert np.array_equal(counts.cpu().numpy()[0, sample, 0], ref["hits"][0])
+    deep = 250000
+    runs = []
+    for plan, chunks, wpb, use_plain in ((red, (deep,), 2, True), (plain, (deep // 2, deep - deep // 2), 8, True)):
+        say(f"[gpu] C2 {deep} steps, chunks={chunks}, wpb={wpb}, n_kept={plan.info['n_kept']}")
+        tg = plan.targets(cfg.targets)
+        state = api.state_init(plan, cfg.seed, cfg.ntraj)
+        counts = api.new_counts(1, cfg.ntraj)
+        step = 0
+        for c in chunks:
+            api.simulate(plan, cfg.seed, state, counts, tg, step, c, count_from=1000, plain=use_plain,
+                         waves_per_block=wpb)
+            step += c
+        runs.append((api.unpack_bits(api.to_original(plan, state).cpu().numpy(), plan.n), counts.cpu().numpy()))
+    assert np.array_equal(runs[0][0][:, kept], runs[1][0][:, kept])
+    assert np.array_equal(runs[0][1], runs[1][1])
+    c = runs[0][1][0]
+    assert np.all(c[:, 0] <= deep - 1000) and np.all(np.abs(c[:, 1].astype(np.int64) - c[:, 2]) <= 1)
