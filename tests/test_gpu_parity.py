@@ -307,3 +307,38 @@ def test_full_size_c2_product_configuration():
     assert np.array_equal(runs[0][1], runs[1][1])
     c = runs[0][1][0]
     assert np.all(c[:, 0] <= deep - 1000) and np.all(np.abs(c[:, 1].astype(np.int64) - c[:, 2]) <= 1)
+
+
+def test_full_size_c3_product_configuration():
+    """C3 at its full trajectory count with the autotuner's plan (grouping into
+    at most 5 union bits and 4 nodes, 8 waves per workgroup): 4 sampled
+    trajectories against the oracle over 20 steps, then 20 000 steps against
+    the reduction-only plain kernel at another launch shape."""
+    cfg = ps.config("C3")
+    net = cfg.net
+    interest = sorted({a for tg in cfg.targets for a, _ in tg})
+    tuned = api.Plan(net, interest=interest, reduce=1, group=1, max_parent_bits=5, max_group_nodes=4)
+    red = api.Plan(net, interest=interest, **REDUCED)
+    assert tuned.info["n_table_slots"] > 0
+    kept = tuned.node_pos() != NONE
+    sample = np.array([0, 20000, 40001, 65535])
+    say("[gpu] C3 full size, 20 steps")
+    ref = osim.run(net, cfg.seed, sample, 20, targets=cfg.targets)
+    tg = tuned.targets(cfg.targets)
+    state = api.state_init(tuned, cfg.seed, cfg.ntraj)
+    counts = api.new_counts(len(cfg.targets), cfg.ntraj)
+    api.simulate(tuned, cfg.seed, state, counts, tg, 0, 20, waves_per_block=8)
+    orig = api.unpack_bits(api.to_original(tuned, state).cpu().numpy(), tuned.n)
+    assert np.array_equal(orig[sample][:, kept], ref["state"][:, kept])
+    assert np.array_equal(counts.cpu().numpy()[:, sample, 0], ref["hits"])
+    runs = []
+    for plan, wpb, use_plain in ((tuned, 8, False), (red, 2, True)):
+        say(f"[gpu] C3 20000 steps, n_slots={plan.info['n_slots']}, wpb={wpb}")
+        tg = plan.targets(cfg.targets)
+        state = api.state_init(plan, cfg.seed, cfg.ntraj)
+        counts = api.new_counts(len(cfg.targets), cfg.ntraj)
+        api.simulate(plan, cfg.seed, state, counts, tg, 0, 20000, count_from=10000, plain=use_plain,
+                     waves_per_block=wpb)
+        runs.append((api.unpack_bits(api.to_original(plan, state).cpu().numpy(), plan.n), counts.cpu().numpy()))
+    assert np.array_equal(runs[0][0][:, kept], runs[1][0][:, kept])
+    assert np.array_equal(runs[0][1], runs[1][1])
