@@ -231,3 +231,25 @@ def test_alias_single_kept_node_and_many_leaves():
     assert np.array_equal(orig[:, 0], ref["state"][:, 0])
     assert np.array_equal(counts.cpu().numpy()[0, :, 0], ref["hits"][0])
     assert ref["perturbed"].sum() > 0
+
+
+def test_alias_full_size_c2_sampled_against_oracle():
+    # the benchmark's alias leg at full size: all 4096 trajectories of C2 on the
+    # leaf-reduction plan at 8 waves per workgroup; 6 sampled trajectories
+    # recomputed by the alias oracle over 300 steps
+    cfg = ps.config("C2")
+    net = cfg.net
+    interest = [a for a, _ in cfg.targets[0]]
+    plan = api.Plan(net, interest=interest, reduce=1, group=0, sampling=1)
+    ref_plan = alias.alias_plan(net, interest, reduce=1, group=0)
+    sample = np.array([0, 5, 1023, 2048, 3071, 4095])
+    say("[gpu] alias C2 full size")
+    tg = plan.targets(cfg.targets)
+    state = api.state_init(plan, cfg.seed, cfg.ntraj)
+    counts = api.new_counts(1, cfg.ntraj)
+    api.simulate(plan, cfg.seed, state, counts, tg, 0, 300, waves_per_block=8)
+    orig = api.unpack_bits(api.to_original(plan, state).cpu().numpy(), plan.n)
+    ref = alias.simulate(net, ref_plan, cfg.seed, sample, 300, targets=cfg.targets)
+    kept = ref_plan["kept"]
+    assert np.array_equal(orig[sample][:, kept], ref["state"][:, kept])
+    assert np.array_equal(counts.cpu().numpy()[0, sample, 0], ref["hits"][0])
