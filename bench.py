@@ -370,7 +370,7 @@ def main():
                          "config to this precision instead of the fixed-length workload")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is design-only "
+        print(json.dumps({"error": "runs on one GPU only; sharding across GPUs is not implemented "
                                    "(trajectories shard by id, counters reduce with one integer all-reduce)"}))
         sys.exit(2)
 
