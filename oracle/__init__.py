@@ -17,4 +17,5 @@ Modules
              Partition (Alg. 4), single-predictor grouping (Sec. 3.3),
              combined predictor functions (Sec. 3.3)
   stats      estimators: trajectory means, batch means, two-state chain figures
+  skart      the Skart stopping rule (skewness- and correlation-adjusted batch means)
 """
