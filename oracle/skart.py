@@ -33,6 +33,8 @@ post-warm-up observations into min(k - d, 1024) batches, the correlation factor
 is A = max(1, (1 + phi) / (1 - phi)) with phi clipped below 0.99, the
 half-length is the larger of the two sides of the (asymmetric) interval, and a
 sequence whose batch means are all equal asks for twice as many observations.
+Every mean of batch means is the total of the observations it covers divided
+by their number, so that equal batch means give deviations of exactly zero.
 """
 import math
 
@@ -47,51 +49,59 @@ ALPHA_RAN = 0.20
 D_MAX = 10
 
 
-def batch_means(x, start, k, m):
-    """k means of consecutive batches of m observations from x[start:]."""
+def batch_sums(x, start, k, m):
+    """Sums of k consecutive batches of m observations from x[start:] (exact
+    integers for 0/1 observations)."""
     seg = np.asarray(x[start:start + k * m], dtype=np.float64)
-    return seg.reshape(k, m).mean(axis=1)
+    return seg.reshape(k, m).sum(axis=1)
 
 
-def skewness(y):
+def _mean(y, mean):
+    return float(np.mean(y)) if mean is None else float(mean)
+
+
+def _constant(y):
+    return y.size == 0 or float(np.max(y)) == float(np.min(y))
+
+
+def skewness(y, mean=None):
     """Adjusted Fisher-Pearson sample skewness; 0 for a constant sample."""
     y = np.asarray(y, dtype=np.float64)
     k = y.size
-    dev = y - y.mean()
-    m2 = float(np.mean(dev ** 2))
-    if m2 <= 0.0 or k < 3:
+    if k < 3 or _constant(y):
         return 0.0
-    g1 = float(np.mean(dev ** 3)) / m2 ** 1.5
+    dev = y - _mean(y, mean)
+    m2 = float(np.sum(dev ** 2)) / k
+    g1 = (float(np.sum(dev ** 3)) / k) / m2 ** 1.5
     return g1 * math.sqrt(k * (k - 1.0)) / (k - 2.0)
 
 
-def von_neumann(y):
+def von_neumann(y, mean=None):
     """von Neumann's ratio statistic C = 1 - sum (y_j - y_j+1)^2 / (2 sum (y_j - ybar)^2)
     and its null standard deviation sqrt((k - 2) / (k^2 - 1)); C = 0 for a
     constant sample."""
     y = np.asarray(y, dtype=np.float64)
     k = y.size
-    ss = float(np.sum((y - y.mean()) ** 2))
     sd = math.sqrt((k - 2.0) / (k * k - 1.0))
-    if ss <= 0.0:
+    if _constant(y):
         return 0.0, sd
+    ss = float(np.sum((y - _mean(y, mean)) ** 2))
     return 1.0 - float(np.sum(np.diff(y) ** 2)) / (2.0 * ss), sd
 
 
-def randomness_passes(y, alpha):
+def randomness_passes(y, alpha, mean=None):
     if len(y) < 3:
         return False
-    c, sd = von_neumann(y)
+    c, sd = von_neumann(y, mean)
     return abs(c) <= float(_st.norm.ppf(1.0 - alpha / 2.0)) * sd
 
 
-def lag1(y):
+def lag1(y, mean=None):
     y = np.asarray(y, dtype=np.float64)
-    dev = y - y.mean()
-    ss = float(np.sum(dev ** 2))
-    if ss <= 0.0:
+    if _constant(y):
         return 0.0
-    return float(np.sum(dev[:-1] * dev[1:])) / ss
+    dev = y - _mean(y, mean)
+    return float(np.sum(dev[:-1] * dev[1:])) / float(np.sum(dev ** 2))
 
 
 def willink_g(zeta, beta):
@@ -105,14 +115,14 @@ def willink_g(zeta, beta):
     return root / (2.0 * beta)
 
 
-def interval(y, conf):
+def interval(y, conf, mean=None):
     """Skewness- and correlation-adjusted batch-means interval from batch means y."""
     y = np.asarray(y, dtype=np.float64)
     k = y.size
-    mean = float(y.mean())
-    var = float(np.var(y, ddof=1))
-    c = skewness(y)
-    phi = min(lag1(y), 0.99)
+    mean = _mean(y, mean)
+    var = 0.0 if _constant(y) else float(np.sum((y - mean) ** 2)) / (k - 1)
+    c = skewness(y, mean)
+    phi = min(lag1(y, mean), 0.99)
     a = max(1.0, (1.0 + phi) / (1.0 - phi))
     beta = c / (6.0 * math.sqrt(k))
     se = math.sqrt(a * var / k)
@@ -147,8 +157,9 @@ def skart(x, r, conf=0.95):
     while True:
         if k * m > n_have:
             return need(k * m)
-        y = batch_means(x, 0, k, m)
-        if abs(skewness(y[k - int(0.8 * k):])) <= SKEW_LIMIT:
+        sums = batch_sums(x, 0, k, m)
+        tail = sums[k - int(0.8 * k):]
+        if abs(skewness(tail / m, tail.sum() / (tail.size * m))) <= SKEW_LIMIT:
             break
         m *= 2
         st["m"] = m
@@ -158,9 +169,14 @@ def skart(x, r, conf=0.95):
         st["m"], st["k"], st["b"] = m, k, b
         if k * m > n_have:
             return need(k * m)
-        y = batch_means(x, 0, k, m)
+        sums = batch_sums(x, 0, k, m)
         alpha = ALPHA_RAN * math.exp(-0.184 * b * b)
-        d = next((dd for dd in range(D_MAX + 1) if randomness_passes(y[dd::dd + 1], alpha)), None)
+        d = None
+        for dd in range(D_MAX + 1):
+            sp = sums[dd::dd + 1]          # every (d+1)-th batch, d spacer batches before each
+            if randomness_passes(sp / m, alpha, sp.sum() / (sp.size * m)):
+                d = dd
+                break
         if d is not None:
             break
         b += 1
@@ -176,8 +192,8 @@ def skart(x, r, conf=0.95):
         n = w + kc * mc
         if n > n_have:
             return need(n)
-        y = batch_means(x, w, kc, mc)
-        ci = interval(y, conf)
+        sums = batch_sums(x, w, kc, mc)
+        ci = interval(sums / mc, conf, sums.sum() / (kc * mc))
         st.update(p_hat=ci["mean"], lower=ci["lower"], upper=ci["upper"], half_width=ci["half_width"],
                   skewness=ci["skewness"], lag1=ci["lag1"], ar_factor=ci["ar_factor"])
         if ci["var"] > 0.0 and ci["half_width"] <= r:
