@@ -345,6 +345,41 @@ def bench_rl(args):
     print(json.dumps(out))
 
 
+def bench_skart(args):
+    """The Skart stopping rule end to end on one trajectory: simulate, record the
+    target indicator, analyse (batch size, spacers and warm-up, adjusted
+    interval) and extend until the half-length meets the precision
+    (pbn_skart_run)."""
+    cfg = ps.config(args.config)
+    n = cfg.net["n"]
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(args.config, 1, 20000)
+    import torch
+    from paper_1605_00854_amd import api
+    torch.cuda.set_device(0)
+    interest = sorted({a for tg in cfg.targets for a, _ in tg})
+    plan = api.Plan(cfg.net, interest=interest, reduce=1, group=0)
+    api.skart_run(plan, cfg.seed + 1, cfg.targets, 0.05, max_steps=1 << 20)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, _ = api.skart_run(plan, cfg.seed, cfg.targets, args.skart, max_steps=(1 << 32) - 2)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = {"metric": "Skart estimate on 1 MI355X: simulated steps/s of the driver",
+           "value": res["steps"] / dt, "unit": "steps/s (one trajectory)", "n_gpus": 1, "steps": 1, "warmup": 1,
+           "ms_per_step": 1e3 * dt, "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
+           "dtype": "u32", "data": "synthetic",
+           "config": {"workload": f"{args.config}: one trajectory to precision {args.skart} at confidence 0.95 "
+                                  f"(n = {n})", "plan": {"reduce": 1, "group": 0}},
+           "result": {k: res[k] for k in ("status", "done", "batch_size", "batch_count", "spacer", "failures",
+                                          "warmup", "ci_batches", "ci_batch_size", "p_hat", "lower", "upper",
+                                          "half_width", "skewness", "lag1", "ar_factor", "steps")},
+           "node_updates_per_s": res["steps"] * n / dt, "seconds": dt,
+           "cpu_baseline": cpu}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -368,6 +403,9 @@ def main():
     ap.add_argument("--rl", type=float, default=0.0,
                     help="run the two-state Markov chain (Raftery-Lewis) driver on one trajectory of the "
                          "config to this precision instead of the fixed-length workload")
+    ap.add_argument("--skart", type=float, default=0.0,
+                    help="run the Skart driver on one trajectory of the config to this precision instead of "
+                         "the fixed-length workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "runs on one GPU only; sharding across GPUs is not implemented "
@@ -378,6 +416,8 @@ def main():
         return bench_planner_fit(args)
     if args.rl:
         return bench_rl(args)
+    if args.skart:
+        return bench_skart(args)
     if args.config == "C4":
         return bench_batch(args)
     if args.config == "C5":

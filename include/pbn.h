@@ -375,6 +375,58 @@ pbn_status pbn_rl_run(const pbn_plan* plan, const void* d_plan, uint64_t seed, u
                       uint64_t initial_steps, uint64_t max_steps, const pbn_launch_opts* launch, pbn_rl_out* out,
                       void* stream);
 
+/* The Skart stopping rule (Tafazzoli, Steiger and Wilson, 2011), the second
+ * steady-state procedure the paper's authors name beside the two-state Markov
+ * chain approach (Section 1), on one recorded hit-indicator sequence: bits[t >>
+ * 5] bit (t & 31) = z_t for t = 0 .. nbits-1 (host array, caller-owned).
+ * Steps, replayed from the start on every call:
+ *   1  1280 batches of size m = 1; m doubles while the skewness of the last
+ *      1024 batch means exceeds 4 in magnitude;
+ *   2  von Neumann's ratio test (two-sided, size 0.20 exp(-0.184 b^2) after b
+ *      failures) on every (d+1)-th batch mean, d = 0 .. 10 spacer batches; when
+ *      every d fails, m <- ceil(sqrt(2) m), k <- max(ceil(0.9 k), 30);
+ *   3  warm-up d m observations; the rest in min(k - d, 1024) batches; the
+ *      interval mean -/+ G(t) sqrt(A S^2 / k) with Willink's skewness-adjusted
+ *      G and A = max(1, (1 + phi) / (1 - phi)) from the lag-one correlation phi
+ *      (clipped at 0.99); while the larger half-length exceeds `precision`, the
+ *      sample grows by (half-length / precision)^2 (batches up to 1024, then
+ *      batch size), or doubles when all batch means are equal.
+ * A step that needs more than nbits observations stops there: done = 0 and
+ * n_required = the observations it needs (a longer replay of the same
+ * sequence takes the same decisions up to that step).  With done = 1,
+ * n_required = the observations used and the interval fields hold the result.
+ * Errors: PBN_EINVAL (null pointers, precision <= 0, conf outside (0, 1)). */
+typedef struct pbn_skart_out {
+  uint32_t done;
+  uint32_t stage;           /* 1, 2, 3: the step reached */
+  uint64_t n_required;
+  uint64_t batch_size;      /* m of steps 1-2 */
+  uint32_t batch_count;     /* k of steps 1-2 */
+  uint32_t spacer;          /* d */
+  uint32_t failures;        /* b */
+  uint32_t ci_batches;      /* batches of the interval */
+  uint64_t ci_batch_size;
+  uint64_t warmup;          /* d m observations */
+  double p_hat, lower, upper, half_width;
+  double skewness, lag1, ar_factor;   /* of the interval's batch means */
+  uint64_t steps;           /* nbits */
+} pbn_skart_out;
+
+pbn_status pbn_skart_analyze(const uint32_t* bits, uint64_t nbits, double precision, double conf,
+                             pbn_skart_out* out);
+
+/* Blocking Skart driver on one trajectory (id `traj`), like pbn_rl_run: s(0)
+ * from the INIT stream, simulate from step 0 recording target 0's indicator,
+ * run pbn_skart_analyze, and extend the same trajectory to the number of
+ * observations it asks for until it finishes.  Buffers, limits and errors as
+ * pbn_rl_run (PBN_ERANGE when the procedure asks for more than min(max_steps,
+ * 32 record_words) steps; `out` holds the last analysis).  Synchronises
+ * `stream`. */
+pbn_status pbn_skart_run(const pbn_plan* plan, const void* d_plan, uint64_t seed, uint32_t traj,
+                         const pbn_targets* targets, uint32_t* d_state, uint64_t* d_counts, uint32_t* d_record,
+                         uint32_t record_words, double precision, double conf, uint64_t max_steps,
+                         const pbn_launch_opts* launch, pbn_skart_out* out, void* stream);
+
 /* Quantiles used by pbn_estimate: Student t with nu degrees of freedom, and the
  * standard normal.  p in (0, 1). */
 double pbn_t_quantile(double p, double nu);

@@ -56,6 +56,15 @@ class pbn_rl_out(C.Structure):
                 ("n_required", C.c_double), ("p_hat", C.c_double), ("steps", C.c_uint64)]
 
 
+class pbn_skart_out(C.Structure):
+    _fields_ = [("done", C.c_uint32), ("stage", C.c_uint32), ("n_required", C.c_uint64),
+                ("batch_size", C.c_uint64), ("batch_count", C.c_uint32), ("spacer", C.c_uint32),
+                ("failures", C.c_uint32), ("ci_batches", C.c_uint32), ("ci_batch_size", C.c_uint64),
+                ("warmup", C.c_uint64), ("p_hat", C.c_double), ("lower", C.c_double), ("upper", C.c_double),
+                ("half_width", C.c_double), ("skewness", C.c_double), ("lag1", C.c_double),
+                ("ar_factor", C.c_double), ("steps", C.c_uint64)]
+
+
 class pbn_work(C.Structure):
     _fields_ = [("d_plan", C.c_void_p), ("d_targets", C.c_void_p), ("d_state", C.c_void_p),
                 ("d_counts", C.c_void_p), ("seed", C.c_uint64), ("traj0", C.c_uint32),
@@ -103,6 +112,9 @@ SIGNATURES = {
     "pbn_graph_launch": (C.c_int32, [_P, _P]),
     "pbn_graph_destroy": (C.c_int32, [_P]),
     "pbn_estimate": (C.c_int32, [_pU64, _U32, _U64, C.c_double, C.c_double, C.POINTER(pbn_estimate_out)]),
+    "pbn_skart_analyze": (C.c_int32, [_pU32, _U64, C.c_double, C.c_double, C.POINTER(pbn_skart_out)]),
+    "pbn_skart_run": (C.c_int32, [_P, _P, _U64, _U32, C.POINTER(pbn_targets), _P, _P, _P, _U32, C.c_double,
+                                  C.c_double, _U64, C.POINTER(pbn_launch_opts), C.POINTER(pbn_skart_out), _P]),
     "pbn_rl_diagnose": (C.c_int32, [_pU32, _U64, C.c_double, C.c_double, C.c_double, _U32,
                                     C.POINTER(pbn_rl_out)]),
     "pbn_rl_run": (C.c_int32, [_P, _P, _U64, _U32, C.POINTER(pbn_targets), _P, _P, _P, _U32, C.c_double,

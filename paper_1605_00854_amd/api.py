@@ -197,6 +197,38 @@ def rl_diagnose(bits, nbits, precision, conf=0.95, eps=1e-3, kmax=100):
     return {name: getattr(out, name) for name, _ in out._fields_ if name != "reserved"}
 
 
+def skart_analyze(bits, nbits, precision, conf=0.95):
+    """pbn_skart_analyze on a host bit array (uint32 words, bit t = z_t)."""
+    w = np.ascontiguousarray(np.asarray(bits).view(np.uint32) if np.asarray(bits).dtype == np.int32
+                             else np.asarray(bits, dtype=np.uint32))
+    out = _lib.pbn_skart_out()
+    check(lib().pbn_skart_analyze(_ptr(w, C.c_uint32), int(nbits), float(precision), float(conf), C.byref(out)))
+    return {name: getattr(out, name) for name, _ in out._fields_}
+
+
+def skart_run(plan, seed, target_sets, precision, *, traj=0, conf=0.95, max_steps=1 << 28, waves_per_block=0,
+              stream=None):
+    """Skart stopping rule on one trajectory (pbn_skart_run, blocking).
+
+    Returns (analysis dict with "status", recorded indicator words as a device tensor)."""
+    import torch
+    tg = plan.targets(target_sets)
+    words = (int(max_steps) + 31) // 32
+    state = new_state(plan, 1)
+    counts = new_counts(tg.ntargets, 1)
+    record = torch.zeros(words, dtype=torch.int32, device="cuda")
+    lo = _lib.pbn_launch_opts(int(waves_per_block))
+    out = _lib.pbn_skart_out()
+    rc = lib().pbn_skart_run(plan.handle, _dptr(plan.device()), int(seed), int(traj), C.byref(tg), _dptr(state),
+                             _dptr(counts), _dptr(record), words, float(precision), float(conf), int(max_steps),
+                             C.byref(lo), C.byref(out), _stream(stream))
+    res = {name: getattr(out, name) for name, _ in out._fields_}
+    res["status"] = int(rc)
+    if rc not in (0, _lib.ERANGE):
+        check(rc)
+    return res, record
+
+
 def unpack_record(words, nbits):
     """0/1 array of the first nbits bits of recorded words (bit t of word t // 32)."""
     w = np.asarray(words).view(np.uint32).reshape(-1)

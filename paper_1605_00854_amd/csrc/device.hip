@@ -1143,6 +1143,52 @@ extern "C" pbn_status pbn_rl_run(const pbn_plan* plan, const void* d_plan, uint6
   }
 }
 
+extern "C" pbn_status pbn_skart_run(const pbn_plan* plan, const void* d_plan, uint64_t seed, uint32_t traj,
+                                     const pbn_targets* targets, uint32_t* d_state, uint64_t* d_counts,
+                                     uint32_t* d_record, uint32_t record_words, double precision, double conf,
+                                     uint64_t max_steps, const pbn_launch_opts* launch, pbn_skart_out* out,
+                                     void* stream) {
+  pbn::clear_error();
+  if (!plan || !d_plan || !targets || !d_state || !d_counts || !d_record || !out || record_words == 0)
+    return fail(PBN_EINVAL, "null argument");
+  *out = pbn_skart_out{};
+  const uint64_t cap = std::min<uint64_t>(32ull * record_words, max_steps);
+  if (cap >= 0xFFFFFFFFull) return fail(PBN_ERANGE, "max_steps must stay below 2^32");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  pbn_status st = hip_check(hipMemsetAsync(d_record, 0, 4ull * record_words, s), "hipMemsetAsync");
+  if (st == PBN_OK)
+    st = hip_check(hipMemsetAsync(d_counts, 0, 24ull * targets->ntargets, s), "hipMemsetAsync");
+  if (st == PBN_OK) st = pbn_state_init(plan, d_plan, seed, traj, 1, d_state, stream);
+  if (st != PBN_OK) return st;
+  pbn_launch_opts lo{};
+  if (launch) lo = *launch;
+  lo.record_traj = 1;
+  lo.record_words = record_words;
+  lo.d_record = d_record;
+  std::vector<uint32_t> host;
+  uint64_t done = 0, want = 1280;   // the procedure's first sample
+  for (;;) {
+    if (want > cap) {
+      out->n_required = want;
+      return fail(PBN_ERANGE, "the procedure asks for more steps than max_steps or the record buffer");
+    }
+    while (done < want) {   // launches of at most 2^24 steps
+      const uint32_t chunk = uint32_t(std::min<uint64_t>(want - done, 1ull << 24));
+      st = simulate_common(plan->has_table == 0, plan, d_plan, seed, traj, 1, uint32_t(done), chunk, 0, targets,
+                           d_state, d_counts, &lo, stream);
+      if (st != PBN_OK) return st;
+      done += chunk;
+    }
+    const size_t words = size_t((done + 31) / 32);
+    host.resize(words);
+    st = hip_check(hipMemcpyAsync(host.data(), d_record, 4 * words, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    if (st == PBN_OK) st = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (st == PBN_OK) st = pbn_skart_analyze(host.data(), done, precision, conf, out);
+    if (st != PBN_OK || out->done) return st;
+    want = std::max<uint64_t>(out->n_required, done + 1);
+  }
+}
+
 extern "C" pbn_status pbn_state_to_original(const pbn_plan* plan, const void* d_plan, const uint32_t* d_state,
                                             uint32_t ntraj, uint32_t* d_out, void* stream) {
   pbn::clear_error();

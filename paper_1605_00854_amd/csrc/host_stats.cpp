@@ -3,6 +3,7 @@
 // trajectory (batch means).  The paper estimates steady-state probabilities
 // with the two-state Markov chain approach of Raftery and Lewis (Sections 1
 // and 4.2); its published figures are reported beside the confidence interval.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -240,4 +241,176 @@ extern "C" pbn_status pbn_rl_diagnose(const uint32_t* bits, uint64_t nbits, doub
     }
   }
   return PBN_OK;
+}
+
+// ------------------------------------------------------------------ Skart
+// The Skart stopping rule (Tafazzoli, Steiger and Wilson, 2011), the second
+// steady-state procedure the paper's authors name beside the two-state Markov
+// chain approach (Section 1), on a recorded 0/1 sequence.  Batch sums are
+// counted from the packed bits; every mean of batch means is the number of ones
+// it covers over the number of observations, so equal batch means deviate by
+// exactly zero.
+
+namespace {
+
+constexpr uint32_t kSkK0 = 1280, kSkKmax = 1024, kSkKmin = 30, kSkDmax = 10;
+constexpr double kSkSkew = 4.0, kSkAlpha = 0.20;
+
+// ones among bits [a, b)
+uint64_t ones_in(const uint32_t* w, uint64_t a, uint64_t b) {
+  uint64_t c = 0;
+  while (a < b && (a & 31u)) c += bit_at(w, a++);
+  for (; a + 32 <= b; a += 32) c += uint64_t(__builtin_popcount(w[a >> 5]));
+  while (a < b) c += bit_at(w, a++);
+  return c;
+}
+
+// Moments of the batch means c_j / m of the sums listed in `c` (n of them).
+struct BatchStats {
+  bool constant;
+  double mean, ss, s3, sdiff2, slag;
+};
+
+BatchStats batch_stats(const std::vector<uint64_t>& c, uint64_t m) {
+  BatchStats r{true, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const size_t n = c.size();
+  uint64_t total = 0;
+  for (size_t j = 0; j < n; ++j) {
+    total += c[j];
+    if (c[j] != c[0]) r.constant = false;
+  }
+  const double dm = double(m);
+  r.mean = double(total) / (double(n) * dm);
+  if (r.constant) return r;
+  double prev = 0.0;
+  for (size_t j = 0; j < n; ++j) {
+    const double y = double(c[j]) / dm, dev = y - r.mean;
+    r.ss += dev * dev;
+    r.s3 += dev * dev * dev;
+    if (j) {
+      const double yp = double(c[j - 1]) / dm;
+      r.sdiff2 += (y - yp) * (y - yp);
+      r.slag += prev * dev;
+    }
+    prev = dev;
+  }
+  return r;
+}
+
+double sample_skewness(const BatchStats& s, size_t k) {
+  if (k < 3 || s.constant) return 0.0;
+  const double kk = double(k), m2 = s.ss / kk, g1 = (s.s3 / kk) / std::pow(m2, 1.5);
+  return g1 * std::sqrt(kk * (kk - 1.0)) / (kk - 2.0);
+}
+
+double willink(double zeta, double beta) {
+  if (beta == 0.0) return zeta;
+  const double u = 6.0 * beta * (zeta - beta);
+  const double root = u > -1.0 ? std::expm1(std::log1p(u) / 3.0) : std::cbrt(1.0 + u) - 1.0;
+  return root / (2.0 * beta);
+}
+
+std::vector<uint64_t> sums_of(const uint32_t* bits, uint64_t start, uint64_t k, uint64_t m) {
+  std::vector<uint64_t> c(k);
+  for (uint64_t j = 0; j < k; ++j) c[j] = ones_in(bits, start + j * m, start + (j + 1) * m);
+  return c;
+}
+
+}  // namespace
+
+extern "C" pbn_status pbn_skart_analyze(const uint32_t* bits, uint64_t nbits, double precision, double conf,
+                                        pbn_skart_out* out) {
+  pbn::clear_error();
+  if (!out || (nbits && !bits)) return fail(PBN_EINVAL, "null argument");
+  if (!(conf > 0 && conf < 1) || !(precision > 0)) return fail(PBN_EINVAL, "bad precision/confidence");
+  const double nan = std::numeric_limits<double>::quiet_NaN();
+  *out = pbn_skart_out{};
+  out->p_hat = out->lower = out->upper = out->half_width = nan;
+  out->skewness = out->lag1 = out->ar_factor = nan;
+  out->steps = nbits;
+  auto need = [&](uint64_t n) {
+    out->n_required = n;
+    return PBN_OK;
+  };
+  // batch size until the last 80 % of the batch means are nearly symmetric
+  uint64_t m = 1, k = kSkK0;
+  out->stage = 1;
+  for (;;) {
+    out->batch_size = m;
+    out->batch_count = uint32_t(k);
+    if (k * m > nbits) return need(k * m);
+    const std::vector<uint64_t> all = sums_of(bits, 0, k, m);
+    const std::vector<uint64_t> tail(all.begin() + (k - uint64_t(0.8 * double(k))), all.end());
+    if (std::fabs(sample_skewness(batch_stats(tail, m), tail.size())) <= kSkSkew) break;
+    m *= 2;
+  }
+  // randomness test of batch means spaced by d batches; the spacer fixes the warm-up
+  out->stage = 2;
+  uint32_t b = 0, d = 0;
+  for (;;) {
+    out->batch_size = m;
+    out->batch_count = uint32_t(k);
+    out->failures = b;
+    if (k * m > nbits) return need(k * m);
+    const std::vector<uint64_t> all = sums_of(bits, 0, k, m);
+    const double alpha = kSkAlpha * std::exp(-0.184 * double(b) * double(b));
+    const double zc = normal_quantile(1.0 - alpha / 2.0);
+    bool pass = false;
+    for (d = 0; d <= kSkDmax && !pass; ++d) {
+      std::vector<uint64_t> sp;
+      for (uint64_t j = d; j < k; j += d + 1) sp.push_back(all[j]);
+      const size_t kk = sp.size();
+      if (kk < 3) continue;
+      const BatchStats s = batch_stats(sp, m);
+      const double c = s.constant ? 0.0 : 1.0 - s.sdiff2 / (2.0 * s.ss);
+      const double sd = std::sqrt((double(kk) - 2.0) / (double(kk) * double(kk) - 1.0));
+      if (std::fabs(c) <= zc * sd) pass = true;
+    }
+    if (pass) {
+      --d;
+      break;
+    }
+    ++b;
+    m = uint64_t(std::ceil(std::sqrt(2.0) * double(m)));
+    k = std::max<uint64_t>(uint64_t(std::ceil(0.9 * double(k))), kSkKmin);
+  }
+  const uint64_t w = uint64_t(d) * m;
+  out->spacer = d;
+  out->warmup = w;
+  // interval on the post-warm-up observations, enlarged until precise enough
+  out->stage = 3;
+  uint64_t kc = std::min<uint64_t>(k - d, kSkKmax);
+  uint64_t mc = (k * m - w) / kc;
+  for (;;) {
+    out->ci_batches = uint32_t(kc);
+    out->ci_batch_size = mc;
+    const uint64_t n = w + kc * mc;
+    if (n > nbits) return need(n);
+    const std::vector<uint64_t> c = sums_of(bits, w, kc, mc);
+    const BatchStats s = batch_stats(c, mc);
+    const double kk = double(kc);
+    const double var = s.constant ? 0.0 : s.ss / (kk - 1.0);
+    const double skew = sample_skewness(s, kc);
+    const double phi = std::fmin(s.constant ? 0.0 : s.slag / s.ss, 0.99);
+    const double a = std::fmax(1.0, (1.0 + phi) / (1.0 - phi));
+    const double beta = skew / (6.0 * std::sqrt(kk));
+    const double se = std::sqrt(a * var / kk);
+    const double tq = t_quantile(0.5 + conf / 2.0, kk - 1.0);
+    const double lo = s.mean - willink(tq, beta) * se, hi = s.mean - willink(-tq, beta) * se;
+    out->p_hat = s.mean;
+    out->lower = lo;
+    out->upper = hi;
+    out->half_width = std::fmax(s.mean - lo, hi - s.mean);
+    out->skewness = skew;
+    out->lag1 = phi;
+    out->ar_factor = a;
+    if (var > 0.0 && out->half_width <= precision) {
+      out->done = 1;
+      return need(n);
+    }
+    const double f = var > 0.0 ? (out->half_width / precision) * (out->half_width / precision) : 2.0;
+    const double grow = f * kk;
+    mc = uint64_t(std::ceil(double(mc) * std::fmax(1.0, grow / double(kSkKmax))));
+    kc = std::min<uint64_t>(uint64_t(std::ceil(grow)), kSkKmax);
+  }
 }

@@ -190,6 +190,10 @@ void exercise_stats(Rng& r) {
     pbn_rl_out o{};
     const pbn_status s2 = pbn_rl_diagnose(bits.data(), nbits, 0.01, 0.95, 1e-3, 100, &o);
     CHECK(s2 == PBN_OK || s2 == PBN_EINVAL || s2 == PBN_ERANGE);
+    pbn_skart_out so{};
+    CHECK(pbn_skart_analyze(bits.data(), nbits, 0.001 + 0.1 * r.unit(), 0.95, &so) == PBN_OK);
+    CHECK(so.done ? so.n_required <= nbits : so.n_required > nbits);
+    CHECK(pbn_skart_analyze(bits.data(), nbits, 0.0, 0.95, &so) == PBN_EINVAL);
     std::vector<uint64_t> w(1 + r.below(12));
     for (auto& x : w) x = 2 + r.below(1000);
     uint32_t m = 0;

@@ -345,3 +345,54 @@ def test_rl_diagnosis_matches_oracle(kind):
             assert a == pytest.approx(b, rel=1e-9, abs=1e-12), key
     with pytest.raises(_lib.PbnError):
         api.rl_diagnose(_pack_bits(z), 2, 1e-3)
+
+
+def _skart_sequence(kind, rng):
+    if kind == "two_state":
+        z = np.zeros(400000, dtype=np.uint8)
+        u = rng.random(z.size)
+        for t in range(1, z.size):
+            z[t] = (u[t] < 0.01) if z[t - 1] == 0 else (u[t] >= 0.05)
+        return z
+    if kind == "sticky":                      # long runs: spacers and batch-size growth
+        lens = rng.geometric(0.002, size=4000)
+        return (np.repeat(np.arange(lens.size) % 2, lens)[:900000]).astype(np.uint8)
+    if kind == "rare":                         # skewed batch means: batch size doubles
+        return (rng.random(700000) < 0.003).astype(np.uint8)
+    if kind == "iid":
+        return (rng.random(300000) < 0.3).astype(np.uint8)
+    if kind == "short":
+        return (rng.random(1000) < 0.5).astype(np.uint8)
+    if kind == "constant":
+        return np.ones(50000, dtype=np.uint8)
+    return np.tile(np.array([0, 0, 1], dtype=np.uint8), 20000)   # equal batch sums at m = 3 k
+
+
+@pytest.mark.parametrize("kind", ["two_state", "sticky", "rare", "iid", "short", "constant", "periodic"])
+@pytest.mark.parametrize("precision", [0.02, 0.004])
+def test_skart_analysis_matches_oracle(kind, precision):
+    from oracle import skart as osk
+    z = _skart_sequence(kind, np.random.default_rng(31))
+    words = _pack_bits(z)
+    for n in (z.size, z.size // 3):
+        got = api.skart_analyze(words, n, precision)
+        want = osk.skart(z[:n], precision)
+        assert bool(got["done"]) == want["done"] and got["n_required"] == want["n_required"]
+        assert (got["batch_size"], got["batch_count"], got["failures"]) == (want["m"], want["k"], want["b"])
+        assert (got["spacer"], got["warmup"]) == (want["d"], want["warmup"])
+        assert (got["ci_batches"], got["ci_batch_size"]) == (want["k_ci"], want["m_ci"])
+        assert got["steps"] == n
+        for key, okey in (("p_hat", "p_hat"), ("lower", "lower"), ("upper", "upper"), ("half_width", "half_width"),
+                          ("skewness", "skewness"), ("lag1", "lag1"), ("ar_factor", "ar_factor")):
+            a, b = got[key], want[okey]
+            if math.isnan(b):
+                assert math.isnan(a), key
+            else:
+                assert a == pytest.approx(b, rel=1e-9, abs=1e-12), key
+
+
+def test_skart_rejects_bad_arguments():
+    words = _pack_bits(np.ones(2000, dtype=np.uint8))
+    for prec, conf in ((0.0, 0.95), (0.01, 1.0), (0.01, 0.0)):
+        with pytest.raises(_lib.PbnError):
+            api.skart_analyze(words, 2000, prec, conf)
