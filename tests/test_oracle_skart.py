@@ -113,6 +113,9 @@ def test_willink_adjustment():
     gap_t = abs(miss_t[0] - miss_t[1]) / reps
     gap_w = abs(miss_w[0] - miss_w[1]) / reps
     assert gap_t > 0.03 and gap_w < gap_t / 2
+    # so the procedure's interval of right-skewed batch means reaches further up than down
+    ci = sk.interval(rng.exponential(size=200), 0.95)
+    assert ci["skewness"] > 0.5 and ci["upper"] - ci["mean"] > 1.05 * (ci["mean"] - ci["lower"])
 
 
 def test_batch_size_rule_on_bernoulli_data():
