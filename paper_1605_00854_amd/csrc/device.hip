@@ -477,6 +477,9 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   // FN-only plans with register-held slots read target values from the pass
   // ballots (state byte b = bit b % 64 of pass b / 64's ballot)
   constexpr bool kBallotTargets = UM == 0 && kCached;
+  // ... and mark a fill's perturbation-only steps before its steps (one scalar
+  // bit per step), so that a step reads its chain word only when it perturbs
+  constexpr bool kPre = kBallotTargets && !ALIAS;
   using Regs = SlotRegs<XW, TTW>;
   const pbn_plan_header* H = reinterpret_cast<const pbn_plan_header*>(a.blob);
   const uint32_t lane = threadIdx.x & 63u;
@@ -688,10 +691,25 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
       }
       wave_sync();
     }
+    uint32_t pmask = 0u;                 // kPre: bit s = step s of the fill is perturbation-only
+    if constexpr (kPre) {
+      bool pert = false;
+      if (lane < scount) {
+        const uint2 pr = *reinterpret_cast<const uint2*>(ring + lane * njobs);
+        pert = pr.y > qn_hi || (pr.y == qn_hi && pr.x >= qn_lo);
+      }
+      pmask = uint32_t(__ballot(pert));   // scount <= 32
+    }
     for (uint32_t s = 0; s < scount; ++s, ++t) {
       const uint8_t* rs = reinterpret_cast<const uint8_t*>(ring + s * njobs);
-      const uint2 pr = *reinterpret_cast<const uint2*>(rs);
-      const uint32_t ulo = uniform(pr.x), uhi = uniform(pr.y);
+      uint32_t ulo = 0u, uhi = 0u;
+      if constexpr (!kPre) {
+        const uint2 pr = *reinterpret_cast<const uint2*>(rs);
+        ulo = uniform(pr.x);
+        uhi = uniform(pr.y);
+      }
+      const bool pert_step = kPre ? ((pmask >> s) & 1u) != 0u
+                                  : !ALIAS && (uhi > qn_hi || (uhi == qn_hi && ulo >= qn_lo));
       uint8_t* csb = reinterpret_cast<uint8_t*>(cur ? sbuf1 : sbuf0);
       bool z = false;
       if (ALIAS && uhi != 0u) {
@@ -706,9 +724,14 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
         }
         wave_sync();
         z = target_z(csb);
-      } else if (!ALIAS && (uhi > qn_hi || (uhi == qn_hi && ulo >= qn_lo))) {
+      } else if (pert_step) {
         // u >= Q[n]: perturbation-only step; walk the skip chain over all n
         // original nodes, flipping kept nodes in place
+        if constexpr (kPre) {
+          const uint2 pr = *reinterpret_cast<const uint2*>(rs);
+          ulo = uniform(pr.x);
+          uhi = uniform(pr.y);
+        }
         unsigned long long u = (static_cast<unsigned long long>(uhi) << 32) | ulo;
         uint32_t j0 = 0;
         for (;;) {
