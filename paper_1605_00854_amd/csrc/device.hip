@@ -478,8 +478,8 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   // ballots (state byte b = bit b % 64 of pass b / 64's ballot)
   constexpr bool kBallotTargets = UM == 0 && kCached;
   // ... and mark a fill's perturbation-only steps before its steps (one scalar
-  // bit per step), so that a step reads its chain word only when it perturbs
-  constexpr bool kPre = kBallotTargets && !ALIAS;
+  // bit per step), so that no step waits on its perturbation word to branch
+  constexpr bool kPre = kBallotTargets;
   using Regs = SlotRegs<XW, TTW>;
   const pbn_plan_header* H = reinterpret_cast<const pbn_plan_header*>(a.blob);
   const uint32_t lane = threadIdx.x & 63u;
@@ -696,7 +696,8 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
       bool pert = false;
       if (lane < scount) {
         const uint2 pr = *reinterpret_cast<const uint2*>(ring + lane * njobs);
-        pert = pr.y > qn_hi || (pr.y == qn_hi && pr.x >= qn_lo);
+        // alias sampling: word 1 is the step's resolved perturbed flag
+        pert = ALIAS ? pr.y != 0u : pr.y > qn_hi || (pr.y == qn_hi && pr.x >= qn_lo);
       }
       pmask = uint32_t(__ballot(pert));   // scount <= 32
     }
@@ -708,11 +709,10 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
         ulo = uniform(pr.x);
         uhi = uniform(pr.y);
       }
-      const bool pert_step = kPre ? ((pmask >> s) & 1u) != 0u
-                                  : !ALIAS && (uhi > qn_hi || (uhi == qn_hi && ulo >= qn_lo));
+      const bool pert_step = kPre ? ((pmask >> s) & 1u) != 0u : uhi > qn_hi || (uhi == qn_hi && ulo >= qn_lo);
       uint8_t* csb = reinterpret_cast<uint8_t*>(cur ? sbuf1 : sbuf0);
       bool z = false;
-      if (ALIAS && uhi != 0u) {
+      if (ALIAS && (kPre ? pert_step : uhi != 0u)) {
         // perturbation-only step (Algorithm 5): flip the nodes of every
         // group's pattern in place; pattern bit b of group q is kept node q k + b
         const uint32_t* rw = reinterpret_cast<const uint32_t*>(rs);
@@ -724,7 +724,7 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
         }
         wave_sync();
         z = target_z(csb);
-      } else if (pert_step) {
+      } else if (!ALIAS && pert_step) {
         // u >= Q[n]: perturbation-only step; walk the skip chain over all n
         // original nodes, flipping kept nodes in place
         if constexpr (kPre) {
