@@ -141,12 +141,11 @@ __device__ __forceinline__ T* uniform_ptr(T* p) {
   return reinterpret_cast<T*>(uniform64(reinterpret_cast<unsigned long long>(p)));
 }
 
-// (b ^ want) & care in one VALU instruction (three-input bitwise op); the
-// table is symmetric in its first and third inputs.
+// (b ^ want) & care: the compiler forms the three-input bitwise instruction
+// itself (b is usually a ballot just written by a vector compare; written out
+// here, the compiler also inserts the wait that such a read needs).
 __device__ __forceinline__ uint32_t masked_xor(uint32_t b, uint32_t care, uint32_t want) {
-  uint32_t r;
-  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x48" : "=v"(r) : "s"(b), "v"(care), "v"(want));
-  return r;
+  return (b ^ want) & care;
 }
 
 // (a << 1) | b in one VALU instruction (keeps gather chains from being
