@@ -220,6 +220,19 @@ __device__ __forceinline__ uint32_t gather(const uint8_t* cs, const uint32_t* pw
   return idx;
 }
 
+// The same gather from a state held as one 64-bit word (bit b = state byte b):
+// the shift takes the position's low 6 bits.
+template <int K>
+__device__ __forceinline__ uint32_t gather_bits(unsigned long long st, const uint32_t* pw) {
+  uint32_t b[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) b[k] = uint32_t(st >> (((k & 1) ? (pw[k >> 1] >> 16) : pw[k >> 1]) & 63u)) & 1u;
+  uint32_t idx = b[K - 1];
+#pragma unroll
+  for (int k = K - 2; k >= 0; --k) idx = shl1_or(idx, b[k]);
+  return idx;
+}
+
 __device__ __forceinline__ uint32_t choose(uint32_t w, uint32_t t0, uint32_t t1, uint32_t t2, uint32_t nfn) {
   const uint32_t j = uint32_t(w >= t0) + uint32_t(w >= t1) + uint32_t(w >= t2);
   return min(j, nfn - 1u);
@@ -304,11 +317,17 @@ __device__ __forceinline__ FnRec<Shape<PM, UM>::PW, Shape<PM, UM>::TTW> load_fn(
   return r;
 }
 
-// Look up an FN record's truth table over its parents in state `cs`.
-template <int PM, int UM>
-__device__ __forceinline__ uint32_t eval_fn(const FnRec<Shape<PM, UM>::PW, Shape<PM, UM>::TTW>& r, const uint8_t* cs) {
+// Look up an FN record's truth table over its parents in state `cs` (bytes in
+// LDS) or, with REG, in the 64-bit state `st`.
+template <int PM, int UM, bool REG = false>
+__device__ __forceinline__ uint32_t eval_fn(const FnRec<Shape<PM, UM>::PW, Shape<PM, UM>::TTW>& r, const uint8_t* cs,
+                                            unsigned long long st = 0ull) {
   constexpr int TTW = Shape<PM, UM>::TTW;
-  const uint32_t idx = gather<PM>(cs, r.pw);
+  uint32_t idx;
+  if constexpr (REG)
+    idx = gather_bits<PM>(st, r.pw);
+  else
+    idx = gather<PM>(cs, r.pw);
   uint32_t ttw = r.tt[0];
   if constexpr (TTW > 1) {
     // word idx / 32 of the 128-bit table, selected among scalars (an indexed
@@ -423,10 +442,10 @@ __device__ __forceinline__ uint32_t eval_slot(const SlotRegs<Shape<PM, UM>::XW, 
 template <int PM, int UM, int MODE>
 __device__ __forceinline__ uint32_t eval_fn_all(const SlotRegs<Shape<PM, UM>::XW, Shape<PM, UM>::TTW>& r,
                                                 const NegThr& nt, const uint8_t* img, const uint8_t* cs,
-                                                const uint8_t* rs, const FnFmt& fm) {
+                                                const uint8_t* rs, const FnFmt& fm, unsigned long long st = 0ull) {
   const uint32_t w = *reinterpret_cast<const uint32_t*>(rs + (r.draw & 0xFFFFFFu));
   const auto f = load_fn<PM, UM, MODE>(img, r.base, choose_neg(w, nt), fm);
-  return eval_fn<PM, UM>(f, cs);
+  return eval_fn<PM, UM, (MODE & 8) != 0>(f, cs, st);
 }
 
 // Store a slot's result: a table slot writes its word of member bytes (from
@@ -465,7 +484,10 @@ struct TrajArgs {
 // MODE: bit 0, FN records of one or two units (batches of plans of both
 // kinds); bit 1, image reads through global-address-space pointers; bit 2,
 // alias sampling (Algorithms 1, 2 and 5's per-group draws) instead of the
-// keyed draws.
+// keyed draws; bit 3, the state held as one 64-bit wave-uniform word (bit b =
+// state byte b) instead of bytes in LDS: one-pass FN-only plans whose slot
+// bytes and zero word lie below 64, where s(t+1) is the pass's output ballot
+// (padded lanes output 0, so the zero word stays 0).
 template <int PM, int UM, int NREG, int MODE>
 __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   constexpr int XW = Shape<PM, UM>::XW, TTW = Shape<PM, UM>::TTW;
@@ -479,6 +501,8 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   // ... and mark a fill's perturbation-only steps before its steps (one scalar
   // bit per step), so that no step waits on its perturbation word to branch
   constexpr bool kPre = kBallotTargets;
+  constexpr bool kRegState = (MODE & 8) != 0;
+  static_assert(!kRegState || (NREG == 1 && UM == 0 && !ALIAS), "register state: one-pass FN-only keyed plans");
   using Regs = SlotRegs<XW, TTW>;
   const pbn_plan_header* H = reinterpret_cast<const pbn_plan_header*>(a.blob);
   const uint32_t lane = threadIdx.x & 63u;
@@ -505,7 +529,9 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   // unpack the packed state (bit b = state byte b), eight 4-bit groups per word
   const uint32_t W = H->state_words;
   uint32_t* gst = a.state + size_t(a.tl) * W;
-  for (uint32_t w = lane; w < W; w += 64u) {
+  unsigned long long rst = 0ull;   // register-held state (kRegState)
+  if constexpr (kRegState) rst = uniform64((W > 1u ? (static_cast<unsigned long long>(gst[1]) << 32) : 0ull) | gst[0]);
+  for (uint32_t w = lane; w < (kRegState ? 0u : W); w += 64u) {
     const uint32_t word = gst[w];
 #pragma unroll
     for (uint32_t i = 0; i < 8u; ++i) {
@@ -607,7 +633,15 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   // steps t >= count_from (state s(t+1)), changes count steps t >= count_from + 1
   // against the previous step's z (zlast: z before the oldest bit).
   uint32_t cur = 0;
-  uint32_t zlast = target_z(reinterpret_cast<const uint8_t*>(sbuf0)) ? 1u : 0u;
+  // register-held state: target t (lane t) from the state word itself
+  auto target_reg = [&](unsigned long long b) -> bool {
+    return !never && (masked_xor(uint32_t(b), care_lo[0], want_lo[0]) | masked_xor(uint32_t(b >> 32), care_hi[0], want_hi[0])) == 0u;
+  };
+  uint32_t zlast;
+  if constexpr (kRegState)
+    zlast = target_reg(rst) ? 1u : 0u;
+  else
+    zlast = target_z(reinterpret_cast<const uint8_t*>(sbuf0)) ? 1u : 0u;
   uint32_t zacc = 0, nacc = 0;
   uint32_t hits = 0, n01 = 0, n10 = 0;
   uint32_t t = a.step0;
@@ -745,14 +779,21 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
           if (C >= n - j0) break;
           const uint32_t i = j0 + C;
           const uint32_t pos = blob_u32<(MODE & 2) != 0>(o2p + i);
-          if (pos != PBN_NONE && lane == 0) csb[pos] ^= 1u;
+          if constexpr (kRegState) {
+            if (pos != PBN_NONE) rst ^= 1ull << uniform(pos);
+          } else if (pos != PBN_NONE && lane == 0) {
+            csb[pos] ^= 1u;
+          }
           j0 = i + 1u;
           if (j0 >= n) break;
           const uint4 x = philox(traj, t, j0, PBN_STREAM_PERT, k0, k1);
           u = (static_cast<unsigned long long>(uniform(x.y)) << 32) | uniform(x.x);
         }
         wave_sync();
-        z = target_z(csb);
+        if constexpr (kRegState)
+          z = target_reg(rst);
+        else
+          z = target_z(csb);
       } else {
         uint8_t* nsb = reinterpret_cast<uint8_t*>(cur ? sbuf0 : sbuf1);
         if constexpr (kCached) {
@@ -761,12 +802,18 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
 #pragma unroll
           for (int p = 0; p < NREG; ++p) {
             if constexpr (UM == 0 && !ALIAS)
-              out[p] = eval_fn_all<PM, UM, MODE>(cached[p], nthr[p], img, csb, rs, fm);
+              out[p] = eval_fn_all<PM, UM, MODE>(cached[p], nthr[p], img, csb, rs, fm, rst);
             else
               out[p] = eval_slot<PM, UM, MODE>(cached[p], &nthr[p], img, csb, rs, fm);
           }
+          if constexpr (kRegState) {
+            // s(t+1): the pass's outputs (lane s = slot s = state byte s); padded
+            // lanes, the zero word among them, output 0
+            rst = __ballot(out[0] != 0u);
+          } else {
 #pragma unroll
-          for (int p = 0; p < NREG; ++p) store_slot<UM>(nsb, cached[p].info, cached[p].spos, out[p]);
+            for (int p = 0; p < NREG; ++p) store_slot<UM>(nsb, cached[p].info, cached[p].spos, out[p]);
+          }
           if constexpr (kBallotTargets) {
             uint32_t mism = 0u;
 #pragma unroll
@@ -784,7 +831,7 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
           }
         }
         cur ^= 1u;
-        wave_sync();
+        if constexpr (!kRegState) wave_sync();
         if constexpr (!kBallotTargets) z = target_z(nsb);
       }
       zacc = zacc + zacc + (z ? 1u : 0u);
@@ -799,6 +846,10 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
     c[0] += hits;
     c[1] += n01;
     c[2] += n10;
+  }
+  if constexpr (kRegState) {
+    if (lane < W) gst[lane] = lane == 0 ? uint32_t(rst) : lane == 1 ? uint32_t(rst >> 32) : 0u;
+    return;
   }
   const uint32_t* fs = cur ? sbuf1 : sbuf0;
   for (uint32_t w = lane; w < W; w += 64u) {
@@ -816,7 +867,7 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
 // One network: one wavefront per trajectory, the plan image staged in LDS when
 // it fits (IMG_LDS), shared by the workgroup's waves.  ALIAS: the plan's alias
 // sampling draws.
-template <bool IMG_LDS, int PM, int UM, int NREG, bool ALIAS>
+template <bool IMG_LDS, int PM, int UM, int NREG, bool ALIAS, bool REGSTATE = false>
 __global__ void __launch_bounds__(1024) k_simulate(SimParams a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   const pbn_plan_header* H = reinterpret_cast<const pbn_plan_header*>(a.blob);
@@ -851,7 +902,7 @@ __global__ void __launch_bounds__(1024) k_simulate(SimParams a) {
   t.tg = &a.tg;
   t.record = a.record && tl < a.record_traj ? a.record + size_t(tl) * a.record_words : nullptr;
   t.record_words = a.record_words;
-  run_traj<PM, UM, NREG, ALIAS ? 4 : 0>(t);
+  run_traj<PM, UM, NREG, (ALIAS ? 4 : 0) | (REGSTATE ? 8 : 0)>(t);
 }
 
 // ---------------------------------------------------------------- batches
@@ -992,9 +1043,9 @@ uint32_t wave_lds_bytes(const pbn_plan* plan, bool single) {
   return (single ? 4u : 8u) * ((plan->state_dwords + 3u) & ~3u) + 16u * ring;
 }
 
-template <bool IMG_LDS, int PM, int UM, int NREG, bool ALIAS>
+template <bool IMG_LDS, int PM, int UM, int NREG, bool ALIAS, bool REGSTATE = false>
 pbn_status launch_sim(const SimParams& p, uint32_t blocks, uint32_t lds, hipStream_t stream) {
-  auto* fn = k_simulate<IMG_LDS, PM, UM, NREG, ALIAS>;
+  auto* fn = k_simulate<IMG_LDS, PM, UM, NREG, ALIAS, REGSTATE>;
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1008,24 +1059,29 @@ pbn_status launch_sim(const SimParams& p, uint32_t blocks, uint32_t lds, hipStre
 
 // Instantiation choice: the smallest gather widths that cover the plan.
 template <bool IMG_LDS, int PM, int UM, bool ALIAS>
-pbn_status dispatch_nreg(const SimParams& p, uint32_t npass, uint32_t blocks, uint32_t lds, hipStream_t s) {
+pbn_status dispatch_nreg(const SimParams& p, uint32_t npass, bool reg, uint32_t blocks, uint32_t lds, hipStream_t s) {
+  if constexpr (UM == 0 && !ALIAS) {
+    // one pass, every state byte below 64: the state lives in a register
+    if (reg) return launch_sim<IMG_LDS, PM, 0, 1, false, true>(p, blocks, lds, s);
+  }
   if (npass == 1) return launch_sim<IMG_LDS, PM, UM, 1, ALIAS>(p, blocks, lds, s);
   if (npass == 2) return launch_sim<IMG_LDS, PM, UM, 2, ALIAS>(p, blocks, lds, s);
   return launch_sim<IMG_LDS, PM, UM, 0, ALIAS>(p, blocks, lds, s);
 }
 
 template <bool IMG_LDS, int PM, bool ALIAS>
-pbn_status dispatch_um(const SimParams& p, uint32_t umax, uint32_t npass, uint32_t blocks, uint32_t lds, hipStream_t s) {
-  if (umax == 0) return dispatch_nreg<IMG_LDS, PM, 0, ALIAS>(p, npass, blocks, lds, s);
-  if (umax <= 8) return dispatch_nreg<IMG_LDS, PM, 8, ALIAS>(p, npass, blocks, lds, s);
-  return dispatch_nreg<IMG_LDS, PM, 16, ALIAS>(p, npass, blocks, lds, s);
+pbn_status dispatch_um(const SimParams& p, uint32_t umax, uint32_t npass, bool reg, uint32_t blocks, uint32_t lds,
+                       hipStream_t s) {
+  if (umax == 0) return dispatch_nreg<IMG_LDS, PM, 0, ALIAS>(p, npass, reg, blocks, lds, s);
+  if (umax <= 8) return dispatch_nreg<IMG_LDS, PM, 8, ALIAS>(p, npass, false, blocks, lds, s);
+  return dispatch_nreg<IMG_LDS, PM, 16, ALIAS>(p, npass, false, blocks, lds, s);
 }
 
 template <bool IMG_LDS, bool ALIAS>
-pbn_status dispatch_pm(const SimParams& p, uint32_t pmax, uint32_t umax, uint32_t npass, uint32_t blocks, uint32_t lds,
-                       hipStream_t s) {
-  if (pmax <= 5) return dispatch_um<IMG_LDS, 5, ALIAS>(p, umax, npass, blocks, lds, s);
-  return dispatch_um<IMG_LDS, 7, ALIAS>(p, umax, npass, blocks, lds, s);
+pbn_status dispatch_pm(const SimParams& p, uint32_t pmax, uint32_t umax, uint32_t npass, bool reg, uint32_t blocks,
+                       uint32_t lds, hipStream_t s) {
+  if (pmax <= 5) return dispatch_um<IMG_LDS, 5, ALIAS>(p, umax, npass, reg, blocks, lds, s);
+  return dispatch_um<IMG_LDS, 7, ALIAS>(p, umax, npass, reg, blocks, lds, s);
 }
 
 pbn_status simulate_common(bool plain, const pbn_plan* plan, const void* d_plan, uint64_t seed, uint32_t traj0,
@@ -1080,11 +1136,16 @@ pbn_status simulate_common(bool plain, const pbn_plan* plan, const void* d_plan,
   if (pmax > 7 || umax > 16) return fail(PBN_ELDS, "plan exceeds the kernel's gather widths");
   const uint32_t units = reinterpret_cast<const pbn_plan_header*>(plan->blob.data())->fn_units;
   if (units != (pmax > 5 ? 2u : 1u)) return fail(PBN_EINVAL, "plan FN record format does not match its parent count");
+  // one-pass FN-only keyed plans whose slot bytes and zero word lie below 64
+  // keep the state in a register (padded lanes' bytes, above the zero word,
+  // are never read and stay 0)
+  const uint32_t zero_pos = reinterpret_cast<const pbn_plan_header*>(plan->blob.data())->zero_pos;
+  const bool reg = npass == 1 && umax == 0 && !plan->sampling && zero_pos + 4u <= 64u;
   if (plan->sampling)
-    return img_lds ? dispatch_pm<true, true>(p, pmax, umax, npass, blocks, lds, s)
-                   : dispatch_pm<false, true>(p, pmax, umax, npass, blocks, lds, s);
-  return img_lds ? dispatch_pm<true, false>(p, pmax, umax, npass, blocks, lds, s)
-                 : dispatch_pm<false, false>(p, pmax, umax, npass, blocks, lds, s);
+    return img_lds ? dispatch_pm<true, true>(p, pmax, umax, npass, false, blocks, lds, s)
+                   : dispatch_pm<false, true>(p, pmax, umax, npass, false, blocks, lds, s);
+  return img_lds ? dispatch_pm<true, false>(p, pmax, umax, npass, reg, blocks, lds, s)
+                 : dispatch_pm<false, false>(p, pmax, umax, npass, reg, blocks, lds, s);
 }
 
 }  // namespace
