@@ -140,3 +140,33 @@ def test_maximum_node_count():
     net = ps.random_pbn(16000, 1e-5, 77, nfn=lambda r: 1 if r.random() < 0.9 else 2,
                         nparents=lambda r: int(r.integers(1, 4)))
     run_both(net, dict(reduce=1, group=1, max_parent_bits=6), [[(0, 1), (15999, 0)]], 13, 2, 6)
+
+
+@pytest.mark.parametrize("name", ["c1", "two_pass"])
+def test_single_step_launches_count_the_new_state(name):
+    # launches of one step: each adds the indicator of s(t+1), never of s(t)
+    # (C1 runs with the state held in a register, the 100-node network with
+    # state bytes in LDS)
+    if name == "c1":
+        net, targets = ps.tiny_c1(), [[(0, 1), (1, 1)]]
+    else:
+        net = ps.medium_c2(n=100, p=0.01, seed=23)
+        targets = [ps.non_leaf_targets(net, 2)]
+    plan = api.Plan(net, interest=[a for a, _ in targets[0]], reduce=0, group=0)
+    say(f"[gpu] single-step launches {name} info={plan.info}")
+    tg = plan.targets(targets)
+    seed, ntraj, steps = 11, 6, 40
+    st = api.state_init(plan, seed, ntraj)
+    cn = api.new_counts(1, ntraj)
+    nw = osim.Network(net)
+    traj = np.arange(ntraj, dtype=np.uint64)
+    s = osim.initial_state(net, seed, traj)
+    prev = np.zeros(ntraj, dtype=np.int64)
+    for t in range(steps):
+        api.simulate(plan, seed, st, cn, tg, t, 1, plain=True)
+        s, _ = osim.step(nw, seed, traj, t, s)
+        hits = cn[0, :, 0].cpu().numpy()
+        assert np.array_equal(hits - prev, osim.target_hit(s, targets[0]).astype(np.int64)), t
+        prev = hits
+    assert np.array_equal(api.unpack_bits(api.to_original(plan, st).cpu().numpy(), plan.n)[:, plan.node_pos() != NONE],
+                          s[:, plan.node_pos() != NONE])
