@@ -116,3 +116,57 @@ def test_batch_large_uneven_sampled():
         orig = api.unpack_bits(api.to_original(plan, b.states[k]).cpu().numpy(), plan.n)
         kept = plan.node_pos() != NONE
         assert np.array_equal(orig[sample][:, kept], ref["state"][:, kept])
+
+
+def test_full_size_c4_batch_configuration():
+    """The batched workload at full size in the benchmark's configuration: 512
+    networks (n ~ U[20, 1500]) x 256 trajectories, leaf-reduction plans, 4
+    waves per workgroup, 10^4 burn-in + 10^5 counted steps in one persistent
+    pass captured in a HIP graph.  Sampled networks match single-network
+    launches of the same plans over the same steps (states and every counter);
+    a 20-step batch of all 512 networks matches the oracle on sampled
+    trajectories."""
+    nets = ps.batch_c4()
+    ntraj, burn, total = 256, 10**4, 11 * 10**4
+
+    def items_for():
+        out = []
+        for k, net in enumerate(nets):
+            tg = [ps.non_leaf_targets(net, 3)]
+            plan = api.Plan(net, interest=[a for a, _ in tg[0]], reduce=1, group=0)
+            out.append((plan, 1004000 + k, ntraj, tg))
+        return out
+
+    items = items_for()
+    sizes = np.array([net["n"] for net in nets])
+    picks = sorted({int(np.argmax(sizes)), int(np.argmin(sizes)), 7, 200, 511})
+    say("[gpu] C4 full size: 512 networks x 256 trajectories x 110000 steps, one graph pass")
+    b = api.Batch(items, count_from=burn, waves_per_block=4)
+    b.init_states()
+    b.set_window(0, total)
+    g = b.graph(1)
+    g.launch()
+    torch.cuda.synchronize()
+    for k in picks:
+        plan, seed, nt, tg = items[k]
+        say(f"[gpu] C4 network {k} (n={plan.n}) against a single-network launch")
+        state = api.state_init(plan, seed, nt)
+        counts = api.new_counts(1, nt)
+        api.simulate(plan, seed, state, counts, plan.targets(tg), 0, total, count_from=burn, plain=True)
+        assert np.array_equal(b.states[k].cpu().numpy(), state.cpu().numpy()), k
+        assert np.array_equal(b.counts[k].cpu().numpy(), counts.cpu().numpy()), k
+    del g, b
+    say("[gpu] C4 full size: 20 steps against the oracle on sampled trajectories")
+    b = api.Batch(items, count_from=0, waves_per_block=4)
+    b.init_states()
+    b.set_window(0, 20)
+    b.launch()
+    torch.cuda.synchronize()
+    sample = np.array([0, 101, 255])
+    for k in picks[:3]:
+        plan, seed, nt, tg = items[k]
+        ref = osim.run(nets[k], seed, sample, 20, targets=tg)
+        orig = api.unpack_bits(api.to_original(plan, b.states[k]).cpu().numpy(), plan.n)
+        kept = plan.node_pos() != NONE
+        assert np.array_equal(orig[sample][:, kept], ref["state"][:, kept]), k
+        assert np.array_equal(b.counts[k].cpu().numpy()[:, sample, 0], ref["hits"]), k
