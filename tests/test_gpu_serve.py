@@ -116,3 +116,31 @@ def test_realtime_poisson_stream_reports_latency():
     assert m["done"] + m["max_steps"] == 40
     assert m["p50_latency_s"] is not None and m["p99_latency_s"] >= m["p50_latency_s"]
     assert m["node_updates_per_s"] > 0
+
+
+def test_full_size_c5_results_identical_alone_and_in_mix():
+    """The served workload at full size in the benchmark's configuration: 2000
+    queries arriving as a Poisson stream at 200/s over the 64 resident
+    networks (n ~ U[50, 3000]), leaf-reduction plans, 256 trajectories per
+    query; sampled queries rerun alone give the same step count, counters and
+    estimate as in the mix."""
+    nets = ps.served_c5()
+    seeds = [1005000 + k for k in range(len(nets))]
+    kw = dict(plan_opts=dict(reduce=1, group=0), traj_per_query=256, chunk=1000, burn_in=1000, min_counted=1000,
+              max_steps=200000, waves_per_block=4)
+    srv = serve.Server(nets, seeds, **kw)
+    say("[gpu] C5 full size: 2000 queries, Poisson 200/s, realtime")
+    m = srv.run(serve.poisson_queries(nets, 2000, rate=200.0, seed=2005), realtime=True)
+    assert m["done"] + m["max_steps"] == 2000, m
+    assert m["p99_latency_s"] >= m["p50_latency_s"] > 0
+    mixed = {q.qid: q for q in srv.done}
+    qs = serve.poisson_queries(nets, 2000, rate=200.0, seed=2005)
+    for qid in (0, 1, 777, 1500, 1999):
+        q = qs[qid]
+        say(f"[gpu] C5 query {qid} alone (network {q.net}, {len(q.targets)} targets, r={q.precision})")
+        alone = serve.Server(nets, seeds, **kw)
+        alone.run([q], realtime=False)
+        a, b = alone.done[0], mixed[qid]
+        assert a.status == b.status and a.steps == b.steps, qid
+        assert np.array_equal(a.result["counts"], b.result["counts"]), qid
+        assert a.result["p_hat"] == b.result["p_hat"], qid
