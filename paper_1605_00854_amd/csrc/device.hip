@@ -278,22 +278,29 @@ struct FnFmt {
   uint32_t jshift;    // log2 of the bytes from predictor j's record to j + 1's
   uint32_t hoff;      // bytes from a record's first unit to its second
   uint32_t zp2;       // zero position in both halves of a word
+  uint32_t var;       // two-unit plan, packed: a slot reading <= 5 parents keeps one unit
 };
 
-// FN record of predictor j of the slot whose predictor 0 is at image offset
-// `base`: one 16-byte unit (5 positions, 32-entry table) or two units (7
-// positions; 128-entry table).  A gather-width-7 kernel reads two-unit plans;
-// with MIXED (batches of plans of both kinds) it also reads one-unit plans
-// (positions 5-7 = the zero position, table words 1-3 never selected).
+// FN record of predictor j of the slot (slot-record word `info`) whose
+// predictor 0 is at image offset `base`: one 16-byte unit (5 positions,
+// 32-entry table) or two units (7 positions; 128-entry table).  A
+// gather-width-7 kernel reads two-unit plans, where a packed image keeps one
+// unit for the slots that read at most 5 parents (fm.var: the slot's parent
+// count decides, lane by lane); with MIXED (batches of plans of both kinds) it
+// also reads one-unit plans.  A one-unit record read by this kernel has
+// positions 5-7 = the zero position and table words 1-3 never selected.
 // MODE: bit 0 MIXED, bit 1 image reads through global-address-space pointers.
 template <int PM, int UM, int MODE>
 __device__ __forceinline__ FnRec<Shape<PM, UM>::PW, Shape<PM, UM>::TTW> load_fn(const uint8_t* img, uint32_t base,
-                                                                               uint32_t j, const FnFmt& fm) {
+                                                                               uint32_t j, const FnFmt& fm,
+                                                                               uint32_t info) {
   constexpr int TTW = Shape<PM, UM>::TTW;
   constexpr bool MIXED = (MODE & 1) != 0, G = (MODE & 2) != 0;
   FnRec<Shape<PM, UM>::PW, TTW> r;
+  const bool two = fm.var ? PBN_SLOT_NU(info) > 5u : (!MIXED || fm.units == 2u);
+  const uint32_t jshift = fm.var ? (two ? 5u : 4u) : fm.jshift;
   // records and units are 16-byte aligned: one 16-byte read per unit
-  const uint8_t* rp = static_cast<const uint8_t*>(__builtin_assume_aligned(img + base + (j << fm.jshift), 16));
+  const uint8_t* rp = static_cast<const uint8_t*>(__builtin_assume_aligned(img + base + (j << jshift), 16));
   const uint4 a = img_u4<G>(rp);
   r.pw[0] = a.x;
   r.pw[1] = a.y;
@@ -301,7 +308,7 @@ __device__ __forceinline__ FnRec<Shape<PM, UM>::PW, Shape<PM, UM>::TTW> load_fn(
   if constexpr (TTW == 1) {
     r.tt[0] = a.w;
   } else {
-    if (!MIXED || fm.units == 2u) {
+    if (two) {
       const uint4 b = img_u4<G>(rp + fm.hoff);
       r.pw[3] = a.w;
       r.tt[0] = b.x;
@@ -375,7 +382,7 @@ __device__ __forceinline__ void load_slot(SlotRegs<Shape<PM, UM>::XW, Shape<PM, 
       r.thr2 = ch.w;
     } else {
       // one-predictor node or padded lane (a dummy record)
-      const auto f = load_fn<PM, UM, MODE>(img, rec.y, 0u, fm);
+      const auto f = load_fn<PM, UM, MODE>(img, rec.y, 0u, fm, rec.x);
 #pragma unroll
       for (int k = 0; k < PW; ++k) r.pw[k] = f.pw[k];
 #pragma unroll
@@ -430,7 +437,7 @@ __device__ __forceinline__ uint32_t eval_slot(const SlotRegs<Shape<PM, UM>::XW, 
       j = alias_pick<(MODE & 2) != 0>(img + r.choice + 16u, w, r.thr0);   // alias record: {offset, L, ...}
     else
       j = nt ? choose_neg(w, *nt) : choose(w, r.thr0, r.thr1, r.thr2, r.draw >> 24);
-    f = load_fn<PM, UM, MODE>(img, r.base, j, fm);
+    f = load_fn<PM, UM, MODE>(img, r.base, j, fm, r.info);
   }
   return eval_fn<PM, UM>(f, cs);
 }
@@ -444,7 +451,7 @@ __device__ __forceinline__ uint32_t eval_fn_all(const SlotRegs<Shape<PM, UM>::XW
                                                 const NegThr& nt, const uint8_t* img, const uint8_t* cs,
                                                 const uint8_t* rs, const FnFmt& fm, unsigned long long st = 0ull) {
   const uint32_t w = *reinterpret_cast<const uint32_t*>(rs + (r.draw & 0xFFFFFFu));
-  const auto f = load_fn<PM, UM, MODE>(img, r.base, choose_neg(w, nt), fm);
+  const auto f = load_fn<PM, UM, MODE>(img, r.base, choose_neg(w, nt), fm, r.info);
   return eval_fn<PM, UM, (MODE & 8) != 0>(f, cs, st);
 }
 
@@ -513,6 +520,7 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   fm.jshift = H->fn_jshift;
   fm.hoff = H->fn_hoff;
   fm.zp2 = zero_pos | (zero_pos << 16);
+  fm.var = H->fn_var;
   const uint32_t zp2 = fm.zp2;
   const uint32_t sdp = (sd + 3u) & ~3u;   // state buffer, padded to 16 bytes
   const uint32_t* blk = reinterpret_cast<const uint32_t*>(a.blob + H->blk_off);

@@ -475,7 +475,10 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   // among its FN slots) rows, predictor j of slot s sits 128 units j bytes
   // after predictor 0, a record's second unit 128 bytes after its first.  An
   // image read from global memory packs records densely instead (fewer cache
-  // lines): predictor j at 16 units j, second unit at +16.
+  // lines): predictor j at 16 units j, second unit at +16; there a plan of
+  // two-unit records gives two units only to the slots whose predictors read
+  // more than 5 parents (fn_var), the others keep one (a slot record's parent
+  // count tells the kernel which).
   const size_t slot_bytes = size_t(npass) * PBN_WAVE * 16;
   size_t nchoice = 0, tab_bytes = 0, nfnrec = 0;
   uint32_t fn_phi = 0;
@@ -507,7 +510,12 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   const size_t chain_bytes = 16 + 8 * size_t(n + 1) + 16 + 4 * size_t(n);
   const size_t swz_bytes = fn_base + 128 * size_t(rows) + tab_bytes + alias_bytes + chain_bytes;
   const bool swz = swz_bytes <= o.lds_budget_bytes;
-  const size_t tab_base = fn_base + (swz ? 128 * size_t(rows) : 16 * size_t(units) * (nfnrec + 1));
+  const bool fn_var = !swz && units == 2;
+  auto slot_units = [&](size_t s) -> uint32_t { return fn_var ? (max_phi(slots[s].members[0]) > 5 ? 2u : 1u) : units; };
+  size_t packed_fn = 16 * size_t(units);   // the dummy record, then every FN slot's records
+  for (size_t s = 0; s < ns; ++s)
+    if (!slots[s].table) packed_fn += 16 * size_t(slot_units(s)) * g.nfn(slots[s].members[0]);
+  const size_t tab_base = fn_base + (swz ? 128 * size_t(rows) : packed_fn);
   const size_t alias_base = tab_base + tab_bytes;
   const size_t q_img = align16(alias_base + alias_bytes);
   const size_t o2p_img = align16(q_img + 8 * size_t(n + 1));
@@ -518,10 +526,10 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   for (size_t s = 0, cur = fn_base + 16 * units; s < ns; ++s)
     if (!slots[s].table) {
       rec0[s] = cur;
-      cur += 16 * size_t(units) * g.nfn(slots[s].members[0]);
+      cur += 16 * size_t(slot_units(s)) * g.nfn(slots[s].members[0]);
     }
   auto fn_rec = [&](uint32_t s, uint32_t j) {
-    return swz ? fn_base + 128 * size_t(row0[s / 8] + j * units) + 16 * (s % 8) : rec0[s] + size_t(jstride) * j;
+    return swz ? fn_base + 128 * size_t(row0[s / 8] + j * units) + 16 * (s % 8) : rec0[s] + 16 * size_t(slot_units(s)) * j;
   };
   auto dummy_of = [&](size_t s) { return swz ? fn_base + 16 * (s % 8) : fn_base; };
 
@@ -532,7 +540,7 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   // the zero position, truth table 0
   const size_t dummy_fn = fn_base;
   for (uint32_t q = 0; q < (swz ? 8u : 1u); ++q)
-    for (uint32_t b = 0; b < (units == 1 ? 6u : 8u); ++b) put16(dummy_fn + 16 * q + 2 * b, uint16_t(zero_pos));
+    for (uint32_t b = 0; b < (units == 1 || fn_var ? 6u : 8u); ++b) put16(dummy_fn + 16 * q + 2 * b, uint16_t(zero_pos));
   // default choice record first: ring offset 0, l = 1, no thresholds (selects predictor 0)
   const size_t default_choice = choice_base;
   put32(default_choice, 1u << 24);
@@ -570,10 +578,11 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
       for (uint32_t f = g.fn_off[v]; f < g.fn_off[v + 1]; ++f) {
         const size_t r = fn_rec(s, f - g.fn_off[v]);
         const uint32_t k = g.nparents(f);
-        const uint32_t npos = units == 1 ? 6u : 8u;   // position slots (unused: the zero position)
+        const uint32_t su = slot_units(s);
+        const uint32_t npos = su == 1 ? 6u : 8u;   // position slots (unused: the zero position)
         for (uint32_t b = 0; b < npos; ++b)
           put16(r + 2 * b, uint16_t(b < k ? plan.node_pos[g.parents[g.par_off[f] + b]] : zero_pos));
-        const size_t tt = units == 1 ? r + 12 : r + hoff;   // truth table: bit x = f(x)
+        const size_t tt = su == 1 ? r + 12 : r + hoff;   // truth table: bit x = f(x)
         const uint32_t ebits = 1u << k;
         for (uint32_t x = 0; x < ebits && x < 128; ++x)
           if (g.eval(f, x)) img[tt + (x >> 3)] |= uint8_t(1u << (x & 7));
@@ -710,6 +719,7 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   h.has_table = max_union > 0 || std::any_of(slots.begin(), slots.end(), [](const Slot& s) { return s.table; });
   h.dummy_fn = uint32_t(dummy_fn);
   h.fn_units = units;
+  h.fn_var = fn_var ? 1u : 0u;
   h.fn_jshift = uint32_t(__builtin_ctz(jstride));
   h.fn_hoff = hoff;
   h.q_img = uint32_t(q_img);

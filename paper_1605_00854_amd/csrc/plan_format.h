@@ -85,7 +85,8 @@ struct pbn_plan_header {
   uint32_t alias_kp;       // nodes of the last group (k')
   uint32_t leaf_thr;       // Algorithm 1: a leaf is perturbed when the drawn word exceeds this
   uint32_t n_sel;          // slots that draw a (combined) predictor function
-  uint32_t pad2;
+  uint32_t fn_var;         // 1: packed two-unit plan whose slots with <= 5 parents keep one-unit
+                           // records (predictor stride 16 units of the slot)
 };
 // Alias sampling draws, per step t: Philox(traj, t, c, PBN_STREAM_ALIAS) for
 // c = 0 .. n_jobs-1 give words w[0 .. 4 n_jobs) (word e of call c is w[4c+e]):

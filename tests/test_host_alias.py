@@ -17,7 +17,7 @@ from paper_1605_00854_amd import api
 FIELDS = ("magic version blob_bytes plan_id n n_kept n_slots n_passes state_dwords state_words n_jobs "
           "fill_steps image_bytes image_off q_off o2p_off p2o_off blk_off pass_off zero_pos max_pmax "
           "image_in_lds has_table dummy_fn n_table fn_base fn_units fn_jshift fn_hoff sampling q_img o2p_img "
-          "pert_off kpos_off alias_k alias_g alias_kp leaf_thr n_sel pad2").split()
+          "pert_off kpos_off alias_k alias_g alias_kp leaf_thr n_sel fn_var").split()
 
 CAPS = dict(max_group_nodes=4, max_parent_bits=12, max_table_entries=4096)
 

@@ -247,9 +247,10 @@ def test_fn_records_decode_to_the_network(which, budget):
     """Plan image format: every FN slot's records hold the byte positions of
     its parents and its truth table -- for an image that goes to LDS in 16-byte
     units of 128-byte rows (lane s at unit s % 8, predictors 128 x units bytes
-    apart), else packed densely; slot records carry the slot's state byte; the
-    zero word follows the last FN byte; padded lanes write bytes of their own
-    above it."""
+    apart), else packed densely, where a plan of two-unit records keeps one
+    unit for the slots whose predictors read at most 5 parents; slot records
+    carry the slot's state byte; the zero word follows the last FN byte; padded
+    lanes write bytes of their own above it."""
     if which == "dense5":
         net = ps.medium_c2(n=90, p=1e-3, seed=11)
     else:
@@ -290,13 +291,17 @@ def test_fn_records_decode_to_the_network(which, budget):
             continue
         (v,) = np.nonzero(slot == s)[0]
         assert w == pos[v]
-        for j, f in enumerate(range(net["fn_off"][v], net["fn_off"][v + 1])):
-            r = y + jstride * j
+        fns = range(net["fn_off"][v], net["fn_off"][v + 1])
+        phi = max(int(net["par_off"][f + 1] - net["par_off"][f]) for f in fns)
+        assert (info >> 6) & 31 == phi                      # the slot's parent count
+        su = units if swz or phi > 5 else 1                  # this slot's units per record
+        for j, f in enumerate(fns):
+            r = y + (jstride if swz else 16 * su) * j
             pars = net["parents"][net["par_off"][f]:net["par_off"][f + 1]]
-            npos = 6 if units == 1 else 8
+            npos = 6 if su == 1 else 8
             got = [u16(r + 2 * b) for b in range(npos)]
             assert got == [int(pos[q]) for q in pars] + [zp] * (npos - len(pars))
-            tt = r + 12 if units == 1 else r + h["fn_hoff"]
+            tt = r + 12 if su == 1 else r + h["fn_hoff"]
             bits = [(int(img[tt + (x >> 3)]) >> (x & 7)) & 1 for x in range(1 << len(pars))]
             want = [int(net["tt"][net["tt_off"][f] + x // 64]) >> (x % 64) & 1 for x in range(1 << len(pars))]
             assert bits == want
