@@ -1081,6 +1081,9 @@ template <bool IMG_LDS, int PM, bool ALIAS>
 pbn_status dispatch_um(const SimParams& p, uint32_t umax, uint32_t npass, bool reg, uint32_t blocks, uint32_t lds,
                        hipStream_t s) {
   if (umax == 0) return dispatch_nreg<IMG_LDS, PM, 0, ALIAS>(p, npass, reg, blocks, lds, s);
+  if constexpr (!ALIAS) {
+    if (umax <= 6) return dispatch_nreg<IMG_LDS, PM, 6, ALIAS>(p, npass, false, blocks, lds, s);
+  }
   if (umax <= 8) return dispatch_nreg<IMG_LDS, PM, 8, ALIAS>(p, npass, false, blocks, lds, s);
   return dispatch_nreg<IMG_LDS, PM, 16, ALIAS>(p, npass, false, blocks, lds, s);
 }
