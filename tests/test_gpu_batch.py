@@ -170,3 +170,37 @@ def test_full_size_c4_batch_configuration():
         kept = plan.node_pos() != NONE
         assert np.array_equal(orig[sample][:, kept], ref["state"][:, kept]), k
         assert np.array_equal(b.counts[k].cpu().numpy()[:, sample, 0], ref["hits"]), k
+
+
+def test_batch_mixes_wide_and_narrow_predictor_records():
+    """Networks whose predictors read up to 7 parents (packed images where only
+    the slots reading 6-7 parents have two-unit records) batched with networks
+    of one-unit records: every network matches the oracle."""
+    items, nets = [], []
+    for k in range(8):
+        wide = k % 2 == 0
+        n = 60 + 37 * k
+        if wide:
+            net = ps.random_pbn(n, 1e-2, 900 + k, nfn=lambda r: int(r.integers(1, 4)),
+                                nparents=lambda r: int(r.integers(1, 8)), leaf_frac=0.1)
+        else:
+            net = ps.medium_c2(n=n, p=1e-2, seed=950 + k)
+        tgs = [ps.non_leaf_targets(net, 2)]
+        plan = api.Plan(net, interest=[a for a, _ in tgs[0]], reduce=1, group=k % 4 == 0,
+                        lds_budget_bytes=0 if wide else 65536)
+        if wide:
+            assert plan.info["max_fn_parents"] > 5
+        items.append((plan, 2000 + k, 5 + k, tgs))
+        nets.append(net)
+    say("[gpu] batch of wide and narrow predictor records")
+    b = api.Batch(items, count_from=10, waves_per_block=4)
+    b.init_states()
+    b.set_window(0, 120)
+    b.launch()
+    torch.cuda.synchronize()
+    for k, ((plan, seed, ntraj, tgs), net) in enumerate(zip(items, nets)):
+        ref = osim.run(net, seed, np.arange(ntraj), 120, targets=tgs, count_from=10)
+        orig = api.unpack_bits(api.to_original(plan, b.states[k]).cpu().numpy(), plan.n)
+        kept = plan.node_pos() != NONE
+        assert np.array_equal(orig[:, kept], ref["state"][:, kept]), f"network {k}"
+        assert np.array_equal(b.counts[k].cpu().numpy()[:, :, 0], ref["hits"]), f"network {k}"
