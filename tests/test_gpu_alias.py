@@ -90,6 +90,7 @@ REDUCED = dict(reduce=1, group=0)
 GROUPED = dict(reduce=1, group=1)
 MULTI_GROUPS = dict(reduce=1, group=1, weight_mode=0, theta=10 ** 6)
 GLOBAL_IMAGE = dict(reduce=1, group=1, weight_mode=0, theta=10 ** 6, lds_budget_bytes=0)
+PACKED = dict(reduce=1, group=0, lds_budget_bytes=0)   # packed image: per-slot FN record units
 
 CASES = [
     # name, opts, seed, traj0, ntraj, chunks, count_from, plain, wpb
@@ -102,6 +103,7 @@ CASES = [
     ("multi400", GROUPED, 5, 0, 6, (60,), 0, False, 1),
     ("sparse120", MULTI_GROUPS, 7, 0, 12, (150,), 0, False, 0),
     ("wide7", REDUCED, 9, 0, 10, (200,), 0, True, 0),
+    ("wide7", PACKED, 9, 2, 10, (120, 80), 20, True, 0),
 ]
 
 
@@ -138,7 +140,7 @@ def test_alias_trajectories_bit_exact(case):
         assert any(len(g) > 1 for g in ref_plan["groups"]), "case must draw combined functions"
     if name == "multi400":
         assert plan.info["n_jobs"] > 64 and plan.info["n_passes"] > 2
-    if opts is GLOBAL_IMAGE:
+    if opts is GLOBAL_IMAGE or opts is PACKED:
         assert plan.info["image_in_lds"] == 0
     if name == "wide7":
         assert plan.info["max_fn_parents"] > 5
