@@ -20,9 +20,9 @@ from . import api, autotune
 
 # Equation 7's form refit on MI355X: 72 synthetic networks (n 100-1500, leaf
 # fraction 0-0.9, density 1.0-8.8), speedup of the autotuned plan over the plain
-# kernel at 2048 trajectories (bench.py --planner-fit 72): R^2 0.64,
-# 10-fold cross-validated 0.59, 24 held-out networks 0.80.
-COEFFS = (0.646663, 1.061703, 0.650440, 0.159849, -0.014616)
+# kernel at 2048 trajectories (bench.py --planner-fit 72): R^2 0.63,
+# 10-fold cross-validated 0.57, 24 held-out networks 0.72.
+COEFFS = (0.489354, 1.255258, 0.866232, 0.237944, -0.019611)
 
 
 def density(net):
