@@ -449,8 +449,9 @@ __device__ __forceinline__ uint32_t eval_slot(const SlotRegs<Shape<PM, UM>::XW, 
 template <int PM, int UM, int MODE>
 __device__ __forceinline__ uint32_t eval_fn_all(const SlotRegs<Shape<PM, UM>::XW, Shape<PM, UM>::TTW>& r,
                                                 const NegThr& nt, const uint8_t* img, const uint8_t* cs,
-                                                const uint8_t* rs, const FnFmt& fm, unsigned long long st = 0ull) {
-  const uint32_t w = *reinterpret_cast<const uint32_t*>(rs + (r.draw & 0xFFFFFFu));
+                                                const uint8_t* rs, const FnFmt& fm, unsigned long long st = 0ull,
+                                                const uint32_t* pre = nullptr) {
+  const uint32_t w = pre ? *pre : *reinterpret_cast<const uint32_t*>(rs + (r.draw & 0xFFFFFFu));
   const auto f = load_fn<PM, UM, MODE>(img, r.base, choose_neg(w, nt), fm, r.info);
   return eval_fn<PM, UM, (MODE & 8) != 0>(f, cs, st);
 }
@@ -742,8 +743,17 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
       }
       pmask = uint32_t(__ballot(pert));   // scount <= 32
     }
+    // register-held state (a latency-bound chain): each step's drawn word is
+    // read one step ahead (the fill's last step re-reads its own)
+    uint32_t wnext = 0u;
+    if constexpr (kRegState)
+      wnext = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(ring) + (cached[0].draw & 0xFFFFFFu));
     for (uint32_t s = 0; s < scount; ++s, ++t) {
       const uint8_t* rs = reinterpret_cast<const uint8_t*>(ring + s * njobs);
+      const uint32_t wcur = wnext;
+      if constexpr (kRegState)
+        wnext = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(ring + min(s + 1u, scount - 1u) * njobs) +
+                                                   (cached[0].draw & 0xFFFFFFu));
       uint32_t ulo = 0u, uhi = 0u;
       if constexpr (!kPre) {
         const uint2 pr = *reinterpret_cast<const uint2*>(rs);
@@ -810,7 +820,8 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
 #pragma unroll
           for (int p = 0; p < NREG; ++p) {
             if constexpr (UM == 0 && !ALIAS)
-              out[p] = eval_fn_all<PM, UM, MODE>(cached[p], nthr[p], img, csb, rs, fm, rst);
+              out[p] = eval_fn_all<PM, UM, MODE>(cached[p], nthr[p], img, csb, rs, fm, rst,
+                                                 kRegState ? &wcur : nullptr);
             else
               out[p] = eval_slot<PM, UM, MODE>(cached[p], &nthr[p], img, csb, rs, fm);
           }
