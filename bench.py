@@ -253,7 +253,8 @@ def bench_serve(args):
         else:
             opts, wpb = dict(reduce=0, group=0), 4
         srv = serve.Server(nets, [1005000 + k for k in range(len(nets))], plan_opts=opts, traj_per_query=256,
-                           chunk=1000, burn_in=1000, min_counted=1000, max_steps=200000, waves_per_block=wpb)
+                           chunk=args.query_chunk, burn_in=1000, min_counted=1000, max_steps=200000,
+                           waves_per_block=wpb)
         qs = serve.poisson_queries(nets, nq, rate=200.0, seed=2005)
         m = srv.run(qs, realtime=True)
         m["plan"] = opts
@@ -262,7 +263,8 @@ def bench_serve(args):
            "value": results["product"]["p99_latency_s"], "unit": "s (p99 latency)", "n_gpus": 1,
            "higher_is_better": False, "dtype": "u32", "data": "synthetic",
            "config": {"workload": f"C5: {nq} queries, Poisson 200/s, 64 resident PBNs n~U[50,3000], "
-                                  "1-5 target nodes, r in {1e-2, 5e-3}, conf 0.95, 256 trajectories per query"},
+                                  "1-5 target nodes, r in {1e-2, 5e-3}, conf 0.95, 256 trajectories per query, "
+                                  f"{args.query_chunk} steps per tick"},
            "compare": results}
     print(json.dumps(out))
 
@@ -393,6 +395,8 @@ def main():
     ap.add_argument("--wpb", type=int, default=0)
     ap.add_argument("--quick-tune", action="store_true")
     ap.add_argument("--queries", type=int, default=2000, help="C5: number of served queries")
+    ap.add_argument("--query-chunk", type=int, default=500,
+                    help="C5: steps every admitted query advances per server tick")
     ap.add_argument("--plan", default="auto", choices=["auto", "plain", "reduction", "cone", "grouped", "alias"],
                     help="product plan: autotuned, or a fixed preparation (profiling runs)")
     ap.add_argument("--copy-probe", type=int, default=0,

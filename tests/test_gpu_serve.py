@@ -122,11 +122,11 @@ def test_full_size_c5_results_identical_alone_and_in_mix():
     """The served workload at full size in the benchmark's configuration: 2000
     queries arriving as a Poisson stream at 200/s over the 64 resident
     networks (n ~ U[50, 3000]), leaf-reduction plans, 256 trajectories per
-    query; sampled queries rerun alone give the same step count, counters and
-    estimate as in the mix."""
+    query, 500 steps per tick; sampled queries rerun alone give the same step
+    count, counters and estimate as in the mix."""
     nets = ps.served_c5()
     seeds = [1005000 + k for k in range(len(nets))]
-    kw = dict(plan_opts=dict(reduce=1, group=0), traj_per_query=256, chunk=1000, burn_in=1000, min_counted=1000,
+    kw = dict(plan_opts=dict(reduce=1, group=0), traj_per_query=256, chunk=500, burn_in=1000, min_counted=1000,
               max_steps=200000, waves_per_block=4)
     srv = serve.Server(nets, seeds, **kw)
     say("[gpu] C5 full size: 2000 queries, Poisson 200/s, realtime")
