@@ -370,8 +370,18 @@ __device__ __forceinline__ void load_slot(SlotRegs<Shape<PM, UM>::XW, Shape<PM, 
   for (int k = 0; k < TTW; ++k) r.tt[k] = 0;
   if (UM > 0 && (rec.x & PBN_SLOT_TABLE)) {
     r.spos = 4u * slot;
+    if (rec.x & PBN_SLOT_INLINE) {
+      // union positions carried by the record (no multi-predictor members:
+      // choice and radix are not read)
+      r.pw[0] = rec.z;
+      if constexpr (UW > 1) r.pw[1] = rec.w;
+      if constexpr (UW > 2) r.pw[2] = PBN_SLOT_P4(rec.x) | (fm.zp2 & 0xFFFF0000u);
 #pragma unroll
-    for (int k = 0; k < UW; ++k) r.pw[k] = img_u32<G>(img + rec.y + 4u * k);
+      for (int k = 3; k < UW; ++k) r.pw[k] = fm.zp2;
+    } else {
+#pragma unroll
+      for (int k = 0; k < UW; ++k) r.pw[k] = img_u32<G>(img + rec.y + 4u * k);
+    }
   } else {
     r.spos = rec.w;   // FN slot or padded lane: its state byte
     if (PBN_SLOT_NMULTI(rec.x)) {

@@ -569,6 +569,7 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
     if (nmulti >= 2) ++multi_groups;
     uint32_t info = PBN_SLOT_VALID | uint32_t(sl.members.size() - 1) | (nmulti << 3);
     uint32_t y = 0, w = 0;
+    uint32_t z = nmulti ? uint32_t(first_choice) : sl.table ? 0u : uint32_t(default_choice);
     if (!sl.table) {
       const uint32_t v = sl.members[0];
       const uint32_t pm = max_phi(v);
@@ -628,6 +629,13 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
           img[tbl + (size_t(c) << nu) + x] = uint8_t(out);
         }
       }
+      if (nmulti == 0 && nu <= 5) {
+        // the union positions in the record itself (no union-list read)
+        auto upos = [&](uint32_t b) { return b < nu ? plan.node_pos[sl.uni[b]] : zero_pos; };
+        info |= PBN_SLOT_INLINE | (upos(4) << 11);
+        z = upos(0) | (upos(1) << 16);
+        w = upos(2) | (upos(3) << 16);
+      }
       tab_cur += align16(32 + (size_t(ncomb) << nu));
       pi.flags |= PBN_PASS_TABLE;
       pi.umax = std::max(pi.umax, nu);
@@ -637,7 +645,7 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
     if (nmulti) pi.flags |= PBN_PASS_MULTI;
     put32(rec + 0, info);
     put32(rec + 4, y);
-    put32(rec + 8, nmulti ? uint32_t(first_choice) : sl.table ? 0u : uint32_t(default_choice));
+    put32(rec + 8, z);
     put32(rec + 12, w);
   }
   if (alias_mode) {

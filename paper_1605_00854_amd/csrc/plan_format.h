@@ -36,6 +36,12 @@
 #define PBN_SLOT_NMEM(i) (((i) & 7u) + 1u)
 #define PBN_SLOT_NMULTI(i) (((i) >> 3) & 7u)
 #define PBN_SLOT_NU(i) (((i) >> 6) & 31u)
+// TABLE slot without multi-predictor members and with at most 5 union bits:
+// its union positions sit in the slot record itself (z = p0 | p1 << 16,
+// w = p2 | p3 << 16, info bits 11-26 = p4; the zero position where the union
+// has fewer bits), so a lane pass reads no union list
+#define PBN_SLOT_INLINE 0x20000000u
+#define PBN_SLOT_P4(i) (((i) >> 11) & 0xFFFFu)
 
 // pass-info flags
 #define PBN_PASS_FN 1u
@@ -139,7 +145,8 @@ struct pbn_pass_info {
 // Slot record (uint4):
 //   x = info word (PBN_SLOT_*)
 //   y = FN: image offset of the fn record of predictor 0 (predictor j at +32 j)
-//       TABLE: image offset of the union-parent list (table follows at +32)
+//       TABLE: image offset of the union-parent list (table follows at +32;
+//       with PBN_SLOT_INLINE the list is also in z, w and the info word)
 //   z = FN: image offset of the slot's choice record (one-predictor nodes and
 //       padded lanes: the default record {ring offset 0, l = 1, no thresholds},
 //       the first choice record of the image);
