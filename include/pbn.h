@@ -30,7 +30,8 @@
  *   Q[h] = floor(v_h 2^64), v_h = fl(v_{h-1} fl(1 - p)); predictor selection of a
  *   node with l >= 2 predictors uses word (r & 3) of the SEL call with index
  *   r >> 2 (r = its rank among multi-predictor nodes of the full network)
- *   against thresholds CUM[m] = min(2^32 - 1, floor(S_m 2^32 + 1/2)).
+ *   against thresholds CUM[m] = min(2^32, floor(S_m 2^32 + 1/2)) (2^32 is never
+ *   reached: a predictor of probability 0 after a partial sum of 1 never fires).
  *   Reduction and grouping never change a kept node's trajectory.
  */
 #ifndef PBN_H
@@ -106,10 +107,11 @@ pbn_status pbn_net_destroy(pbn_net* net);
 
 /* Integer tables of the random-number contract, for inspection and tests.
  *   q      [n+1] Q[h] for h = 0..n (Q[0] = 0: the certain event, never compared)
- *   cum    [3 n] thresholds of node i at cum[3 i + m], m < l(i) - 1; the unused
- *                entries are 0xFFFFFFFF
+ *   cum    [3 n] thresholds of node i at cum[3 i + m], m < l(i) - 1, each at
+ *                most 2^32 (2^32: never reached, the predictors after it have
+ *                probability 0); the unused entries are 2^32
  *   rank   [n]   rank among nodes with >= 2 predictors, or -1                  */
-pbn_status pbn_net_tables(const pbn_net* net, uint64_t* q, uint32_t* cum, int32_t* rank);
+pbn_status pbn_net_tables(const pbn_net* net, uint64_t* q, uint64_t* cum, int32_t* rank);
 
 /* --------------------------------------------------------------------- plan
  * Preparation (Algorithm 5): leaf-node reduction (Definition 1), node grouping

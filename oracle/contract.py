@@ -18,9 +18,12 @@ reproducible reading so that a trajectory is a pure function of
   one is drawn from a 64-bit uniform u as C = #{h in 1..n : Q[h] > u}
   (geometric skip sampling of the iid Bernoulli(p) vector gamma of Eq. 1).
 * Selection probabilities c_0..c_{l-1} of a node become integer thresholds
-  CUM[m] = min(2^32 - 1, floor(S_m * 2^32 + 1/2)), m = 0..l-2, where S_m is
+  CUM[m] = min(2^32, floor(S_m * 2^32 + 1/2)), m = 0..l-2, where S_m is
   the left-to-right double sum c_0 + ... + c_m; a 32-bit uniform u selects
-  predictor j = #{m : u >= CUM[m]}.
+  predictor j = #{m : u >= CUM[m]}.  A threshold of 2^32 is never reached, so
+  predictors whose selection probability follows a partial sum of 1 are never
+  chosen (Section 2.1: a predictor is chosen with its selection probability,
+  and zero means never).
 * Node i with l(i) >= 2 takes its uniform from word (r & 3) of the SEL call
   with index r >> 2, where r is the rank of i among all nodes with two or more
   predictors, in node-id order, in the full network.  Ranks do not depend on
@@ -50,7 +53,7 @@ def selection_thresholds(probs):
     out = []
     for m in range(len(probs) - 1):
         s = s + float(probs[m])         # left-to-right double sum
-        out.append(min((1 << 32) - 1, int(np.floor(np.ldexp(s, 32) + 0.5))))
+        out.append(min(1 << 32, int(np.floor(np.ldexp(s, 32) + 0.5))))
     return out
 
 

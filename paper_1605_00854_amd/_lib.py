@@ -87,7 +87,7 @@ SIGNATURES = {
     "pbn_last_error": (C.c_char_p, []),
     "pbn_net_create": (C.c_int32, [C.POINTER(pbn_desc), C.POINTER(_P)]),
     "pbn_net_destroy": (C.c_int32, [_P]),
-    "pbn_net_tables": (C.c_int32, [_P, _pU64, _pU32, _pI32]),
+    "pbn_net_tables": (C.c_int32, [_P, _pU64, _pU64, _pI32]),
     "pbn_plan_opts_default": (None, [C.POINTER(pbn_plan_opts)]),
     "pbn_plan_build": (C.c_int32, [_P, _pU32, _U32, C.POINTER(pbn_plan_opts), C.POINTER(_P)]),
     "pbn_plan_destroy": (C.c_int32, [_P]),

@@ -44,9 +44,9 @@ class Net:
     def tables(self):
         """(Q[0..n], cum[n,3], rank[n]) of the random-number contract."""
         q = np.zeros(self.n + 1, dtype=np.uint64)
-        cum = np.zeros(3 * self.n, dtype=np.uint32)
+        cum = np.zeros(3 * self.n, dtype=np.uint64)
         rank = np.zeros(self.n, dtype=np.int32)
-        check(lib().pbn_net_tables(self.handle, _ptr(q, C.c_uint64), _ptr(cum, C.c_uint32),
+        check(lib().pbn_net_tables(self.handle, _ptr(q, C.c_uint64), _ptr(cum, C.c_uint64),
                                    _ptr(rank, C.c_int32)))
         return q, cum.reshape(self.n, 3), rank
 

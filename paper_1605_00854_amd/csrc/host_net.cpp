@@ -39,17 +39,18 @@ static void quantise_perturbation(pbn_net& g) {
   }
 }
 
-// CUM[m] = min(2^32 - 1, floor(S_m * 2^32 + 1/2)), S_m the left-to-right double
-// partial sum of the selection probabilities.
+// CUM[m] = min(2^32, floor(S_m * 2^32 + 1/2)), S_m the left-to-right double
+// partial sum of the selection probabilities.  A 32-bit uniform never reaches
+// 2^32, so a predictor after a partial sum of 1 (probability 0) is never chosen.
 static void quantise_selection(pbn_net& g) {
-  g.cum.assign(3 * size_t(g.n), 0xFFFFFFFFu);
+  g.cum.assign(3 * size_t(g.n), kCumNever);
   for (uint32_t i = 0; i < g.n; ++i) {
     double s = 0.0;
     const uint32_t l = g.nfn(i);
     for (uint32_t m = 0; m + 1 < l; ++m) {
       s = s + g.sel[g.fn_off[i] + m];
       const double v = std::floor(std::ldexp(s, 32) + 0.5);
-      g.cum[3 * size_t(i) + m] = v >= 4294967295.0 ? 0xFFFFFFFFu : static_cast<uint32_t>(v);
+      g.cum[3 * size_t(i) + m] = v >= 4294967296.0 ? kCumNever : static_cast<uint64_t>(v);
     }
   }
   g.rank.assign(g.n, -1);
@@ -128,7 +129,7 @@ extern "C" pbn_status pbn_net_destroy(pbn_net* g) {
   return PBN_OK;
 }
 
-extern "C" pbn_status pbn_net_tables(const pbn_net* g, uint64_t* q, uint32_t* cum, int32_t* rank) {
+extern "C" pbn_status pbn_net_tables(const pbn_net* g, uint64_t* q, uint64_t* cum, int32_t* rank) {
   pbn::clear_error();
   if (!g) return fail(PBN_EINVAL, "null network");
   if (q)

@@ -562,8 +562,16 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
     for (uint32_t v : sl.members) {
       if (g.nfn(v) < 2) continue;
       ++nmulti;
-      put32(choice_cur + 0, draw_off(v) | (g.nfn(v) << 24));
-      for (int m = 0; m < 3; ++m) put32(choice_cur + 4 + 4 * m, g.cum[3 * size_t(v) + m]);
+      // the record's l counts the predictors a 32-bit word can reach: those
+      // after a threshold of 2^32 (probability 0) are left out, so the
+      // kernel's clamp to l - 1 and its never-reached thresholds exclude them
+      uint32_t reach = 1;
+      while (reach < g.nfn(v) && g.cum[3 * size_t(v) + reach - 1] < kCumNever) ++reach;
+      put32(choice_cur + 0, draw_off(v) | (reach << 24));
+      for (int m = 0; m < 3; ++m) {
+        const uint64_t c = g.cum[3 * size_t(v) + m];
+        put32(choice_cur + 4 + 4 * m, c < kCumNever ? uint32_t(c) : 0xFFFFFFFFu);
+      }
       choice_cur += 16;
     }
     if (nmulti >= 2) ++multi_groups;

@@ -7,6 +7,8 @@
 #include "../../include/pbn.h"
 #include "plan_format.h"
 
+constexpr uint64_t kCumNever = 1ull << 32;   // a selection threshold no 32-bit uniform reaches
+
 struct pbn_net {
   uint32_t n = 0;
   double p = 0.0;
@@ -15,7 +17,7 @@ struct pbn_net {
   std::vector<uint64_t> tt;
   // random-number contract tables (quantised once at creation)
   std::vector<uint64_t> Q;      // Q[0..n], Q[0] unused (0)
-  std::vector<uint32_t> cum;    // 3 per node, unused 0xFFFFFFFF
+  std::vector<uint64_t> cum;    // 3 per node, at most 2^32 (never reached); unused 2^32
   std::vector<int32_t> rank;    // rank among multi-predictor nodes, -1 otherwise
   uint32_t n_multi = 0;
 

@@ -222,7 +222,7 @@ int main() {
       continue;
     }
     std::vector<uint64_t> q(n + 1);
-    std::vector<uint32_t> cum(3 * size_t(n));
+    std::vector<uint64_t> cum(3 * size_t(n));
     std::vector<int32_t> rank(n);
     CHECK(pbn_net_tables(net, q.data(), cum.data(), rank.data()) == PBN_OK);
     for (uint32_t reduce = 0; reduce <= 2; ++reduce)

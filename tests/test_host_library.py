@@ -47,8 +47,36 @@ def test_quantisation_matches_oracle(name):
     for i in range(net["n"]):
         c = contract.selection_thresholds(net["sel_prob"][net["fn_off"][i]:net["fn_off"][i + 1]])
         assert [int(x) for x in cum[i][: len(c)]] == c
-        assert all(int(x) == 0xFFFFFFFF for x in cum[i][len(c):])
+        assert all(int(x) == 1 << 32 for x in cum[i][len(c):])
     assert np.array_equal(rank, contract.multi_ranks(net))
+
+
+def test_zero_probability_predictors_are_unreachable_in_the_plan():
+    # node 0: predictors of probability 0.5, 0.5, 0 (the last one is never
+    # chosen); node 1: 1, 0; node 2: 0.5, 0, 0.5 (the middle one is never chosen)
+    net = ps.assemble(3, 0.01, [[(0.5, [1], [0, 1]), (0.5, [2], [1, 0]), (0.0, [1, 2], [1, 1, 1, 1])],
+                                [(1.0, [0], [0, 1]), (0.0, [2], [1, 0])],
+                                [(0.5, [0], [1, 0]), (0.0, [1], [0, 1]), (0.5, [0, 1], [0, 1, 1, 0])]])
+    q, cum, rank = api.Net(net).tables()
+    assert [int(x) for x in cum[0][:2]] == [1 << 31, 1 << 32]
+    assert [int(x) for x in cum[1][:1]] == [1 << 32]
+    assert [int(x) for x in cum[2][:2]] == [1 << 31, 1 << 31]
+    for i in range(3):
+        c = contract.selection_thresholds(net["sel_prob"][net["fn_off"][i]:net["fn_off"][i + 1]])
+        assert [int(x) for x in cum[i][: len(c)]] == c
+    # the plan's choice records (16 bytes: draw offset | l << 24, CUM[0..2] as
+    # 32-bit words) count the predictors a 32-bit word reaches: 2, 1, 3
+    plan = api.Plan(net, interest=[0, 1, 2], reduce=0, group=0)
+    blob = plan.blob()
+    hdr = np.frombuffer(blob[:64].tobytes(), dtype="<u4")
+    n_slots, image_off = int(hdr[6]), int(hdr[13])
+    reach = []
+    for slot in range(n_slots):
+        info, _, choice, _ = np.frombuffer(blob[image_off + 16 * slot:image_off + 16 * slot + 16].tobytes(), dtype="<u4")
+        if (int(info) >> 3) & 7:
+            rec = np.frombuffer(blob[image_off + int(choice):image_off + int(choice) + 16].tobytes(), dtype="<u4")
+            reach.append(int(rec[0]) >> 24)
+    assert sorted(reach) == [1, 2, 3]
 
 
 @pytest.mark.parametrize("name", sorted(NETS))

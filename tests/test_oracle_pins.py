@@ -93,9 +93,27 @@ def test_selection_thresholds_round_partial_sums():
             acc += Fraction(float(probs[m]))
             # within half a unit plus the double-sum rounding of the partial sum
             assert abs(Fraction(cum[m]) - acc * (1 << 32)) <= Fraction(1, 2) + (m + 1) * Fraction(1 << 32, 1 << 52)
-    assert contract.selection_thresholds([1.0 - 1e-12, 1e-12]) == [(1 << 32) - 1]
+    # 1e-12 is 0.0043 of one 2^-32 unit: to the nearest unit, zero words select it
+    assert contract.selection_thresholds([1.0 - 1e-12, 1e-12]) == [1 << 32]
     assert contract.selection_thresholds([0.5, 0.5]) == [1 << 31]
     assert contract.selection_thresholds([0.0, 1.0]) == [0]
+
+
+def test_zero_selection_probability_never_fires():
+    # Section 2.1: predictor j is chosen with probability c_j, so c_j = 0 means
+    # never.  A predictor is reached by the 32-bit words u >= CUM[j-1] below
+    # CUM[j]; after a partial sum of exactly 1 the threshold must exceed every
+    # 32-bit word (the largest is 2^32 - 1), wherever the zeros sit.
+    top = (1 << 32) - 1
+    assert contract.selection_thresholds([0.5, 0.5, 0.0]) == [1 << 31, 1 << 32]
+    assert contract.selection_thresholds([0.25, 0.75, 0.0, 0.0]) == [1 << 30, 1 << 32, 1 << 32]
+    assert contract.selection_thresholds([1.0, 0.0]) == [1 << 32]
+    for probs in ([0.5, 0.5, 0.0], [1.0, 0.0, 0.0, 0.0], [0.3, 0.7, 0.0], [0.125, 0.375, 0.5, 0.0]):
+        cum = contract.selection_thresholds(probs)
+        assert cum[-1] > top                       # no word selects the last predictor
+    # a zero in the middle: equal thresholds leave no word between them
+    cum = contract.selection_thresholds([0.5, 0.0, 0.5])
+    assert cum == [1 << 31, 1 << 31]
 
 
 # ---------------------------------------------------- Perturbation chain ---

@@ -171,6 +171,50 @@ def test_partition_multi_meets_theta_or_stops_at_singletons():
             assert len(groups) >= min(mhat, k)
 
 
+def test_partition_multi_stops_when_the_sum_equals_theta():
+    # Section 3.3's problem bounds the sum of group weights by theta (<=).
+    # Four nodes of weight 2, theta = 8: Eq. 2 gives m = 2 (2 * 16^(1/2) = 8);
+    # Algorithm 3 with m = 2 puts nodes 0, 2 in group 0 and 1, 3 in group 1
+    # (ties go to the lower group), weights 4 + 4 = 8 <= 8, so Algorithm 4
+    # stops there.  The literal strict test (8 < 8 fails at every m) would
+    # end at four singletons.
+    items = [(0, 2), (1, 2), (2, 2), (3, 2)]
+    assert so.partition_multi(items, 8) == [[0, 2], [1, 3]]
+    # one less than the sum: infeasible at every m, one group per item
+    assert so.partition_multi(items, 7) == [[0], [1], [2], [3]]
+
+
+def test_partition_multi_returns_the_first_feasible_m():
+    # weights 3, 3, 2, 2, 2 (nodes 0..4), theta = 17.  Eq. 2: W = 72;
+    # m = 1: 72 > 17; m = 2: 72 * 2^2 = 288 <= 17^2 = 289, so Algorithm 4 starts
+    # at m = 2.  Algorithm 3, m = 2: 0 -> g0 (3), 1 -> g1 (3), 2 -> g0 (tie, 6),
+    # 3 -> g1 (6), 4 -> g0 (tie, 12): 12 + 6 = 18 > 17, so m grows to 3:
+    # 0 -> g0 (3), 1 -> g1 (3), 2 -> g2 (2), 3 -> g2 (4), 4 -> g0 (tie of 3 and
+    # 3, 6): 6 + 3 + 4 = 13 <= 17.  m = 4 would also fit (3 + 3 + 4 + 2 = 12),
+    # so returning anything but the first feasible m shows here.
+    items = [(0, 3), (1, 3), (2, 2), (3, 2), (4, 2)]
+    assert so.eq2_lower_bound([w for _, w in items], 17) == 2
+    assert so.partition_multi(items, 17) == [[0, 4], [1], [2, 3]]
+
+
+def test_group_single_ties_go_to_the_smaller_union_then_the_lower_index():
+    # max_bits = 3.  Node 10 opens g0 = {1, 2}; node 11 ({3, 4}) would make g0's
+    # union 4 bits, so it opens g1.  Node 12 ({5}) shares no parent with either
+    # and both unions would be 3 bits: the lower index, g0, takes it.
+    parents = {10: [1, 2], 11: [3, 4], 12: [5]}
+    assert so.group_single([10, 11, 12], parents, max_nodes=4, max_bits=3) == [[10, 12], [11]]
+    # max_bits = 4.  g0 = {1, 2, 3}; node 11 ({4, 5}) would give 5 bits: g1.
+    # Node 12 ({6}) shares nothing with either; g0 would grow to 4 bits, g1 to
+    # 3: the smaller union wins over the lower index.
+    parents = {10: [1, 2, 3], 11: [4, 5], 12: [6]}
+    assert so.group_single([10, 11, 12], parents, max_nodes=4, max_bits=4) == [[10], [11, 12]]
+    # max_bits = 5.  g0 = {1, 2, 3, 4}; node 11 ({5, 6}) would give 6 bits: g1.
+    # Node 12 ({1, 7}) shares parent 1 with g0 (union 5 bits) and nothing with
+    # g1 (union 4 bits): shared parents come before the union size.
+    parents = {10: [1, 2, 3, 4], 11: [5, 6], 12: [1, 7]}
+    assert so.group_single([10, 11, 12], parents, max_nodes=4, max_bits=5) == [[10, 12], [11]]
+
+
 def test_group_single_respects_caps_and_prefers_shared_parents():
     parents = {0: [5, 6], 1: [7, 8], 2: [5, 6, 9], 3: [7], 4: [1, 2, 3, 4]}
     groups = so.group_single([0, 1, 2, 3, 4], parents, max_nodes=2, max_bits=3)
