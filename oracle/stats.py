@@ -10,7 +10,8 @@ Here, from their published definitions:
 * two_state: for the hit indicator z_t, alpha = P(0 -> 1), beta = P(1 -> 0)
   estimated from transition counts; the required sample size
   N = alpha beta (2 - alpha - beta) / (alpha + beta)^3 * (Phi^-1((1+conf)/2) / r)^2
-  and the burn-in m* = log(eps (alpha + beta) / max(alpha, beta)) / log|1 - alpha - beta|.
+  and the burn-in m* = log(eps (alpha + beta) / max(alpha, beta)) / log|1 - alpha - beta|
+  (m* = 1 where that logarithm is -inf or 0: alpha + beta = 1, or alpha = beta = 1).
 * rl92_diagnose: the full single-chain procedure of Raftery and Lewis (1992)
   on a recorded indicator sequence: the thinning interval k is the smallest k
   for which the k-thinned sequence is better described by a first-order than
@@ -54,7 +55,10 @@ def two_state(n01, n10, n0, n1, r, conf=0.95, eps=1e-3):
     z = float(_st.norm.ppf(0.5 + conf / 2.0))
     nreq = alpha * beta * (2.0 - alpha - beta) / (alpha + beta) ** 3 * (z / r) ** 2
     lam = abs(1.0 - alpha - beta)
-    if lam == 0.0:
+    if lam == 0.0 or lam == 1.0:
+        # log(lam) is -inf or 0: lam = 0 is an independent sequence, stationary
+        # after one step; lam = 1 with alpha + beta > 0 means alpha = beta = 1,
+        # a deterministic alternation whose time average needs no warm-up
         burn = 1.0
     else:
         burn = math.log(eps * (alpha + beta) / max(alpha, beta)) / math.log(lam)

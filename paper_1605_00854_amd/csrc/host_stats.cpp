@@ -34,7 +34,9 @@ double normal_quantile(double p) {
   return x;
 }
 
-// Regularised incomplete beta I_x(a, b) by its continued fraction (modified Lentz).
+// Regularised incomplete beta I_x(a, b): the standard continued fraction of the
+// incomplete beta function, evaluated with the modified Lentz method (Lentz 1976;
+// Thompson and Barnett 1986), as numerical-methods texts lay it out.
 double betacf(double a, double b, double x) {
   const double tiny = 1e-300, eps = 1e-16;
   double c = 1.0, d = 1.0 - (a + b) * x / (a + 1.0);
@@ -142,7 +144,9 @@ extern "C" pbn_status pbn_estimate(const uint64_t* counts, uint32_t units, uint6
     const double z = normal_quantile(0.5 + conf / 2);
     out->n_required = alpha * beta * (2 - alpha - beta) / std::pow(alpha + beta, 3) * (z / precision) * (z / precision);
     const double lam = std::fabs(1 - alpha - beta);
-    out->burn_in = lam == 0 ? 1.0 : std::log(1e-3 * (alpha + beta) / std::fmax(alpha, beta)) / std::log(lam);
+    // lam = 0 (independent) or 1 (alpha = beta = 1, a deterministic alternation):
+    // the logarithm is -inf or 0; one step of burn-in
+    out->burn_in = lam == 0 || lam == 1 ? 1.0 : std::log(1e-3 * (alpha + beta) / std::fmax(alpha, beta)) / std::log(lam);
   }
   return PBN_OK;
 }
@@ -230,7 +234,7 @@ extern "C" pbn_status pbn_rl_diagnose(const uint32_t* bits, uint64_t nbits, doub
     const double z = normal_quantile(0.5 + conf / 2);
     const double nstar = alpha * beta * (2 - alpha - beta) / std::pow(alpha + beta, 3) * (z / precision) * (z / precision);
     const double lam = std::fabs(1 - alpha - beta);
-    const double mstar = lam == 0 ? 1.0 : std::log(eps * (alpha + beta) / std::fmax(alpha, beta)) / std::log(lam);
+    const double mstar = lam == 0 || lam == 1 ? 1.0 : std::log(eps * (alpha + beta) / std::fmax(alpha, beta)) / std::log(lam);
     out->n_required = nstar * k;
     out->burn_in = mstar * k;
     const uint64_t first = uint64_t(std::ceil(out->burn_in));

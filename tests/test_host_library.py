@@ -245,6 +245,15 @@ def test_estimate_matches_oracle_statistics(seed):
     assert abs(got["burn_in"] - burn) < 1e-9 * abs(burn)
 
 
+def test_estimate_of_an_alternating_indicator_has_finite_sizes():
+    # every step changes the indicator: alpha = beta = 1, |1 - alpha - beta| = 1,
+    # where the burn-in formula's logarithm is 0
+    from oracle import stats as ost
+    a, b, nreq, burn = ost.two_state(500, 500, 500, 500, 1e-3)
+    got = api.estimate(np.array([[500, 500, 500]]), 1000, conf=0.95, precision=1e-3)
+    assert (got["alpha"], got["beta"], got["n_required"], got["burn_in"]) == (a, b, nreq, burn) == (1.0, 1.0, 0.0, 1.0)
+
+
 def test_two_state_sample_size_reduces_to_binomial():
     """For an iid indicator, alpha = pi and beta = 1 - pi, and the two-state
     sample size is the binomial one: pi (1 - pi) (z / r)^2."""
@@ -344,7 +353,7 @@ def _pack_bits(z):
     return words
 
 
-@pytest.mark.parametrize("kind", ["first", "second", "iid", "constant", "short"])
+@pytest.mark.parametrize("kind", ["first", "second", "iid", "constant", "alternating", "short"])
 def test_rl_diagnosis_matches_oracle(kind):
     from oracle import stats as ost
     rng = np.random.default_rng(21)
@@ -363,6 +372,8 @@ def test_rl_diagnosis_matches_oracle(kind):
         z = (rng.random(33333) < 0.2).astype(int)
     elif kind == "constant":
         z = np.ones(5000, dtype=int)
+    elif kind == "alternating":
+        z = np.arange(4001) & 1
     else:
         z = np.array([0, 1, 1, 0, 1])
     got = api.rl_diagnose(_pack_bits(z), z.size, 1e-3, conf=0.95, eps=1e-3, kmax=50)

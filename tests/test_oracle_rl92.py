@@ -75,6 +75,19 @@ def test_diagnosis_thins_a_second_order_chain():
     assert os_.rl92_diagnose(os_.thinned(markov2(200000, 13), d["k"]), 1e-3)["k"] == 1
 
 
+def test_alternating_sequence_needs_no_thinning_and_averages_one_half():
+    # a deterministic period-2 sequence: a second-order chain predicts nothing
+    # a first-order one does not (G^2 = 0), alpha = beta = 1, |1 - alpha - beta|
+    # = 1 (the burn-in formula's logarithm is 0), no sampling error (N* = 0),
+    # and the time average of an even-length window is exactly 1/2
+    z = np.arange(10001) & 1
+    d = os_.rl92_diagnose(z, 1e-3)
+    assert d["k"] == 1 and d["g2"] == 0.0
+    assert (d["alpha"], d["beta"]) == (1.0, 1.0)
+    assert d["n_required"] == 0.0 and d["burn_in"] == 1.0
+    assert d["p_hat"] == 0.5
+
+
 def test_diagnosis_sizes_scale_with_k_and_constant_sequences_are_infinite():
     z = markov1(0.05, 0.2, 100000, 14)
     d = os_.rl92_diagnose(z, 1e-3)
