@@ -38,12 +38,10 @@ constexpr uint32_t kW0 = 0x9E3779B9u, kW1 = 0xBB67AE85u;
 constexpr uint32_t kM0 = 0xD2511F53u, kM1 = 0xCD9E8D57u;
 
 // Three-input XOR in one VALU instruction: gfx950's three-input bitwise op
-// with truth table 0x96 (a ^ b ^ c).  Pure ALU; the key operand is
-// wave-uniform and lives in an SGPR.
+// with truth table 0x96 (a ^ b ^ c), through the compiler's builtin (plain
+// a ^ b ^ k compiles to two XORs).  The key operand is wave-uniform.
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t k) {
-  uint32_t r;
-  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
-  return r;
+  return __builtin_amdgcn_bitop3_b32(a, b, k, 0x96);
 }
 
 // Philox4x32-10 (Salmon et al., SC'11): counter (c0..c3), key (k0, k1).  Each
@@ -148,20 +146,16 @@ __device__ __forceinline__ uint32_t masked_xor(uint32_t b, uint32_t care, uint32
   return (b ^ want) & care;
 }
 
-// (a << 1) | b in one VALU instruction (keeps gather chains from being
-// re-associated into shift-and-or trees that take more instructions).
-__device__ __forceinline__ uint32_t shl1_or(uint32_t a, uint32_t b) {
-  uint32_t r;
-  asm("v_lshl_or_b32 %0, %1, 1, %2" : "=v"(r) : "v"(a), "v"(b));
-  return r;
-}
+// (a << sh) | b: one shift-or instruction.  A gather passes sh = 1 from a
+// launch argument: with a constant shift the compiler re-associates the chain
+// of shift-ors into a tree of separate shifts and three-input ors (more
+// instructions per parent bit); with a run-time amount it keeps the chain.
+__device__ __forceinline__ uint32_t shl_or(uint32_t a, uint32_t b, uint32_t sh) { return (a << sh) | b; }
 
 // High word of w + c for a 64-bit c = 2^64 - t: 0 when w >= t, all ones when
-// w < t (t <= 2^32).  One full-rate multiply-add (w * 1 + c).
+// w < t (t <= 2^32).  One 64-bit add (gfx950's shift-add on 64-bit operands).
 __device__ __forceinline__ uint32_t borrow_hi(uint32_t w, unsigned long long c) {
-  unsigned long long d, carry;
-  asm("v_mad_u64_u32 %0, %1, %2, 1, %3" : "=v"(d), "=s"(carry) : "v"(w), "v"(c));
-  return uint32_t(d >> 32);
+  return uint32_t((static_cast<unsigned long long>(w) + c) >> 32);
 }
 
 struct SimParams {
@@ -174,7 +168,7 @@ struct SimParams {
   uint32_t wave_bytes;   // LDS bytes per wave: state buffer(s) + ring
   uint32_t record_traj;  // trajectories 0 .. record_traj-1 record target 0's indicator bits
   uint32_t record_words; // words per recording trajectory
-  uint32_t pad;
+  uint32_t gshift;       // 1: the gather step's shift, passed at run time (see shl_or)
   uint32_t* record;      // [record_traj][record_words] or null
   pbn_targets tg;
 };
@@ -208,7 +202,7 @@ struct SlotRegs {
 };
 
 template <int K>
-__device__ __forceinline__ uint32_t gather(const uint8_t* cs, const uint32_t* pw) {
+__device__ __forceinline__ uint32_t gather(const uint8_t* cs, const uint32_t* pw, uint32_t sh) {
   // all K byte reads are independent: issued back to back, one wait; state
   // bytes are 0 or 1, so the index is a chain of shift-or steps
   uint32_t b[K];
@@ -216,20 +210,20 @@ __device__ __forceinline__ uint32_t gather(const uint8_t* cs, const uint32_t* pw
   for (int k = 0; k < K; ++k) b[k] = cs[(k & 1) ? (pw[k >> 1] >> 16) : (pw[k >> 1] & 0xFFFFu)];
   uint32_t idx = b[K - 1];
 #pragma unroll
-  for (int k = K - 2; k >= 0; --k) idx = shl1_or(idx, b[k]);
+  for (int k = K - 2; k >= 0; --k) idx = shl_or(idx, b[k], sh);
   return idx;
 }
 
 // The same gather from a state held as one 64-bit word (bit b = state byte b):
 // the shift takes the position's low 6 bits.
 template <int K>
-__device__ __forceinline__ uint32_t gather_bits(unsigned long long st, const uint32_t* pw) {
+__device__ __forceinline__ uint32_t gather_bits(unsigned long long st, const uint32_t* pw, uint32_t sh) {
   uint32_t b[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) b[k] = uint32_t(st >> (((k & 1) ? (pw[k >> 1] >> 16) : pw[k >> 1]) & 63u)) & 1u;
   uint32_t idx = b[K - 1];
 #pragma unroll
-  for (int k = K - 2; k >= 0; --k) idx = shl1_or(idx, b[k]);
+  for (int k = K - 2; k >= 0; --k) idx = shl_or(idx, b[k], sh);
   return idx;
 }
 
@@ -279,6 +273,7 @@ struct FnFmt {
   uint32_t hoff;      // bytes from a record's first unit to its second
   uint32_t zp2;       // zero position in both halves of a word
   uint32_t var;       // two-unit plan, packed: a slot reading <= 5 parents keeps one unit
+  uint32_t sh;        // 1, the shift of a gather step (a launch argument; see shl_or)
 };
 
 // FN record of predictor j of the slot (slot-record word `info`) whose
@@ -328,13 +323,13 @@ __device__ __forceinline__ FnRec<Shape<PM, UM>::PW, Shape<PM, UM>::TTW> load_fn(
 // LDS) or, with REG, in the 64-bit state `st`.
 template <int PM, int UM, bool REG = false>
 __device__ __forceinline__ uint32_t eval_fn(const FnRec<Shape<PM, UM>::PW, Shape<PM, UM>::TTW>& r, const uint8_t* cs,
-                                            unsigned long long st = 0ull) {
+                                            uint32_t sh, unsigned long long st = 0ull) {
   constexpr int TTW = Shape<PM, UM>::TTW;
   uint32_t idx;
   if constexpr (REG)
-    idx = gather_bits<PM>(st, r.pw);
+    idx = gather_bits<PM>(st, r.pw, sh);
   else
-    idx = gather<PM>(cs, r.pw);
+    idx = gather<PM>(cs, r.pw, sh);
   uint32_t ttw = r.tt[0];
   if constexpr (TTW > 1) {
     // word idx / 32 of the 128-bit table, selected among scalars (an indexed
@@ -406,7 +401,7 @@ __device__ __forceinline__ void load_slot(SlotRegs<Shape<PM, UM>::XW, Shape<PM, 
 // bit k (Section 3.3).
 template <int PM, int UM, int MODE>
 __device__ __forceinline__ uint32_t eval_table(const SlotRegs<Shape<PM, UM>::XW, Shape<PM, UM>::TTW>& r,
-                                               const uint8_t* img, const uint8_t* cs, const uint8_t* rs) {
+                                               const uint8_t* img, const uint8_t* cs, const uint8_t* rs, uint32_t sh) {
   constexpr bool G = (MODE & 2) != 0, ALIAS = (MODE & 4) != 0;
   uint32_t c = 0;
   const uint32_t nm = PBN_SLOT_NMULTI(r.info);
@@ -421,7 +416,7 @@ __device__ __forceinline__ uint32_t eval_table(const SlotRegs<Shape<PM, UM>::XW,
     const uint32_t w = *reinterpret_cast<const uint32_t*>(rs + (ch.x & 0xFFFFFFu));
     c += choose(w, ch.y, ch.z, ch.w, ch.x >> 24) * ((r.radix >> (8u * m)) & 0xFFu);
   }
-  const uint32_t x = gather<(UM > 0 ? UM : 1)>(cs, r.pw);
+  const uint32_t x = gather<(UM > 0 ? UM : 1)>(cs, r.pw, sh);
   const uint32_t v = img_u8<G>(img + r.base + 32u + (c << PBN_SLOT_NU(r.info)) + x);
   return v;   // member k's output in bit k
 }
@@ -434,7 +429,7 @@ __device__ __forceinline__ uint32_t eval_slot(const SlotRegs<Shape<PM, UM>::XW, 
                                               const NegThr* nt, const uint8_t* img, const uint8_t* cs,
                                               const uint8_t* rs, const FnFmt& fm) {
   constexpr int PW = Shape<PM, UM>::PW, TTW = Shape<PM, UM>::TTW;
-  if (UM > 0 && (r.info & PBN_SLOT_TABLE)) return eval_table<PM, UM, MODE>(r, img, cs, rs);
+  if (UM > 0 && (r.info & PBN_SLOT_TABLE)) return eval_table<PM, UM, MODE>(r, img, cs, rs, fm.sh);
   FnRec<PW, TTW> f;
 #pragma unroll
   for (int k = 0; k < PW; ++k) f.pw[k] = r.pw[k];
@@ -449,7 +444,7 @@ __device__ __forceinline__ uint32_t eval_slot(const SlotRegs<Shape<PM, UM>::XW, 
       j = nt ? choose_neg(w, *nt) : choose(w, r.thr0, r.thr1, r.thr2, r.draw >> 24);
     f = load_fn<PM, UM, MODE>(img, r.base, j, fm, r.info);
   }
-  return eval_fn<PM, UM>(f, cs);
+  return eval_fn<PM, UM>(f, cs, fm.sh);
 }
 
 // FN-only plans with slot data held in registers: every lane reads the record
@@ -463,7 +458,7 @@ __device__ __forceinline__ uint32_t eval_fn_all(const SlotRegs<Shape<PM, UM>::XW
                                                 const uint32_t* pre = nullptr) {
   const uint32_t w = pre ? *pre : *reinterpret_cast<const uint32_t*>(rs + (r.draw & 0xFFFFFFu));
   const auto f = load_fn<PM, UM, MODE>(img, r.base, choose_neg(w, nt), fm, r.info);
-  return eval_fn<PM, UM, (MODE & 8) != 0>(f, cs, st);
+  return eval_fn<PM, UM, (MODE & 8) != 0>(f, cs, fm.sh, st);
 }
 
 // Store a slot's result: a table slot writes its word of member bytes (from
@@ -491,6 +486,7 @@ struct TrajArgs {
   const pbn_targets* tg;
   uint32_t* record;                 // this trajectory's indicator bits (target 0), or null
   uint32_t record_words;
+  uint32_t gshift;                  // 1 (see shl_or)
 };
 
 // PM: parent bytes gathered per FN slot (>= the plan's largest predictor);
@@ -532,6 +528,7 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   fm.hoff = H->fn_hoff;
   fm.zp2 = zero_pos | (zero_pos << 16);
   fm.var = H->fn_var;
+  fm.sh = a.gshift;
   const uint32_t zp2 = fm.zp2;
   const uint32_t sdp = (sd + 3u) & ~3u;   // state buffer, padded to 16 bytes
   const uint32_t* blk = reinterpret_cast<const uint32_t*>(a.blob + H->blk_off);
@@ -795,6 +792,11 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
         }
         unsigned long long u = (static_cast<unsigned long long>(uhi) << 32) | ulo;
         uint32_t j0 = 0;
+        // the chain's next draws, indices sbase .. sbase + 63, one per lane
+        // (computed when a walk goes past them): a walk that flips again
+        // within them reads its next word with one lane read
+        uint32_t sbase = 0u, spec_lo = 0u, spec_hi = 0u;
+        bool have = false;
         for (;;) {
           uint32_t base = 0;
           for (uint32_t st = stride0;; st /= 64u) {
@@ -814,8 +816,17 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
           }
           j0 = i + 1u;
           if (j0 >= n) break;
-          const uint4 x = philox(traj, t, j0, PBN_STREAM_PERT, k0, k1);
-          u = (static_cast<unsigned long long>(uniform(x.y)) << 32) | uniform(x.x);
+          if (!have || j0 - sbase >= 64u) {
+            const uint4 x = philox(traj, t, j0 + lane, PBN_STREAM_PERT, k0, k1);
+            spec_lo = x.x;
+            spec_hi = x.y;
+            sbase = j0;
+            have = true;
+          }
+          const uint32_t off = j0 - sbase;   // wave-uniform lane index
+          // the builtin returns int: take both words as unsigned 32-bit values
+          u = (static_cast<unsigned long long>(uint32_t(__builtin_amdgcn_readlane(spec_hi, off))) << 32) |
+              uint32_t(__builtin_amdgcn_readlane(spec_lo, off));
         }
         wave_sync();
         if constexpr (kRegState)
@@ -931,6 +942,7 @@ __global__ void __launch_bounds__(1024) k_simulate(SimParams a) {
   t.tg = &a.tg;
   t.record = a.record && tl < a.record_traj ? a.record + size_t(tl) * a.record_words : nullptr;
   t.record_words = a.record_words;
+  t.gshift = a.gshift;
   run_traj<PM, UM, NREG, (ALIAS ? 4 : 0) | (REGSTATE ? 8 : 0)>(t);
 }
 
@@ -948,7 +960,7 @@ struct BatchParams {
   uint32_t ntasks;
   uint32_t wpb;
   uint32_t wave_bytes;
-  uint32_t pad;
+  uint32_t gshift;                 // 1: the gather step's shift, passed at run time (see shl_or)
   pbn_batch_ctl* ctl;              // device: task counter and the step window
 };
 
@@ -987,6 +999,7 @@ __global__ void __launch_bounds__(1024) k_batch(BatchParams a, const pbn_work* _
       t.tg = it.d_targets;
       t.record = nullptr;
       t.record_words = 0;
+      t.gshift = a.gshift;
       run_traj<PM, UM, 0, (PM == 7 ? 1 : 0) | 2>(t);
     }
   }
@@ -1154,6 +1167,7 @@ pbn_status simulate_common(bool plain, const pbn_plan* plan, const void* d_plan,
   p.count_from = count_from;
   p.wpb = wpb;
   p.wave_bytes = wave_bytes;
+  p.gshift = 1;
   p.tg = *targets;
   if (launch && launch->d_record) {
     p.record = launch->d_record;
@@ -1378,6 +1392,7 @@ pbn_status batch_enqueue(const pbn_plan* const* plans, uint32_t nitems, const pb
   p.ntasks = ntasks;
   p.wpb = wpb;
   p.wave_bytes = sh.wave_bytes;
+  p.gshift = 1;
   p.ctl = d_ctl;
   const uint32_t lds = 16u + wpb * sh.wave_bytes;
   if (sh.pm == 5) {

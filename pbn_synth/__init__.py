@@ -195,6 +195,14 @@ def batch_c4(count=512, seed=1004):
     return [medium_c2(int(sizes[k]), float(ps[k]), seed * 1000 + k) for k in range(count)]
 
 
+def batch_c4_network(k, count=512, seed=1004):
+    """Network k of batch_c4(count, seed), generated alone."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sizes = rng.integers(20, 1501, size=count)
+    ps = rng.choice([1e-3, 1e-4], size=count)
+    return medium_c2(int(sizes[k]), float(ps[k]), seed * 1000 + k)
+
+
 def served_c5(count=64, seed=1005):
     """Resident networks for the query service: n ~ U[50, 3000], p in {1e-3, 1e-4}."""
     rng = np.random.Generator(np.random.PCG64(seed))

@@ -172,6 +172,46 @@ def test_full_size_c4_batch_configuration():
         assert np.array_equal(b.counts[k].cpu().numpy()[:, sample, 0], ref["hits"]), k
 
 
+def test_full_size_c4_against_the_oracle_over_1000_steps():
+    """C4's 512 networks x 256 trajectories in one persistent launch of 1000
+    steps counted from step 500; 4 trajectories of the smallest, the largest
+    and three more networks against the oracle: every kept node and all three
+    counters.  The oracle runs in worker processes (no GPU use) while the GPU
+    runs the batch."""
+    import multiprocessing as mp
+
+    import oracle_jobs
+    nets = ps.batch_c4()
+    ntraj, steps, count_from = 256, 1000, 500
+    items = []
+    for k, net in enumerate(nets):
+        tg = [ps.non_leaf_targets(net, 3)]
+        plan = api.Plan(net, interest=[a for a, _ in tg[0]], reduce=1, group=0)
+        items.append((plan, 1004000 + k, ntraj, tg))
+    sizes = np.array([net["n"] for net in nets])
+    picks = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 7, 200, 511})
+    sample = [0, 85, 170, 255]
+    jobs = [(k, items[k][1], sample, steps, count_from, items[k][3]) for k in picks]
+    say(f"[gpu] C4 full size, 1000 steps; oracle on networks {picks} (n = {sizes[picks].tolist()})")
+    with mp.get_context("spawn").Pool(len(jobs)) as pool:
+        pending = pool.map_async(oracle_jobs.c4_network_run, jobs)
+        b = api.Batch(items, count_from=count_from, waves_per_block=4)
+        b.init_states()
+        b.set_window(0, steps)
+        b.launch()
+        torch.cuda.synchronize()
+        refs = pending.get(timeout=600)
+    for k, ref in zip(picks, refs):
+        plan = items[k][0]
+        orig = api.unpack_bits(api.to_original(plan, b.states[k]).cpu().numpy(), plan.n)
+        kept = plan.node_pos() != NONE
+        c = b.counts[k].cpu().numpy()
+        assert np.array_equal(orig[sample][:, kept], ref["state"][:, kept]), k
+        assert np.array_equal(c[:, sample, 0], ref["hits"]), k
+        assert np.array_equal(c[:, sample, 1], ref["n01"]), k
+        assert np.array_equal(c[:, sample, 2], ref["n10"]), k
+
+
 def test_batch_mixes_wide_and_narrow_predictor_records():
     """Networks whose predictors read up to 7 parents (packed images where only
     the slots reading 6-7 parents have two-unit records) batched with networks

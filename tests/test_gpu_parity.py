@@ -311,9 +311,12 @@ def test_full_size_c2_product_configuration():
 
 def test_full_size_c3_product_configuration():
     """C3 at its full trajectory count with the autotuner's plan (grouping into
-    at most 5 union bits and 4 nodes, 8 waves per workgroup): 4 sampled
-    trajectories against the oracle over 20 steps, then 20 000 steps against
-    the reduction-only plain kernel at another launch shape."""
+    at most 5 union bits and 4 nodes, 8 waves per workgroup): 64 trajectories
+    spread over the 65 536 against the oracle, every kept node and all three
+    counters -- over steps 0-249 counted from step 0, and over one 500-step
+    launch from step 0 counted from step 250, so that the counters cross the
+    burn-in boundary inside a launch; then 20 000 steps against the
+    reduction-only plain kernel at another launch shape."""
     cfg = ps.config("C3")
     net = cfg.net
     interest = sorted({a for tg in cfg.targets for a, _ in tg})
@@ -321,16 +324,25 @@ def test_full_size_c3_product_configuration():
     red = api.Plan(net, interest=interest, **REDUCED)
     assert tuned.info["n_table_slots"] > 0
     kept = tuned.node_pos() != NONE
-    sample = np.array([0, 20000, 40001, 65535])
-    say("[gpu] C3 full size, 20 steps")
-    ref = osim.run(net, cfg.seed, sample, 20, targets=cfg.targets)
+    sample = np.linspace(0, cfg.ntraj - 1, 64).round().astype(np.int64)
+    say("[gpu] C3 full size: oracle on 64 trajectories x 500 steps")
+    nw = osim.Network(net)
+    ref_a = osim.run(net, cfg.seed, sample, 250, targets=cfg.targets, nw=nw)
+    ref_b = osim.run(net, cfg.seed, sample, 250, step0=250, count_from=250, targets=cfg.targets, nw=nw,
+                     state=ref_a["state"])
     tg = tuned.targets(cfg.targets)
-    state = api.state_init(tuned, cfg.seed, cfg.ntraj)
-    counts = api.new_counts(len(cfg.targets), cfg.ntraj)
-    api.simulate(tuned, cfg.seed, state, counts, tg, 0, 20, waves_per_block=8)
-    orig = api.unpack_bits(api.to_original(tuned, state).cpu().numpy(), tuned.n)
-    assert np.array_equal(orig[sample][:, kept], ref["state"][:, kept])
-    assert np.array_equal(counts.cpu().numpy()[:, sample, 0], ref["hits"])
+    for steps, count_from, ref in ((250, 0, ref_a), (500, 250, ref_b)):
+        say(f"[gpu] C3 full size, {steps} steps in one launch, counted from step {count_from}")
+        state = api.state_init(tuned, cfg.seed, cfg.ntraj)
+        counts = api.new_counts(len(cfg.targets), cfg.ntraj)
+        api.simulate(tuned, cfg.seed, state, counts, tg, 0, steps, count_from=count_from, waves_per_block=8)
+        orig = api.unpack_bits(api.to_original(tuned, state).cpu().numpy(), tuned.n)
+        c = counts.cpu().numpy()
+        assert np.array_equal(orig[sample][:, kept], ref["state"][:, kept]), steps
+        assert np.array_equal(c[:, sample, 0], ref["hits"]), steps
+        assert np.array_equal(c[:, sample, 1], ref["n01"]), steps
+        assert np.array_equal(c[:, sample, 2], ref["n10"]), steps
+    assert ref_b["hits"].sum() > 0 and (ref_b["n01"].sum() + ref_b["n10"].sum()) > 0
     runs = []
     for plan, wpb, use_plain in ((tuned, 8, False), (red, 2, True)):
         say(f"[gpu] C3 20000 steps, n_slots={plan.info['n_slots']}, wpb={wpb}")
