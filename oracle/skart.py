@@ -1,5 +1,11 @@
 """Skart stopping rule for one recorded output sequence (TEST INFRASTRUCTURE ONLY).
 
+Parity unpinned: no published Skart implementation or worked example is
+available here, so the constants below are this project's reading of the
+published procedure; its components (skewness, the t interval, von Neumann's
+test, Willink's adjustment, the correlation factor) and its end-to-end coverage
+are pinned, the exact constants are not.
+
 The paper names the Skart method beside the two-state Markov chain approach as
 the statistical procedures its authors used for steady-state analysis of large
 PBNs (Section 1, previous work); it does not restate it.  Skart (Tafazzoli,
