@@ -474,7 +474,7 @@ typedef struct pbn_batch_ctl {
   uint32_t next_task;
   uint32_t step0;
   uint32_t nsteps;
-  uint32_t reserved;
+  uint32_t ntasks;   /* written by pbn_batch_launch_noalloc's own schedule; unused otherwise */
 } pbn_batch_ctl;
 
 typedef struct pbn_graph pbn_graph;
@@ -490,6 +490,29 @@ pbn_status pbn_batch_graph_create(const pbn_plan* const* plans, uint32_t nitems,
                                   pbn_batch_ctl* d_ctl, uint32_t waves_per_block, uint32_t passes,
                                   pbn_graph** out);
 pbn_status pbn_graph_launch(pbn_graph* graph, void* stream);
+
+/* Allocation-free batch launch, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation.  Same computation as pbn_batch_launch with the step
+ * window (step0, nsteps) passed by value: every trajectory of every item
+ * advances from step step0 + item.step0 by nsteps steps; states and counters
+ * (the items' caller-owned buffers) come out identical.
+ *   plans[nitems]  host: the items' plans (kernel shape, as pbn_batch_launch)
+ *   ntraj[nitems]  host: the items' trajectory counts (must equal d_items[k].ntraj)
+ *   d_items        device: the work items, as pbn_batch_launch
+ * The control block and the task schedule live in a device array of the
+ * library (512.25 KiB per GPU, held until the process ends) instead of caller
+ * buffers: at most 4096 items and 65 536 tasks of waves_per_block trajectories
+ * per call (PBN_ELIMIT beyond).  Items run in the caller's order (list the
+ * largest networks first, as pbn_batch_tasks orders them).  The call makes no
+ * device allocation, no memset and no host synchronisation; each call resets
+ * the array's task counter with a kernel.  All calls on one GPU share that
+ * GPU's array: calls that overlap on one GPU (several streams or host threads)
+ * race and must be serialised by the caller.                                  */
+pbn_status pbn_batch_launch_noalloc(const pbn_plan* const* plans, const uint32_t* ntraj, uint32_t nitems,
+                                    const pbn_work* d_items, uint32_t step0, uint32_t nsteps,
+                                    uint32_t waves_per_block, void* stream);
+pbn_status pbn_graph_destroy(pbn_graph* graph);
 pbn_status pbn_graph_destroy(pbn_graph* graph);
 
 #ifdef __cplusplus

@@ -361,6 +361,7 @@ class Batch:
         self.items_dev = _to_device_bytes(works)
         self._plan_arr = (C.c_void_p * len(items))(*[p.handle.value for p in self.plans])
         ntraj = np.asarray([it[2] for it in items], dtype=np.uint32)
+        self._ntraj = ntraj
         nt = C.c_uint32()
         check(lib().pbn_batch_tasks(self._plan_arr, _ptr(ntraj, C.c_uint32), len(items), self.wpb,
                                     None, None, C.byref(nt)))
@@ -388,6 +389,13 @@ class Batch:
 
     def launch(self, stream=None):
         check(lib().pbn_batch_launch(*self._args(), _stream(stream)))
+
+    def launch_noalloc(self, step0, nsteps, stream=None):
+        """pbn_batch_launch_noalloc: the step window by value, the schedule in
+        the library's device array (items in list order)."""
+        check(lib().pbn_batch_launch_noalloc(self._plan_arr, _ptr(self._ntraj, C.c_uint32), len(self.plans),
+                                             _dptr(self.items_dev), int(step0), int(nsteps), self.wpb,
+                                             _stream(stream)))
 
     def graph(self, passes):
         g = C.c_void_p()

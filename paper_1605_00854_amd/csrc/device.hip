@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <cstdio>
 #include <string>
 #include <vector>
@@ -970,12 +971,14 @@ __global__ void __launch_bounds__(1024) k_batch(BatchParams a, const pbn_work* _
   uint32_t& claimed = *reinterpret_cast<uint32_t*>(smem);   // first 16 bytes: the claimed task
   const uint32_t wave = uniform(threadIdx.x >> 6);   // wave-uniform: keeps per-trajectory data scalar
   const uint32_t wstep0 = a.ctl->step0, nsteps = a.ctl->nsteps;
+  // PBN_NONE: the schedule was written on the device (allocation-free launch)
+  const uint32_t ntasks = a.ntasks != PBN_NONE ? a.ntasks : uniform(a.ctl->ntasks);
   for (;;) {
     if (threadIdx.x == 0) claimed = atomicAdd(&a.ctl->next_task, 1u);
     __syncthreads();
     const uint32_t task = uniform(claimed);   // the same for the workgroup: scalar loads of the task's item
     __syncthreads();
-    if (task >= a.ntasks) return;        // uniform across the workgroup
+    if (task >= ntasks) return;          // uniform across the workgroup
     // the task's work item, read into wave-uniform values (scalar registers)
     const pbn_work& it = items[uniform(a.tasks[task])];
     const uint32_t tl = uniform(a.task_first[task]) + wave;
@@ -1009,6 +1012,58 @@ __global__ void __launch_bounds__(1024) k_batch(BatchParams a, const pbn_work* _
 // before a batch pass, advance the step window after it.
 __global__ void k_batch_begin(pbn_batch_ctl* ctl) { ctl->next_task = 0; }
 __global__ void k_batch_end(pbn_batch_ctl* ctl) { ctl->step0 += ctl->nsteps; }
+
+// ------------------------------------------------ allocation-free batches
+// pbn_batch_launch_noalloc keeps what pbn_batch_launch takes from the caller
+// as workspace -- the control block and the task schedule -- in one
+// file-scope device array, so that the entry point allocates nothing.  Each
+// GPU holds its own copy until the process ends; the host reaches it only
+// through the address hipGetSymbolAddress returns for the current device.
+constexpr uint32_t kNoAllocMaxItems = 4096u;    // work items per call
+constexpr uint32_t kNoAllocMaxTasks = 65536u;   // tasks (waves_per_block trajectories of one item) per call
+constexpr uint32_t kScratchCtlWords = 64u;      // the control block, alone in the first 256 bytes
+constexpr size_t kScratchWords = kScratchCtlWords + 2u * size_t(kNoAllocMaxTasks);
+static __device__ __align__(256) uint32_t scratch[kScratchWords];   // 512.25 KiB
+
+// The schedule of one allocation-free launch, written by one workgroup of
+// 1024 threads: items in the caller's order, ceil(ntraj / wpb) tasks each
+// (task k of an item starts at trajectory k wpb); the control block gets a
+// zero task counter, the step window and the task count.  Items beyond
+// kNoAllocMaxItems and tasks beyond kNoAllocMaxTasks are rejected on the host.
+__global__ void __launch_bounds__(1024) k_noalloc_schedule(const pbn_work* items, uint32_t nitems, uint32_t wpb,
+                                                          uint32_t step0, uint32_t nsteps, uint32_t* scr) {
+  __shared__ uint32_t part[1024];
+  const uint32_t t = threadIdx.x;
+  const uint32_t chunk = (nitems + 1023u) / 1024u;
+  const uint32_t lo = min(nitems, t * chunk), hi = min(nitems, lo + chunk);
+  uint32_t mine = 0;
+  for (uint32_t k = lo; k < hi; ++k) mine += (items[k].ntraj + wpb - 1u) / wpb;
+  part[t] = mine;
+  __syncthreads();
+  for (uint32_t d = 1; d < 1024u; d <<= 1) {   // inclusive prefix sums
+    const uint32_t v = t >= d ? part[t - d] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t* tasks = scr + kScratchCtlWords;
+  uint32_t* first = tasks + kNoAllocMaxTasks;
+  uint32_t at = part[t] - mine;
+  for (uint32_t k = lo; k < hi; ++k) {
+    const uint32_t cnt = (items[k].ntraj + wpb - 1u) / wpb;
+    for (uint32_t f = 0; f < cnt && at < kNoAllocMaxTasks; ++f, ++at) {
+      tasks[at] = k;
+      first[at] = f * wpb;
+    }
+  }
+  if (t == 1023u) {
+    pbn_batch_ctl* ctl = reinterpret_cast<pbn_batch_ctl*>(scr);
+    ctl->next_task = 0;
+    ctl->step0 = step0;
+    ctl->nsteps = nsteps;
+    ctl->ntasks = min(part[1023], kNoAllocMaxTasks);
+  }
+}
 
 // s(0): bit i of node i's INIT word, placed at the node's plan position.
 __global__ void k_state_init(const uint8_t* blob, unsigned long long seed, uint32_t traj0, uint32_t ntraj,
@@ -1357,8 +1412,14 @@ pbn_status batch_shape(const pbn_plan* const* plans, uint32_t nitems, BatchShape
   return PBN_OK;
 }
 
+// `sched`: the allocation-free launch's schedule arguments (items, nitems,
+// step window; p.ctl and p.tasks point into the device array), or null.
+struct NoAllocSched {
+  uint32_t nitems, step0, nsteps, ntasks;
+};
+
 template <int PM, int UM>
-pbn_status launch_batch_t(const BatchParams& p, uint32_t lds, hipStream_t s) {
+pbn_status launch_batch_t(const BatchParams& p, uint32_t lds, hipStream_t s, const NoAllocSched* sched = nullptr) {
   auto* fn = k_batch<PM, UM>;
   int dev = 0, ncu = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -1368,16 +1429,22 @@ pbn_status launch_batch_t(const BatchParams& p, uint32_t lds, hipStream_t s) {
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, int(64u * p.wpb), lds);
   if (e != hipSuccess) return hip_check(e, "batch occupancy query");
   const uint32_t resident = uint32_t(std::max(1, per_cu) * std::max(1, ncu));
-  const uint32_t blocks = std::max(1u, std::min(p.ntasks, resident));
-  hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(1), 0, s, p.ctl);
-  hipLaunchKernelGGL(fn, dim3(blocks), dim3(64u * p.wpb), lds, s, p, p.items);
-  hipLaunchKernelGGL(k_batch_end, dim3(1), dim3(1), 0, s, p.ctl);
+  const uint32_t blocks = std::max(1u, std::min(sched ? sched->ntasks : p.ntasks, resident));
+  if (sched) {
+    hipLaunchKernelGGL(k_noalloc_schedule, dim3(1), dim3(1024), 0, s, p.items, sched->nitems, p.wpb, sched->step0,
+                       sched->nsteps, reinterpret_cast<uint32_t*>(p.ctl));
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(64u * p.wpb), lds, s, p, p.items);
+  } else {
+    hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(1), 0, s, p.ctl);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(64u * p.wpb), lds, s, p, p.items);
+    hipLaunchKernelGGL(k_batch_end, dim3(1), dim3(1), 0, s, p.ctl);
+  }
   return hip_check(hipGetLastError(), "k_batch launch");
 }
 
 pbn_status batch_enqueue(const pbn_plan* const* plans, uint32_t nitems, const pbn_work* d_items,
                          const uint32_t* d_tasks, const uint32_t* d_task_first, uint32_t ntasks, pbn_batch_ctl* d_ctl,
-                         uint32_t wpb, hipStream_t s) {
+                         uint32_t wpb, hipStream_t s, const NoAllocSched* sched = nullptr) {
   if (!plans || !d_items || !d_tasks || !d_task_first || !d_ctl) return fail(PBN_EINVAL, "null argument");
   if (wpb < 1 || wpb > 16) return fail(PBN_EINVAL, "waves_per_block must be 1..16");
   if (nitems == 0 || ntasks == 0) return PBN_OK;
@@ -1396,13 +1463,13 @@ pbn_status batch_enqueue(const pbn_plan* const* plans, uint32_t nitems, const pb
   p.ctl = d_ctl;
   const uint32_t lds = 16u + wpb * sh.wave_bytes;
   if (sh.pm == 5) {
-    if (sh.um == 0) return launch_batch_t<5, 0>(p, lds, s);
-    if (sh.um == 8) return launch_batch_t<5, 8>(p, lds, s);
-    return launch_batch_t<5, 16>(p, lds, s);
+    if (sh.um == 0) return launch_batch_t<5, 0>(p, lds, s, sched);
+    if (sh.um == 8) return launch_batch_t<5, 8>(p, lds, s, sched);
+    return launch_batch_t<5, 16>(p, lds, s, sched);
   }
-  if (sh.um == 0) return launch_batch_t<7, 0>(p, lds, s);
-  if (sh.um == 8) return launch_batch_t<7, 8>(p, lds, s);
-  return launch_batch_t<7, 16>(p, lds, s);
+  if (sh.um == 0) return launch_batch_t<7, 0>(p, lds, s, sched);
+  if (sh.um == 8) return launch_batch_t<7, 8>(p, lds, s, sched);
+  return launch_batch_t<7, 16>(p, lds, s, sched);
 }
 
 }  // namespace
@@ -1441,6 +1508,57 @@ extern "C" pbn_status pbn_batch_launch(const pbn_plan* const* plans, uint32_t ni
   pbn::clear_error();
   return batch_enqueue(plans, nitems, d_items, d_tasks, d_task_first, ntasks, d_ctl, waves_per_block,
                        static_cast<hipStream_t>(stream));
+}
+
+namespace {
+
+// Device address of this file's `scratch` array on the current device, taken
+// once per device (each GPU holds its own copy).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t* g_scratch_ptr[kMaxDevices] = {};
+
+pbn_status noalloc_scratch(uint32_t** out) {
+  int dev = 0;
+  pbn_status st = hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (st != PBN_OK) return st;
+  if (dev < 0 || dev >= kMaxDevices) return fail(PBN_ELIMIT, "device index beyond the library's table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    st = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress");
+    if (st != PBN_OK) return st;
+    g_scratch_ptr[dev] = static_cast<uint32_t*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return PBN_OK;
+}
+
+}  // namespace
+
+extern "C" pbn_status pbn_batch_launch_noalloc(const pbn_plan* const* plans, const uint32_t* ntraj, uint32_t nitems,
+                                               const pbn_work* d_items, uint32_t step0, uint32_t nsteps,
+                                               uint32_t waves_per_block, void* stream) {
+  pbn::clear_error();
+  if (!plans || !ntraj || !d_items) return fail(PBN_EINVAL, "null argument");
+  if (waves_per_block < 1 || waves_per_block > 16) return fail(PBN_EINVAL, "waves_per_block must be 1..16");
+  if (nitems > kNoAllocMaxItems)
+    return fail(PBN_ELIMIT, "nitems = " + std::to_string(nitems) + " exceeds the allocation-free launch's " +
+                                std::to_string(kNoAllocMaxItems));
+  if (uint64_t(step0) + nsteps > 0xFFFFFFFFull) return fail(PBN_ERANGE, "step counter exceeds 32 bits");
+  uint64_t total = 0;
+  for (uint32_t k = 0; k < nitems; ++k) total += (uint64_t(ntraj[k]) + waves_per_block - 1) / waves_per_block;
+  if (total > kNoAllocMaxTasks)
+    return fail(PBN_ELIMIT, "the batch needs " + std::to_string(total) + " tasks; the allocation-free launch holds " +
+                                std::to_string(kNoAllocMaxTasks) + " (raise waves_per_block or split the batch)");
+  if (nitems == 0 || total == 0 || nsteps == 0) return PBN_OK;
+  uint32_t* scr = nullptr;
+  pbn_status st = noalloc_scratch(&scr);
+  if (st != PBN_OK) return st;
+  const NoAllocSched sched{nitems, step0, nsteps, uint32_t(total)};
+  return batch_enqueue(plans, nitems, d_items, scr + kScratchCtlWords, scr + kScratchCtlWords + kNoAllocMaxTasks,
+                       PBN_NONE, reinterpret_cast<pbn_batch_ctl*>(scr), waves_per_block,
+                       static_cast<hipStream_t>(stream), &sched);
 }
 
 extern "C" pbn_status pbn_batch_graph_create(const pbn_plan* const* plans, uint32_t nitems, const pbn_work* d_items,
