@@ -266,10 +266,16 @@ pbn_status pbn_state_init(const pbn_plan* plan, const void* d_plan, uint64_t see
  *                 (word w bit b = step count_from + 32 w + b).  NULL: none.
  * Errors: PBN_EINVAL when d_record is set and record_words is 0. */
 typedef struct pbn_launch_opts {
-  uint32_t waves_per_block;       /* trajectories per workgroup, 1 .. 16      */
+  uint32_t waves_per_block;       /* wavefronts per workgroup, 1 .. 16        */
   uint32_t record_traj;
   uint32_t record_words;
-  uint32_t reserved;
+  uint32_t traj_per_wave;         /* 0 or 1: one trajectory per wavefront;
+                                     2 .. 4: that many trajectories share a
+                                     wavefront's lane passes (keyed FN-only
+                                     plans whose K slot sets fit 4 passes of
+                                     64 lanes, K n_jobs <= 64, K targets <= 64,
+                                     no recording; PBN_EINVAL otherwise).
+                                     Results are identical for every value. */
   uint32_t* d_record;
 } pbn_launch_opts;
 
@@ -513,7 +519,25 @@ pbn_status pbn_batch_launch_noalloc(const pbn_plan* const* plans, const uint32_t
                                     const pbn_work* d_items, uint32_t step0, uint32_t nsteps,
                                     uint32_t waves_per_block, void* stream);
 pbn_status pbn_graph_destroy(pbn_graph* graph);
-pbn_status pbn_graph_destroy(pbn_graph* graph);
+
+/* --------------------------------------------------------------- probes
+ * Measurement kernels for the step kernel's roofline (no simulation work).
+ * The caller times them on `stream`; a launch performs
+ * blocks x 256 threads x iters x 8 gathers.
+ *
+ * pbn_probe_lds_gather: random gathers of `width` bytes (1, 4 or 16) from a
+ *   2^log2_bytes-byte LDS buffer (7 <= log2_bytes <= 16) per workgroup;
+ *   pattern 0: random aligned addresses (bank conflicts as they fall),
+ *   pattern 1: the lanes of a wave read bank-distinct words of random rows.
+ * pbn_probe_vmem_gather: random 16-byte gathers from the caller's device
+ *   buffer of at least 2^log2_bytes bytes (4 <= log2_bytes <= 30) through the
+ *   vector L1 and L2.
+ * d_sink: one device word, written only by an improbable value (keeps the
+ * reads).  Errors: PBN_EINVAL for out-of-range arguments, PBN_EHIP.         */
+pbn_status pbn_probe_lds_gather(uint32_t log2_bytes, uint32_t width, uint32_t pattern, uint32_t iters,
+                                uint32_t blocks, uint32_t* d_sink, void* stream);
+pbn_status pbn_probe_vmem_gather(const void* d_buf, uint32_t log2_bytes, uint32_t iters, uint32_t blocks,
+                                 uint32_t* d_sink, void* stream);
 
 #ifdef __cplusplus
 }

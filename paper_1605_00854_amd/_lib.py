@@ -47,7 +47,7 @@ class pbn_targets(C.Structure):
 
 class pbn_launch_opts(C.Structure):
     _fields_ = [("waves_per_block", C.c_uint32), ("record_traj", C.c_uint32), ("record_words", C.c_uint32),
-                ("reserved", C.c_uint32), ("d_record", C.c_void_p)]
+                ("traj_per_wave", C.c_uint32), ("d_record", C.c_void_p)]
 
 
 class pbn_rl_out(C.Structure):
@@ -108,6 +108,8 @@ SIGNATURES = {
     "pbn_batch_tasks": (C.c_int32, [C.POINTER(_P), _pU32, _U32, _U32, _pU32, _pU32, _pU32]),
     "pbn_batch_launch": (C.c_int32, [C.POINTER(_P), _U32, _P, _P, _P, _U32, _P, _U32, _P]),
     "pbn_batch_launch_noalloc": (C.c_int32, [C.POINTER(_P), _pU32, _U32, _P, _U32, _U32, _U32, _P]),
+    "pbn_probe_lds_gather": (C.c_int32, [_U32, _U32, _U32, _U32, _U32, _P, _P]),
+    "pbn_probe_vmem_gather": (C.c_int32, [_P, _U32, _U32, _U32, _P, _P]),
     "pbn_batch_graph_create": (C.c_int32, [C.POINTER(_P), _U32, _P, _P, _P, _U32, _P, _U32, _U32,
                                            C.POINTER(_P)]),
     "pbn_graph_launch": (C.c_int32, [_P, _P]),

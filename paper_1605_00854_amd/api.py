@@ -290,13 +290,15 @@ def state_init(plan, seed, ntraj, traj0=0, state=None, stream=None):
 
 
 def simulate(plan, seed, state, counts, targets, step0, nsteps, *, traj0=0, count_from=0, plain=False,
-             waves_per_block=0, stream=None, record=None):
+             waves_per_block=0, traj_per_wave=1, stream=None, record=None):
     """Advance trajectories traj0 .. traj0+ntraj-1 by nsteps (global steps step0..).
 
+    traj_per_wave: trajectories sharing one wavefront's lane passes (1 .. 4).
     record: optional int32 device tensor [r][words]: trajectories 0 .. r-1 of
     the launch OR target 0's indicator bits into it (bit t - count_from)."""
     ntraj = state.shape[0]
     lo = _lib.pbn_launch_opts(int(waves_per_block))
+    lo.traj_per_wave = int(traj_per_wave)
     if record is not None:
         lo.record_traj = int(record.shape[0])
         lo.record_words = int(record.shape[1])

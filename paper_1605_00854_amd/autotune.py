@@ -1,6 +1,6 @@
 """Autotuner: picks the preparation options (reduction, grouping caps, weights)
-and the launch shape (trajectories per workgroup) of the step kernel by timing
-short probe runs on the device.
+and the launch shape (wavefronts per workgroup, trajectories per wavefront) of
+the step kernel by timing short probe runs on the device.
 
 Every candidate simulates the same trajectories bit for bit (reduction and
 grouping never change a kept node), so the choice is purely a speed choice.
@@ -25,7 +25,7 @@ def candidates(quick=False, reduce=1):
     candidates use: 1 (Definition 1's leaves) or 2 (the cone of influence of
     the nodes of interest, which removes a superset of the leaves)."""
     out = [PLAIN, dict(reduce=reduce, group=0)]
-    bits = (4, 6, 8) if quick else (4, 5, 6, 8, 10, 12)
+    bits = (4, 5, 6, 8) if quick else (4, 5, 6, 8, 10, 12)
     nodes = (2, 4) if quick else (2, 3, 4)
     for b in bits:
         for g in nodes:
@@ -45,16 +45,41 @@ def best_reduction(net, interest):
 _CACHE = {}
 
 
-def _probe(torch, plan, tg, seed, ntraj, steps, wpb, plain):
+def traj_per_wave_choices(plan, ntargets):
+    """Trajectories per wavefront the step kernel accepts for a plan: 1, and
+    2 .. 4 for keyed plans without table slots whose K slot sets fit four lane
+    passes and whose K steps' draws fit one wave; only counts that save lane
+    passes are worth probing."""
+    out = [1]
+    info = plan.info
+    if info["n_table_slots"] or info["max_union_bits"] or plan.opts.sampling:
+        return out
+    S, passes = info["n_slots"], info["n_passes"]
+    for k in (2, 3, 4):
+        packed = (k * S + 63) // 64
+        if packed <= 4 and k * info["n_jobs"] <= 64 and k * ntargets <= 64 and packed < k * passes:
+            out.append(k)
+    return out
+
+
+def best_launch(trials):
+    """(waves per workgroup, trajectories per wavefront) of the fastest trial."""
+    ok = [t for t in trials if "node_updates_per_s" in t]
+    best = max(ok, key=lambda t: t["node_updates_per_s"])
+    return best["wpb"], best.get("tpw", 1)
+
+
+def _probe(torch, plan, tg, seed, ntraj, steps, wpb, plain, tpw=1):
     state = api.state_init(plan, seed, ntraj)
     counts = api.new_counts(tg.ntargets, ntraj)
-    api.simulate(plan, seed, state, counts, tg, 0, min(steps, 64), plain=plain, waves_per_block=wpb)
+    api.simulate(plan, seed, state, counts, tg, 0, min(steps, 64), plain=plain, waves_per_block=wpb,
+                 traj_per_wave=tpw)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    api.simulate(plan, seed, state, counts, tg, 64, steps, plain=plain, waves_per_block=wpb)
+    api.simulate(plan, seed, state, counts, tg, 64, steps, plain=plain, waves_per_block=wpb, traj_per_wave=tpw)
     e1.record(stream)
     e1.synchronize()
     return e0.elapsed_time(e1) * 1e-3
@@ -86,14 +111,16 @@ def tune(net, interest, target_sets, ntraj, seed=1, probe_steps=2000, wpbs=(2, 4
         seen.add(sig)
         tg = plan.targets(target_sets)
         plain = plan.info["n_table_slots"] == 0
-        for wpb in wpbs:
-            dt = _probe(torch, plan, tg, seed, ntraj, probe_steps, wpb, plain)
-            rate = ntraj * probe_steps * n / dt
-            trials.append({"opts": opts, "wpb": wpb, "node_updates_per_s": rate, "slots": plan.info["n_slots"],
-                           "table_slots": plan.info["n_table_slots"], "passes": plan.info["n_passes"]})
-            if verbose:
-                print(f"[autotune] {opts} wpb={wpb} slots={plan.info['n_slots']} "
-                      f"tables={plan.info['n_table_slots']} {rate:.3e}", flush=True)
+        for tpw in traj_per_wave_choices(plan, tg.ntargets):
+            for wpb in wpbs:
+                dt = _probe(torch, plan, tg, seed, ntraj, probe_steps, wpb, plain, tpw)
+                rate = ntraj * probe_steps * n / dt
+                trials.append({"opts": opts, "wpb": wpb, "tpw": tpw, "node_updates_per_s": rate,
+                               "slots": plan.info["n_slots"], "table_slots": plan.info["n_table_slots"],
+                               "passes": plan.info["n_passes"]})
+                if verbose:
+                    print(f"[autotune] {opts} wpb={wpb} tpw={tpw} slots={plan.info['n_slots']} "
+                          f"tables={plan.info['n_table_slots']} {rate:.3e}", flush=True)
     ok = [t for t in trials if "node_updates_per_s" in t]
     best = max(ok, key=lambda t: t["node_updates_per_s"])
     out = (best["opts"], best["wpb"], trials)

@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libpbn_amd.so")
 ARCH = "gfx950"
 
 HOST_SOURCES = ["host_net.cpp", "host_plan.cpp", "host_stats.cpp"]
-DEVICE_SOURCES = ["device.hip"]
+DEVICE_SOURCES = ["device.hip", "probe.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall", "-Wno-unused-function"]
 # never emit packed FP32 instructions (none are needed: the path is integer only)

@@ -171,6 +171,8 @@ struct SimParams {
   uint32_t record_words; // words per recording trajectory
   uint32_t gshift;       // 1: the gather step's shift, passed at run time (see shl_or)
   uint32_t* record;      // [record_traj][record_words] or null
+  uint32_t tpw;          // trajectories per wavefront (k_simulate_multi)
+  uint32_t mfill;        // steps per Philox fill (k_simulate_multi)
   pbn_targets tg;
 };
 
@@ -350,10 +352,7 @@ __device__ __forceinline__ void load_slot(SlotRegs<Shape<PM, UM>::XW, Shape<PM, 
                                           uint32_t slot, const FnFmt& fm) {
   constexpr int XW = Shape<PM, UM>::XW, TTW = Shape<PM, UM>::TTW, PW = Shape<PM, UM>::PW, UW = Shape<PM, UM>::UW;
   constexpr bool G = (MODE & 2) != 0;
-  uint4 rec = img_u4<G>(img + 16u * slot);
-  // all four words are taken here: keeps the record one 16-byte read instead
-  // of pieces re-read inside the branches below
-  asm volatile("" : "+v"(rec.x), "+v"(rec.y), "+v"(rec.z), "+v"(rec.w));
+  const uint4 rec = img_u4<G>(img + 16u * slot);
   r.info = rec.x;
   r.base = rec.y;
   r.choice = rec.z;
@@ -470,6 +469,55 @@ __device__ __forceinline__ void store_slot(uint8_t* ns, uint32_t info, uint32_t 
     *reinterpret_cast<uint32_t*>(ns + spos) = (out * 0x204081u) & 0x01010101u;   // bit k -> byte k
   else
     ns[spos] = uint8_t(out);
+}
+
+// A perturbation-only step (u >= Q[n], Eq. 1): walk the skip chain over all
+// n original nodes of one trajectory, starting from its first drawn word u,
+// and flip the kept nodes (bytes of `csb`, or bits of the wave-uniform word
+// `rst` with REG).  Each draw counts the unperturbed nodes before the next
+// perturbed one with ballots over Q (radix 64).  The chain's later draws are
+// computed 64 at a time, one per lane (indices sbase .. sbase + 63), when the
+// walk goes past them; a walk that flips again within them reads its next
+// word with one lane read.  All lanes of the wave take part.
+template <bool G, bool REG>
+__device__ __forceinline__ void walk_chain(unsigned long long u, uint32_t n, uint32_t stride0,
+                                           const unsigned long long* Q, const uint32_t* o2p, uint32_t traj, uint32_t t,
+                                           uint32_t k0, uint32_t k1, uint32_t lane, uint8_t* csb,
+                                           unsigned long long& rst) {
+  uint32_t j0 = 0;
+  uint32_t sbase = 0u, spec_lo = 0u, spec_hi = 0u;
+  bool have = false;
+  for (;;) {
+    uint32_t base = 0;
+    for (uint32_t st = stride0;; st /= 64u) {
+      const uint32_t h = base + st * (lane + 1u);
+      const bool gt = h <= n && blob_u64<G>(Q + h) > u;
+      base += st * uint32_t(__popcll(__ballot(gt)));
+      if (st == 1u) break;
+    }
+    const uint32_t C = uniform(base);
+    if (C >= n - j0) break;
+    const uint32_t i = j0 + C;
+    const uint32_t pos = blob_u32<G>(o2p + i);
+    if constexpr (REG) {
+      if (pos != PBN_NONE) rst ^= 1ull << uniform(pos);
+    } else if (pos != PBN_NONE && lane == 0) {
+      csb[pos] ^= 1u;
+    }
+    j0 = i + 1u;
+    if (j0 >= n) break;
+    if (!have || j0 - sbase >= 64u) {
+      const uint4 x = philox(traj, t, j0 + lane, PBN_STREAM_PERT, k0, k1);
+      spec_lo = x.x;
+      spec_hi = x.y;
+      sbase = j0;
+      have = true;
+    }
+    const uint32_t off = j0 - sbase;   // wave-uniform lane index
+    // the builtin returns int: take both words as unsigned 32-bit values
+    u = (static_cast<unsigned long long>(uint32_t(__builtin_amdgcn_readlane(spec_hi, off))) << 32) |
+        uint32_t(__builtin_amdgcn_readlane(spec_lo, off));
+  }
 }
 
 // Everything one wavefront needs to advance one trajectory.
@@ -791,44 +839,8 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
           ulo = uniform(pr.x);
           uhi = uniform(pr.y);
         }
-        unsigned long long u = (static_cast<unsigned long long>(uhi) << 32) | ulo;
-        uint32_t j0 = 0;
-        // the chain's next draws, indices sbase .. sbase + 63, one per lane
-        // (computed when a walk goes past them): a walk that flips again
-        // within them reads its next word with one lane read
-        uint32_t sbase = 0u, spec_lo = 0u, spec_hi = 0u;
-        bool have = false;
-        for (;;) {
-          uint32_t base = 0;
-          for (uint32_t st = stride0;; st /= 64u) {
-            const uint32_t h = base + st * (lane + 1u);
-            const bool gt = h <= n && blob_u64<(MODE & 2) != 0>(Q + h) > u;
-            base += st * uint32_t(__popcll(__ballot(gt)));
-            if (st == 1u) break;
-          }
-          const uint32_t C = uniform(base);
-          if (C >= n - j0) break;
-          const uint32_t i = j0 + C;
-          const uint32_t pos = blob_u32<(MODE & 2) != 0>(o2p + i);
-          if constexpr (kRegState) {
-            if (pos != PBN_NONE) rst ^= 1ull << uniform(pos);
-          } else if (pos != PBN_NONE && lane == 0) {
-            csb[pos] ^= 1u;
-          }
-          j0 = i + 1u;
-          if (j0 >= n) break;
-          if (!have || j0 - sbase >= 64u) {
-            const uint4 x = philox(traj, t, j0 + lane, PBN_STREAM_PERT, k0, k1);
-            spec_lo = x.x;
-            spec_hi = x.y;
-            sbase = j0;
-            have = true;
-          }
-          const uint32_t off = j0 - sbase;   // wave-uniform lane index
-          // the builtin returns int: take both words as unsigned 32-bit values
-          u = (static_cast<unsigned long long>(uint32_t(__builtin_amdgcn_readlane(spec_hi, off))) << 32) |
-              uint32_t(__builtin_amdgcn_readlane(spec_lo, off));
-        }
+        walk_chain<(MODE & 2) != 0, kRegState>((static_cast<unsigned long long>(uhi) << 32) | ulo, n, stride0, Q, o2p,
+                                               traj, t, k0, k1, lane, csb, rst);
         wave_sync();
         if constexpr (kRegState)
           z = target_reg(rst);
@@ -905,6 +917,269 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   }
 }
 
+// Several trajectories per wavefront: FN-only keyed plans whose slots leave
+// lanes of their last pass idle (C2: 85 slots in two passes of 64).  With K
+// trajectories per wave, virtual slot v = 64 p + lane of pass p is slot v mod S
+// of trajectory v / S (S slots per trajectory), so the K S virtual slots take
+// ceil(K S / 64) passes instead of K ceil(S / 64).  Each trajectory keeps its
+// own state buffer, drawn words and counters, and every result is the one the
+// one-trajectory kernel gives.  Per step, the passes evaluate every virtual
+// slot from s(t); trajectories perturbed in the step write nothing (their
+// lanes store to a spare byte) and then walk their perturbation chains one
+// after the other.  Target t of trajectory j is counted on lane t K + j.
+struct MultiArgs {
+  const uint8_t* blob;
+  const uint8_t* img;
+  uint8_t* wb;                      // this wave's LDS: K state buffers, a spare word, the ring
+  unsigned long long seed;
+  uint32_t traj0;                   // global id of the wave's trajectory 0
+  uint32_t tl0;                     // its index in the launch's state/count arrays
+  uint32_t nvalid;                  // trajectories of this wave (1 .. K)
+  uint32_t K;                       // trajectories per wave
+  uint32_t fill;                    // steps per Philox fill (fill K n_jobs <= 4 x 64, fill K <= 64)
+  uint32_t ntraj, step0, nsteps, count_from;
+  uint32_t* state;
+  unsigned long long* counts;
+  const pbn_targets* tg;
+  uint32_t gshift;
+};
+
+template <int PM, int NP>
+__device__ __forceinline__ void run_multi(const MultiArgs& a) {
+  constexpr int UM = 0, MODE = 0;
+  constexpr int XW = Shape<PM, UM>::XW, TTW = Shape<PM, UM>::TTW;
+  using Regs = SlotRegs<XW, TTW>;
+  const pbn_plan_header* H = reinterpret_cast<const pbn_plan_header*>(a.blob);
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t n = H->n, njobs = H->n_jobs, S = H->n_slots, zero_pos = H->zero_pos;
+  const uint32_t K = a.K, nvalid = a.nvalid, kj = K * njobs;
+  FnFmt fm;
+  fm.units = H->fn_units;
+  fm.jshift = H->fn_jshift;
+  fm.hoff = H->fn_hoff;
+  fm.zp2 = zero_pos | (zero_pos << 16);
+  fm.var = H->fn_var;
+  fm.sh = a.gshift;
+  const uint32_t sbytes = 4u * ((H->state_dwords + 3u) & ~3u);   // one trajectory's buffer, 16-byte multiple
+  uint8_t* sb = a.wb;
+  uint8_t* spare = a.wb + K * sbytes;
+  uint4* ring = reinterpret_cast<uint4*>(a.wb + K * sbytes + 16u);
+  const uint32_t* blk = reinterpret_cast<const uint32_t*>(a.blob + H->blk_off);
+  const uint8_t* img = a.img;
+  const unsigned long long* Q = reinterpret_cast<const unsigned long long*>(img + H->q_img);
+  const uint32_t* o2p = reinterpret_cast<const uint32_t*>(img + H->o2p_img);
+  const uint32_t k0 = uint32_t(a.seed), k1 = uint32_t(a.seed >> 32);
+
+  // unpack the packed states (bit b = state byte b); absent trajectories: zeros
+  const uint32_t W = H->state_words;
+  for (uint32_t j = 0; j < K; ++j) {
+    uint32_t* buf = reinterpret_cast<uint32_t*>(sb + j * sbytes);
+    const uint32_t* gst = a.state + size_t(a.tl0 + j) * W;
+    for (uint32_t w = lane; w < W; w += 64u) {
+      const uint32_t word = j < nvalid ? gst[w] : 0u;
+#pragma unroll
+      for (uint32_t i = 0; i < 8u; ++i) buf[8u * w + i] = (((word >> (4u * i)) & 0xFu) * 0x204081u) & 0x01010101u;
+    }
+  }
+
+  // this lane's virtual slot in each pass: slot data held for the launch
+  Regs cached[NP];
+  NegThr nthr[NP];
+  uint32_t sbase[NP], tj[NP];   // byte offset of the slot's trajectory buffer; that trajectory
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const uint32_t v = uint32_t(p) * 64u + lane;
+    if (v < K * S) {
+      const uint32_t j = v / S;
+      load_slot<PM, UM, MODE>(cached[p], img, v - j * S, fm);
+      cached[p].draw += j * njobs * 16u;   // the trajectory's drawn words within a step's segment
+      sbase[p] = j * sbytes;
+      tj[p] = j;
+    } else {
+      // no slot: predictor 0 of the dummy record (parents = the zero word,
+      // table 0) writes 0 into the zero word of trajectory 0's buffer
+      cached[p] = Regs{};
+      cached[p].base = H->dummy_fn;
+      cached[p].draw = 1u << 24;
+      cached[p].thr0 = cached[p].thr1 = cached[p].thr2 = 0xFFFFFFFFu;
+      cached[p].spos = zero_pos;
+#pragma unroll
+      for (int k = 0; k < XW; ++k) cached[p].pw[k] = fm.zp2;
+      sbase[p] = 0u;
+      tj[p] = 0u;
+    }
+    nthr[p] = neg_thresholds(cached[p].thr0, cached[p].thr1, cached[p].thr2, cached[p].draw >> 24);
+  }
+
+  // targets.  From the pass ballots: lane q = t K + j keeps, per pass, the
+  // bits of target t's pairs in trajectory j (care) and those that must be 1
+  // (want).  From a state buffer (perturbed trajectories): lane k reads pair
+  // k, lane t tests target t.
+  const uint32_t npairs = a.tg->npairs, ntg = a.tg->ntargets;
+  const uint32_t qt = lane / K, qj = lane - qt * K;
+  const bool qlive = qt < ntg;
+  const uint32_t my_pos = lane < npairs ? a.tg->pos[lane] : zero_pos;
+  const uint32_t my_val = lane < npairs ? a.tg->val[lane] : 0u;
+  const unsigned long long my_mask = lane < ntg ? a.tg->mask[lane] : 0ull;
+  uint32_t want_lo[NP], want_hi[NP], care_lo[NP], care_hi[NP];
+  bool never = false;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) want_lo[p] = want_hi[p] = care_lo[p] = care_hi[p] = 0u;
+  if (qlive) {
+    for (unsigned long long m = a.tg->mask[qt]; m; m &= m - 1ull) {
+      const uint32_t k = uint32_t(__builtin_ctzll(m));
+      const uint32_t pos = a.tg->pos[k], val = a.tg->val[k];
+      if (pos >= S) {   // a removed node: reads the zero word
+        if (val) never = true;
+        continue;
+      }
+      const uint32_t v = qj * S + pos;
+      const uint32_t bit = 1u << (v & 31u), hi = (v >> 5) & 1u;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        if ((v >> 6) == uint32_t(p)) {
+          care_lo[p] |= hi ? 0u : bit;
+          care_hi[p] |= hi ? bit : 0u;
+          if (val) {
+            want_lo[p] |= hi ? 0u : bit;
+            want_hi[p] |= hi ? bit : 0u;
+          }
+        }
+      }
+    }
+  }
+  // target bits (bit t) of one trajectory's buffer
+  auto target_bits = [&](const uint8_t* s) -> unsigned long long {
+    const unsigned long long mism = __ballot(s[my_pos] != my_val);   // lanes past npairs read the zero word
+    return __ballot(lane < ntg && (mism & my_mask) == 0ull);
+  };
+  wave_sync();
+
+  // a fill of `fill` steps: call lane + 64 r is job (c mod kj) mod n_jobs of
+  // trajectory (c mod kj) / n_jobs at step c / kj
+  const uint32_t bsteps = a.fill;
+  uint32_t my_s[kFillRounds], my_j[kFillRounds], my_c2[kFillRounds], my_c3[kFillRounds];
+#pragma unroll
+  for (int r = 0; r < kFillRounds; ++r) {
+    const uint32_t idx = lane + 64u * uint32_t(r);
+    const uint32_t st = idx / kj, rem = idx - st * kj, j = rem / njobs, job = rem - j * njobs;
+    my_s[r] = st;
+    my_j[r] = j;
+    my_c2[r] = job ? blk[job - 1u] : 0u;
+    my_c3[r] = job ? PBN_STREAM_SEL : PBN_STREAM_PERT;
+  }
+  uint32_t stride0 = 1;
+  while (stride0 * 64u < n) stride0 *= 64u;
+  const unsigned long long Qn = Q[n];
+  const uint32_t qn_lo = uint32_t(Qn), qn_hi = uint32_t(Qn >> 32);
+  const uint32_t kmask = (1u << K) - 1u, vmask = (1u << nvalid) - 1u;
+
+  // indicators, as in the one-trajectory kernel, on lane q
+  uint32_t zlast;
+  {
+    uint32_t z0 = 0u;
+    for (uint32_t j = 0; j < K; ++j) {
+      const unsigned long long b = target_bits(sb + j * sbytes);
+      if (qj == j) z0 = uint32_t(b >> qt) & 1u;
+    }
+    zlast = z0;
+  }
+  uint32_t zacc = 0, nacc = 0, hits = 0, n01 = 0, n10 = 0;
+  uint32_t t = a.step0, tacc = t;
+  auto low_bits = [](long long m) -> uint32_t { return m <= 0 ? 0u : m >= 32 ? 0xFFFFFFFFu : (1u << m) - 1u; };
+  auto fold = [&]() {
+    if (nacc == 0u) return;
+    const long long newest = (long long)tacc + nacc - 1;
+    const uint32_t keep = low_bits(nacc);
+    const uint32_t hm = low_bits(newest - (long long)a.count_from + 1) & keep;
+    const uint32_t tm = low_bits(newest - (long long)a.count_from) & keep;
+    const uint32_t prev = (zacc >> 1) | (zlast << (nacc - 1u));
+    hits += __popc(zacc & hm);
+    n01 += __popc(~prev & zacc & tm);
+    n10 += __popc(prev & ~zacc & tm);
+    zlast = zacc & 1u;
+    zacc = 0u;
+    tacc += nacc;
+    nacc = 0u;
+  };
+
+  const uint32_t tend = a.step0 + a.nsteps;
+  while (t < tend) {
+    const uint32_t scount = min(bsteps, tend - t);
+    if (nacc + scount > 32u) fold();
+#pragma unroll
+    for (int r = 0; r < kFillRounds; ++r)
+      if (lane + 64u * uint32_t(r) < scount * kj)
+        ring[lane + 64u * uint32_t(r)] = philox(a.traj0 + my_j[r], t + my_s[r], my_c2[r], my_c3[r], k0, k1);
+    wave_sync();
+    // bit s K + j: trajectory j is perturbed in step s of the fill
+    bool pert = false;
+    if (lane < scount * K) {
+      const uint32_t st = lane / K, j = lane - st * K;
+      const uint2 pr = *reinterpret_cast<const uint2*>(ring + st * kj + j * njobs);
+      pert = j < nvalid && (pr.y > qn_hi || (pr.y == qn_hi && pr.x >= qn_lo));
+    }
+    const unsigned long long pmask = __ballot(pert);
+    for (uint32_t s = 0; s < scount; ++s, ++t) {
+      const uint8_t* rs = reinterpret_cast<const uint8_t*>(ring + s * kj);
+      const uint32_t pb = uint32_t(pmask >> (s * K)) & kmask;
+      bool z = false;
+      if (pb != vmask) {
+        // every pass reads s(t) before any writes s(t+1)
+        uint32_t out[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) out[p] = eval_fn_all<PM, UM, MODE>(cached[p], nthr[p], img, sb + sbase[p], rs, fm);
+        uint32_t mism = 0u;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          const unsigned long long b = __ballot(out[p] != 0u);
+          mism |= masked_xor(uint32_t(b), care_lo[p], want_lo[p]) | masked_xor(uint32_t(b >> 32), care_hi[p], want_hi[p]);
+          uint8_t* dst = ((pb >> tj[p]) & 1u) ? spare : sb + sbase[p] + cached[p].spos;
+          *dst = uint8_t(out[p]);
+        }
+        z = !never && mism == 0u;
+        wave_sync();
+      }
+      for (uint32_t m = pb; m; m &= m - 1u) {
+        // perturbation-only step of trajectory j (Eq. 1): its chain, then its targets
+        const uint32_t j = uint32_t(__builtin_ctz(m));
+        const uint2 pr = *reinterpret_cast<const uint2*>(rs + j * njobs * 16u);
+        unsigned long long unused = 0ull;
+        walk_chain<false, false>((static_cast<unsigned long long>(uniform(pr.y)) << 32) | uniform(pr.x), n, stride0,
+                                 Q, o2p, a.traj0 + j, t, k0, k1, lane, sb + j * sbytes, unused);
+        wave_sync();
+        const unsigned long long b = target_bits(sb + j * sbytes);
+        if (qj == j) z = ((b >> qt) & 1ull) != 0ull;
+      }
+      zacc = zacc + zacc + (z ? 1u : 0u);
+      ++nacc;
+    }
+    wave_sync();
+  }
+  fold();
+
+  if (qlive && qj < nvalid) {
+    unsigned long long* c = a.counts + (size_t(qt) * a.ntraj + a.tl0 + qj) * 3u;
+    c[0] += hits;
+    c[1] += n01;
+    c[2] += n10;
+  }
+  for (uint32_t j = 0; j < nvalid; ++j) {
+    const uint32_t* fs = reinterpret_cast<const uint32_t*>(sb + j * sbytes);
+    uint32_t* gst = a.state + size_t(a.tl0 + j) * W;
+    for (uint32_t w = lane; w < W; w += 64u) {
+      uint32_t word = 0;
+#pragma unroll
+      for (uint32_t i = 0; i < 8u; ++i) {
+        const uint32_t v = fs[8u * w + i];
+        const uint32_t nib = (v & 1u) | ((v >> 7) & 2u) | ((v >> 14) & 4u) | ((v >> 21) & 8u);
+        word |= nib << (4u * i);
+      }
+      gst[w] = word;
+    }
+  }
+}
+
 // One network: one wavefront per trajectory, the plan image staged in LDS when
 // it fits (IMG_LDS), shared by the workgroup's waves.  ALIAS: the plan's alias
 // sampling draws.
@@ -945,6 +1220,45 @@ __global__ void __launch_bounds__(1024) k_simulate(SimParams a) {
   t.record_words = a.record_words;
   t.gshift = a.gshift;
   run_traj<PM, UM, NREG, (ALIAS ? 4 : 0) | (REGSTATE ? 8 : 0)>(t);
+}
+
+// One network, K = a.tpw trajectories per wavefront (run_multi); NP lane
+// passes.  Trajectories tl0 .. tl0 + K - 1 of wave w, tl0 = K w.
+template <bool IMG_LDS, int PM, int NP>
+__global__ void __launch_bounds__(1024) k_simulate_multi(SimParams a) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  const pbn_plan_header* H = reinterpret_cast<const pbn_plan_header*>(a.blob);
+  const uint32_t wave = uniform(threadIdx.x >> 6);
+  const uint32_t img_bytes = H->image_bytes;
+  const uint8_t* gimg = a.blob + H->image_off;
+  uint32_t img_lds = 0;
+  if constexpr (IMG_LDS) {
+    for (uint32_t o = threadIdx.x * 16u; o < img_bytes; o += blockDim.x * 16u)
+      *reinterpret_cast<uint4*>(smem + o) = *reinterpret_cast<const uint4*>(gimg + o);
+    img_lds = (img_bytes + 15u) & ~15u;
+  }
+  __syncthreads();
+  const uint32_t tl0 = (blockIdx.x * a.wpb + wave) * a.tpw;
+  if (tl0 >= a.ntraj) return;
+  MultiArgs m;
+  m.blob = a.blob;
+  m.img = IMG_LDS ? smem : gimg;
+  m.wb = smem + img_lds + wave * a.wave_bytes;
+  m.seed = a.seed;
+  m.traj0 = a.traj0 + tl0;
+  m.tl0 = tl0;
+  m.nvalid = min(a.tpw, a.ntraj - tl0);
+  m.K = a.tpw;
+  m.fill = a.mfill;
+  m.ntraj = a.ntraj;
+  m.step0 = a.step0;
+  m.nsteps = a.nsteps;
+  m.count_from = a.count_from;
+  m.state = a.state;
+  m.counts = a.counts;
+  m.tg = &a.tg;
+  m.gshift = a.gshift;
+  run_multi<PM, NP>(m);
 }
 
 // ---------------------------------------------------------------- batches
@@ -1184,6 +1498,47 @@ pbn_status dispatch_pm(const SimParams& p, uint32_t pmax, uint32_t umax, uint32_
   return dispatch_um<IMG_LDS, 7, ALIAS>(p, umax, npass, reg, blocks, lds, s);
 }
 
+template <bool IMG_LDS, int PM, int NP>
+pbn_status launch_multi(const SimParams& p, uint32_t blocks, uint32_t lds, hipStream_t stream) {
+  auto* fn = k_simulate_multi<IMG_LDS, PM, NP>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       int(kLdsMax));
+    if (e != hipSuccess) return hip_check(e, "hipFuncSetAttribute");
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(fn, dim3(blocks), dim3(64u * p.wpb), lds, stream, p);
+  return hip_check(hipGetLastError(), "k_simulate_multi launch");
+}
+
+template <bool IMG_LDS, int PM>
+pbn_status dispatch_multi_np(const SimParams& p, uint32_t np, uint32_t blocks, uint32_t lds, hipStream_t s) {
+  switch (np) {
+    case 1: return launch_multi<IMG_LDS, PM, 1>(p, blocks, lds, s);
+    case 2: return launch_multi<IMG_LDS, PM, 2>(p, blocks, lds, s);
+    case 3: return launch_multi<IMG_LDS, PM, 3>(p, blocks, lds, s);
+    default: return launch_multi<IMG_LDS, PM, 4>(p, blocks, lds, s);
+  }
+}
+
+// Steps per Philox fill with K trajectories per wave: the f <= 32 with
+// f K n_jobs <= 4 x 64 calls and f K <= 64 whose calls use the largest share
+// of their rounds of 64 lanes (ties: the larger f).
+uint32_t multi_fill_steps(uint32_t njobs, uint32_t K) {
+  uint32_t best = 1;
+  double best_use = 0.0;
+  for (uint32_t f = 1; f <= 32 && f * K * njobs <= uint32_t(kFillRounds) * 64u && f * K <= 64u; ++f) {
+    const uint32_t calls = f * K * njobs, rounds = (calls + 63u) / 64u;
+    const double use = double(calls) / double(rounds * 64u);
+    if (use >= best_use - 1e-12) {
+      best = f;
+      best_use = use;
+    }
+  }
+  return best;
+}
+
 pbn_status simulate_common(bool plain, const pbn_plan* plan, const void* d_plan, uint64_t seed, uint32_t traj0,
                            uint32_t ntraj, uint32_t step0, uint32_t nsteps, uint32_t count_from,
                            const pbn_targets* targets, uint32_t* d_state, uint64_t* d_counts,
@@ -1200,7 +1555,19 @@ pbn_status simulate_common(bool plain, const pbn_plan* plan, const void* d_plan,
   if (plain && plan->has_table) return fail(PBN_EINVAL, "the plain kernel needs a plan without table slots");
   if (ntraj == 0 || nsteps == 0) return PBN_OK;
 
-  const uint32_t wave_bytes = wave_lds_bytes(plan, plan->info.n_passes <= 2u);
+  const uint32_t tpw = launch && launch->traj_per_wave > 1u ? launch->traj_per_wave : 1u;
+  if (tpw > 1u) {
+    // several trajectories per wave: FN-only keyed plans of at most 4 passes
+    // of K slot sets, without indicator recording
+    const uint32_t nps = (tpw * plan->info.n_slots + 63u) / 64u;
+    if (tpw > 4u || plan->sampling || plan->info.max_union_bits != 0 || (launch && launch->d_record) ||
+        tpw * plan->n_jobs > 64u || nps > 4u || targets->ntargets * tpw > 64u)
+      return fail(PBN_EINVAL, "traj_per_wave > 1 needs a keyed FN-only plan whose K slot sets fit 4 lane passes, "
+                              "K n_jobs <= 64, K targets <= 64 and no recording (K <= 4)");
+  }
+  const uint32_t mfill = tpw > 1u ? multi_fill_steps(plan->n_jobs, tpw) : 0u;
+  const uint32_t wave_bytes = tpw > 1u ? tpw * 4u * ((plan->state_dwords + 3u) & ~3u) + 16u + 16u * mfill * tpw * plan->n_jobs
+                                       : wave_lds_bytes(plan, plan->info.n_passes <= 2u);
   const bool img_lds = plan->info.image_in_lds != 0;
   const uint32_t img = img_lds ? ((plan->info.image_bytes + 15u) & ~15u) : 0u;
   uint32_t wpb = launch && launch->waves_per_block ? launch->waves_per_block : 4u;
@@ -1223,13 +1590,16 @@ pbn_status simulate_common(bool plain, const pbn_plan* plan, const void* d_plan,
   p.wpb = wpb;
   p.wave_bytes = wave_bytes;
   p.gshift = 1;
+  p.tpw = tpw;
+  p.mfill = mfill;
   p.tg = *targets;
   if (launch && launch->d_record) {
     p.record = launch->d_record;
     p.record_traj = launch->record_traj;
     p.record_words = launch->record_words;
   }
-  const uint32_t blocks = (ntraj + wpb - 1) / wpb;
+  const uint32_t waves = (ntraj + tpw - 1) / tpw;
+  const uint32_t blocks = (waves + wpb - 1) / wpb;
   const uint32_t lds = img + wpb * wave_bytes;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const uint32_t pmax = plan->info.max_fn_parents, umax = plan->info.max_union_bits;
@@ -1237,6 +1607,12 @@ pbn_status simulate_common(bool plain, const pbn_plan* plan, const void* d_plan,
   if (pmax > 7 || umax > 16) return fail(PBN_ELDS, "plan exceeds the kernel's gather widths");
   const uint32_t units = reinterpret_cast<const pbn_plan_header*>(plan->blob.data())->fn_units;
   if (units != (pmax > 5 ? 2u : 1u)) return fail(PBN_EINVAL, "plan FN record format does not match its parent count");
+  if (tpw > 1u) {
+    const uint32_t nps = (tpw * plan->info.n_slots + 63u) / 64u;
+    if (pmax <= 5)
+      return img_lds ? dispatch_multi_np<true, 5>(p, nps, blocks, lds, s) : dispatch_multi_np<false, 5>(p, nps, blocks, lds, s);
+    return img_lds ? dispatch_multi_np<true, 7>(p, nps, blocks, lds, s) : dispatch_multi_np<false, 7>(p, nps, blocks, lds, s);
+  }
   // one-pass FN-only keyed plans whose slot bytes and zero word lie below 64
   // keep the state in a register (padded lanes' bytes, above the zero word,
   // are never read and stay 0)

@@ -63,6 +63,8 @@ NETS = {
     "sparse120": lambda: sparse_multi(120, 14),
     "c3_slice": lambda: ps.large_c3(n=1500, p=2e-4, seed=15),
     "modules": lambda: ps.with_detached_modules(ps.medium_c2(n=60, p=3e-3, seed=16), 3, 20, seed=17),
+    "wide40": lambda: ps.random_pbn(40, 1e-2, 18, nfn=lambda r: int(r.integers(1, 4)),
+                                    nparents=lambda r: int(r.integers(1, 8)), leaf_frac=0.1),
 }
 
 
@@ -86,28 +88,29 @@ def oracle_run(name, seed, traj0, ntraj, steps, count_from):
                     count_from=count_from)
 
 
-def gpu_run(name, opts, seed, traj0, ntraj, chunks, count_from=0, plain=False, wpb=0):
+def gpu_run(name, opts, seed, traj0, ntraj, chunks, count_from=0, plain=False, wpb=0, tpw=1):
     net = net_of(name)
     tgs = targets_of(net)
     interest = sorted({a for tg in tgs for a, _ in tg})
     plan = api.Plan(net, interest=interest, **opts)
-    say(f"[gpu] {name} opts={opts} info={plan.info} traj={traj0}+{ntraj} chunks={chunks} plain={plain} wpb={wpb}")
+    say(f"[gpu] {name} opts={opts} info={plan.info} traj={traj0}+{ntraj} chunks={chunks} plain={plain} wpb={wpb} "
+        f"tpw={tpw}")
     tg = plan.targets(tgs)
     state = api.state_init(plan, seed, ntraj, traj0=traj0)
     counts = api.new_counts(len(tgs), ntraj)
     step = 0
     for c in chunks:
         api.simulate(plan, seed, state, counts, tg, step, c, traj0=traj0, count_from=count_from,
-                     plain=plain, waves_per_block=wpb)
+                     plain=plain, waves_per_block=wpb, traj_per_wave=tpw)
         step += c
     orig = api.unpack_bits(api.to_original(plan, state).cpu().numpy(), plan.n)
     torch.cuda.synchronize()
     return plan, orig, counts.cpu().numpy(), state.cpu().numpy()
 
 
-def check(name, opts, seed, traj0, ntraj, chunks, count_from=0, plain=False, wpb=0):
+def check(name, opts, seed, traj0, ntraj, chunks, count_from=0, plain=False, wpb=0, tpw=1):
     ref = oracle_run(name, seed, traj0, ntraj, sum(chunks), count_from)
-    plan, orig, counts, _ = gpu_run(name, opts, seed, traj0, ntraj, chunks, count_from, plain, wpb)
+    plan, orig, counts, _ = gpu_run(name, opts, seed, traj0, ntraj, chunks, count_from, plain, wpb, tpw)
     kept = plan.node_pos() != NONE
     bad = np.nonzero((orig[:, kept] != ref["state"][:, kept]).any(axis=1))[0]
     assert bad.size == 0, f"{bad.size} trajectories differ, first {traj0 + bad[0]}"
@@ -264,6 +267,44 @@ def test_autotune_candidates_are_bit_identical(name):
         common = kept & ref[1]
         assert np.array_equal(orig[:, common], ref[0][:, common]), opts
         assert np.array_equal(c, ref[2]), opts
+
+
+MULTI_CASES = [
+    # (network, plan, trajectories per wave, seed, traj0, ntraj, chunks, count_from, plain, wpb)
+    ("c2", "REDUCED", 2, 41, 0, 131, (150, 113), 40, True, 0),      # 170 virtual slots: 3 passes
+    ("c2", "REDUCED", 3, 42, 7, 100, (263,), 0, True, 8),           # 255 of 256 lanes: 4 passes; ragged last wave
+    ("c2", "PLAIN", 2, 43, 0, 64, (90, 90), 5, True, 2),            # 200 virtual slots
+    ("c2_hot", "REDUCED", 2, 44, 0, 61, (120, 80), 30, True, 4),    # two perturbations per step on average
+    ("c2_small", "PLAIN", 4, 45, 3, 50, (200,), 10, True, 4),       # 148 virtual slots in 3 passes
+    ("c2_small", "REDUCED", 4, 46, 0, 7, (90, 90), 0, False, 8),    # 2 passes; fewer trajectories than one wave holds
+    ("modules", "CONE", 4, 47, 0, 90, (160,), 20, True, 4),         # cone plan, 4 passes
+    ("wide40", "REDUCED", 3, 48, 0, 45, (120, 33), 15, True, 4),    # predictors of up to 7 parents
+]
+
+
+@pytest.mark.parametrize("case", MULTI_CASES, ids=lambda c: f"{c[0]}-{c[1]}-k{c[2]}")
+def test_several_trajectories_per_wave_match_the_oracle(case):
+    """Several trajectories sharing a wavefront's lane passes: every kept node
+    and every counter equals the oracle's, whatever the trajectory count, the
+    chunking, the burn-in boundary and the perturbation rate."""
+    name, opts, tpw, seed, traj0, ntraj, chunks, count_from, plain, wpb = case
+    check(name, globals()[opts], seed, traj0, ntraj, chunks, count_from, plain, wpb, tpw)
+
+
+def test_several_trajectories_per_wave_reject_unsupported_plans():
+    net = net_of("c2")
+    tgs = targets_of(net)
+    interest = sorted({a for tg in tgs for a, _ in tg})
+    plan = api.Plan(net, interest=interest, **GROUPED)
+    tg = plan.targets(tgs)
+    state = api.state_init(plan, 1, 8)
+    counts = api.new_counts(len(tgs), 8)
+    with pytest.raises(api._lib.PbnError, match="traj_per_wave"):
+        api.simulate(plan, 1, state, counts, tg, 0, 10, traj_per_wave=2)          # table slots
+    red = api.Plan(net, interest=interest, **REDUCED)
+    state = api.state_init(red, 1, 8)
+    with pytest.raises(api._lib.PbnError, match="traj_per_wave"):
+        api.simulate(red, 1, state, counts, red.targets(tgs), 0, 10, traj_per_wave=4)   # 340 virtual slots
 
 
 def test_full_size_c2_product_configuration():
