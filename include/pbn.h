@@ -163,11 +163,17 @@ typedef struct pbn_plan_opts {
   uint32_t max_parent_bits;
   uint32_t max_group_nodes;
   uint32_t sampling;
+  uint32_t state_bits;  /* 0: one LDS byte per node while simulating; 1: packed
+                           bits (keyed draws only): lane pass p owns a segment of
+                           256 bits (4 per lane) when it holds a table slot, else
+                           64 (1 per lane); the step kernel reads parents as bits
+                           and writes each pass's results as whole words */
+  uint32_t reserved;
 } pbn_plan_opts;
 
 /* Defaults: reduce = 1, group = 1, weight_mode = 1, theta = 65536,
  * lds_budget_bytes = 65536, max_table_entries = 4096, max_parent_bits = 12,
- * max_group_nodes = 4. */
+ * max_group_nodes = 4, sampling = 0, state_bits = 0. */
 void pbn_plan_opts_default(pbn_plan_opts* opts);
 
 pbn_status pbn_plan_build(const pbn_net* net, const uint32_t* interest, uint32_t n_interest,
@@ -529,15 +535,15 @@ pbn_status pbn_graph_destroy(pbn_graph* graph);
  *   2^log2_bytes-byte LDS buffer (7 <= log2_bytes <= 16) per workgroup;
  *   pattern 0: random aligned addresses (bank conflicts as they fall),
  *   pattern 1: the lanes of a wave read bank-distinct words of random rows.
- * pbn_probe_vmem_gather: random 16-byte gathers from the caller's device
- *   buffer of at least 2^log2_bytes bytes (4 <= log2_bytes <= 30) through the
- *   vector L1 and L2.
+ * pbn_probe_vmem_gather: random gathers of `width` bytes (1 or 16) from the
+ *   caller's device buffer of at least 2^log2_bytes bytes (4 <= log2_bytes <=
+ *   30) through the vector L1 and L2.
  * d_sink: one device word, written only by an improbable value (keeps the
  * reads).  Errors: PBN_EINVAL for out-of-range arguments, PBN_EHIP.         */
 pbn_status pbn_probe_lds_gather(uint32_t log2_bytes, uint32_t width, uint32_t pattern, uint32_t iters,
                                 uint32_t blocks, uint32_t* d_sink, void* stream);
-pbn_status pbn_probe_vmem_gather(const void* d_buf, uint32_t log2_bytes, uint32_t iters, uint32_t blocks,
-                                 uint32_t* d_sink, void* stream);
+pbn_status pbn_probe_vmem_gather(const void* d_buf, uint32_t log2_bytes, uint32_t width, uint32_t iters,
+                                 uint32_t blocks, uint32_t* d_sink, void* stream);
 
 #ifdef __cplusplus
 }

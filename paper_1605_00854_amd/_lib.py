@@ -29,7 +29,8 @@ class pbn_plan_opts(C.Structure):
     _fields_ = [("reduce", C.c_uint32), ("group", C.c_uint32), ("weight_mode", C.c_uint32),
                 ("lds_budget_bytes", C.c_uint32), ("theta", C.c_uint64),
                 ("max_table_entries", C.c_uint32), ("max_parent_bits", C.c_uint32),
-                ("max_group_nodes", C.c_uint32), ("sampling", C.c_uint32)]
+                ("max_group_nodes", C.c_uint32), ("sampling", C.c_uint32),
+                ("state_bits", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class pbn_plan_info(C.Structure):
@@ -109,7 +110,7 @@ SIGNATURES = {
     "pbn_batch_launch": (C.c_int32, [C.POINTER(_P), _U32, _P, _P, _P, _U32, _P, _U32, _P]),
     "pbn_batch_launch_noalloc": (C.c_int32, [C.POINTER(_P), _pU32, _U32, _P, _U32, _U32, _U32, _P]),
     "pbn_probe_lds_gather": (C.c_int32, [_U32, _U32, _U32, _U32, _U32, _P, _P]),
-    "pbn_probe_vmem_gather": (C.c_int32, [_P, _U32, _U32, _U32, _P, _P]),
+    "pbn_probe_vmem_gather": (C.c_int32, [_P, _U32, _U32, _U32, _U32, _P, _P]),
     "pbn_batch_graph_create": (C.c_int32, [C.POINTER(_P), _U32, _P, _P, _P, _U32, _P, _U32, _U32,
                                            C.POINTER(_P)]),
     "pbn_graph_launch": (C.c_int32, [_P, _P]),

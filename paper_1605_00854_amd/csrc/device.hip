@@ -230,6 +230,23 @@ __device__ __forceinline__ uint32_t gather_bits(unsigned long long st, const uin
   return idx;
 }
 
+// The same gather from a packed state in LDS (bit b of the state = bit b % 32
+// of word b / 32): one word read per parent, the bit taken by a field extract
+// whose offset is the position's low 5 bits.
+template <int K>
+__device__ __forceinline__ uint32_t gather_lbits(const uint32_t* words, const uint32_t* pw, uint32_t sh) {
+  uint32_t b[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint32_t p = (k & 1) ? (pw[k >> 1] >> 16) : (pw[k >> 1] & 0xFFFFu);
+    b[k] = __builtin_amdgcn_ubfe(words[p >> 5], p & 31u, 1u);
+  }
+  uint32_t idx = b[K - 1];
+#pragma unroll
+  for (int k = K - 2; k >= 0; --k) idx = shl_or(idx, b[k], sh);
+  return idx;
+}
+
 __device__ __forceinline__ uint32_t choose(uint32_t w, uint32_t t0, uint32_t t1, uint32_t t2, uint32_t nfn) {
   const uint32_t j = uint32_t(w >= t0) + uint32_t(w >= t1) + uint32_t(w >= t2);
   return min(j, nfn - 1u);
@@ -298,7 +315,7 @@ __device__ __forceinline__ FnRec<Shape<PM, UM>::PW, Shape<PM, UM>::TTW> load_fn(
   const bool two = fm.var ? PBN_SLOT_NU(info) > 5u : (!MIXED || fm.units == 2u);
   const uint32_t jshift = fm.var ? (two ? 5u : 4u) : fm.jshift;
   // records and units are 16-byte aligned: one 16-byte read per unit
-  const uint8_t* rp = static_cast<const uint8_t*>(__builtin_assume_aligned(img + base + (j << jshift), 16));
+  const uint8_t* rp = static_cast<const uint8_t*>(__builtin_assume_aligned(img + (base + (j << jshift)), 16));
   const uint4 a = img_u4<G>(rp);
   r.pw[0] = a.x;
   r.pw[1] = a.y;
@@ -324,13 +341,15 @@ __device__ __forceinline__ FnRec<Shape<PM, UM>::PW, Shape<PM, UM>::TTW> load_fn(
 
 // Look up an FN record's truth table over its parents in state `cs` (bytes in
 // LDS) or, with REG, in the 64-bit state `st`.
-template <int PM, int UM, bool REG = false>
+template <int PM, int UM, bool REG = false, bool LBITS = false>
 __device__ __forceinline__ uint32_t eval_fn(const FnRec<Shape<PM, UM>::PW, Shape<PM, UM>::TTW>& r, const uint8_t* cs,
                                             uint32_t sh, unsigned long long st = 0ull) {
   constexpr int TTW = Shape<PM, UM>::TTW;
   uint32_t idx;
   if constexpr (REG)
     idx = gather_bits<PM>(st, r.pw, sh);
+  else if constexpr (LBITS)
+    idx = gather_lbits<PM>(reinterpret_cast<const uint32_t*>(cs), r.pw, sh);
   else
     idx = gather<PM>(cs, r.pw, sh);
   uint32_t ttw = r.tt[0];
@@ -375,7 +394,7 @@ __device__ __forceinline__ void load_slot(SlotRegs<Shape<PM, UM>::XW, Shape<PM, 
       for (int k = 3; k < UW; ++k) r.pw[k] = fm.zp2;
     } else {
 #pragma unroll
-      for (int k = 0; k < UW; ++k) r.pw[k] = img_u32<G>(img + rec.y + 4u * k);
+      for (int k = 0; k < UW; ++k) r.pw[k] = img_u32<G>(img + (rec.y + 4u * k));
     }
   } else {
     r.spos = rec.w;   // FN slot or padded lane: its state byte
@@ -412,12 +431,16 @@ __device__ __forceinline__ uint32_t eval_table(const SlotRegs<Shape<PM, UM>::XW,
       c = alias_pick<G>(img + r.choice + 16u, *reinterpret_cast<const uint32_t*>(rs + hd.x), hd.y);
     }
   } else for (uint32_t m = 0; m < nm; ++m) {
-    const uint4 ch = img_u4<G>(img + r.choice + 16u * m);
+    const uint4 ch = img_u4<G>(img + (r.choice + 16u * m));
     const uint32_t w = *reinterpret_cast<const uint32_t*>(rs + (ch.x & 0xFFFFFFu));
     c += choose(w, ch.y, ch.z, ch.w, ch.x >> 24) * ((r.radix >> (8u * m)) & 0xFFu);
   }
-  const uint32_t x = gather<(UM > 0 ? UM : 1)>(cs, r.pw, sh);
-  const uint32_t v = img_u8<G>(img + r.base + 32u + (c << PBN_SLOT_NU(r.info)) + x);
+  uint32_t x;
+  if constexpr ((MODE & 16) != 0)
+    x = gather_lbits<(UM > 0 ? UM : 1)>(reinterpret_cast<const uint32_t*>(cs), r.pw, sh);
+  else
+    x = gather<(UM > 0 ? UM : 1)>(cs, r.pw, sh);
+  const uint32_t v = img_u8<G>(img + (r.base + 32u + (c << PBN_SLOT_NU(r.info)) + x));
   return v;   // member k's output in bit k
 }
 
@@ -444,7 +467,59 @@ __device__ __forceinline__ uint32_t eval_slot(const SlotRegs<Shape<PM, UM>::XW, 
       j = nt ? choose_neg(w, *nt) : choose(w, r.thr0, r.thr1, r.thr2, r.draw >> 24);
     f = load_fn<PM, UM, MODE>(img, r.base, j, fm, r.info);
   }
-  return eval_fn<PM, UM>(f, cs, fm.sh);
+  return eval_fn<PM, UM, false, (MODE & 16) != 0>(f, cs, fm.sh);
+}
+
+// One slot of a plan whose slot data are read from the image every pass:
+// the slot record, then only what the slot's kind needs (a table slot's union
+// positions and choice records, a multi-predictor node's choice record and
+// chosen predictor record, a one-predictor node's record); returns the
+// slot's output (member k in bit k) and the state position it writes.
+template <int PM, int UM, int MODE>
+__device__ __forceinline__ uint32_t eval_stream(const uint8_t* img, uint32_t slot, const uint8_t* cs, const uint8_t* rs,
+                                                const FnFmt& fm, uint32_t& spos, bool& table) {
+  constexpr int PW = Shape<PM, UM>::PW, TTW = Shape<PM, UM>::TTW, UW = Shape<PM, UM>::UW;
+  constexpr bool G = (MODE & 2) != 0, LB = (MODE & 16) != 0;
+  const uint4 rec = img_u4<G>(img + 16u * slot);
+  table = UM > 0 && (rec.x & PBN_SLOT_TABLE);
+  if (UM > 0 && (rec.x & PBN_SLOT_TABLE)) {
+    spos = 4u * slot;
+    uint32_t pw[UW];
+    uint32_t c = 0;
+    if (rec.x & PBN_SLOT_INLINE) {
+      pw[0] = rec.z;
+      if constexpr (UW > 1) pw[1] = rec.w;
+      if constexpr (UW > 2) pw[2] = PBN_SLOT_P4(rec.x) | (fm.zp2 & 0xFFFF0000u);
+#pragma unroll
+      for (int k = 3; k < UW; ++k) pw[k] = fm.zp2;
+    } else {
+#pragma unroll
+      for (int k = 0; k < UW; ++k) pw[k] = img_u32<G>(img + (rec.y + 4u * k));
+      const uint32_t nm = PBN_SLOT_NMULTI(rec.x);
+      for (uint32_t m = 0; m < nm; ++m) {
+        const uint4 ch = img_u4<G>(img + (rec.z + 16u * m));
+        const uint32_t w = *reinterpret_cast<const uint32_t*>(rs + (ch.x & 0xFFFFFFu));
+        c += choose(w, ch.y, ch.z, ch.w, ch.x >> 24) * ((rec.w >> (8u * m)) & 0xFFu);
+      }
+    }
+    uint32_t x;
+    if constexpr (LB)
+      x = gather_lbits<(UM > 0 ? UM : 1)>(reinterpret_cast<const uint32_t*>(cs), pw, fm.sh);
+    else
+      x = gather<(UM > 0 ? UM : 1)>(cs, pw, fm.sh);
+    return img_u8<G>(img + (rec.y + 32u + (c << PBN_SLOT_NU(rec.x)) + x));
+  }
+  spos = rec.w;   // FN slot or padded lane: its state position
+  uint32_t j = 0;
+  if (PBN_SLOT_NMULTI(rec.x)) {
+    const uint4 ch = img_u4<G>(img + rec.z);
+    const uint32_t w = *reinterpret_cast<const uint32_t*>(rs + (ch.x & 0xFFFFFFu));
+    j = choose(w, ch.y, ch.z, ch.w, ch.x >> 24);
+  }
+  const auto f = load_fn<PM, UM, MODE>(img, rec.y, j, fm, rec.x);
+  (void)PW;
+  (void)TTW;
+  return eval_fn<PM, UM, false, LB>(f, cs, fm.sh);
 }
 
 // FN-only plans with slot data held in registers: every lane reads the record
@@ -466,20 +541,20 @@ __device__ __forceinline__ uint32_t eval_fn_all(const SlotRegs<Shape<PM, UM>::XW
 template <int UM>
 __device__ __forceinline__ void store_slot(uint8_t* ns, uint32_t info, uint32_t spos, uint32_t out) {
   if (UM > 0 && (info & PBN_SLOT_TABLE))
-    *reinterpret_cast<uint32_t*>(ns + spos) = (out * 0x204081u) & 0x01010101u;   // bit k -> byte k
+    *reinterpret_cast<uint32_t*>(ns + spos) = __umul24(out, 0x204081u) & 0x01010101u;   // bit k -> byte k
   else
     ns[spos] = uint8_t(out);
 }
 
 // A perturbation-only step (u >= Q[n], Eq. 1): walk the skip chain over all
 // n original nodes of one trajectory, starting from its first drawn word u,
-// and flip the kept nodes (bytes of `csb`, or bits of the wave-uniform word
-// `rst` with REG).  Each draw counts the unperturbed nodes before the next
+// and flip the kept nodes (bytes of `csb`, bits of the wave-uniform word
+// `rst` with REG, or bits of the packed words at `csb` with LBITS).  Each draw counts the unperturbed nodes before the next
 // perturbed one with ballots over Q (radix 64).  The chain's later draws are
 // computed 64 at a time, one per lane (indices sbase .. sbase + 63), when the
 // walk goes past them; a walk that flips again within them reads its next
 // word with one lane read.  All lanes of the wave take part.
-template <bool G, bool REG>
+template <bool G, bool REG, bool LBITS = false>
 __device__ __forceinline__ void walk_chain(unsigned long long u, uint32_t n, uint32_t stride0,
                                            const unsigned long long* Q, const uint32_t* o2p, uint32_t traj, uint32_t t,
                                            uint32_t k0, uint32_t k1, uint32_t lane, uint8_t* csb,
@@ -501,6 +576,8 @@ __device__ __forceinline__ void walk_chain(unsigned long long u, uint32_t n, uin
     const uint32_t pos = blob_u32<G>(o2p + i);
     if constexpr (REG) {
       if (pos != PBN_NONE) rst ^= 1ull << uniform(pos);
+    } else if constexpr (LBITS) {
+      if (pos != PBN_NONE && lane == 0) reinterpret_cast<uint32_t*>(csb)[pos >> 5] ^= 1u << (pos & 31u);
     } else if (pos != PBN_NONE && lane == 0) {
       csb[pos] ^= 1u;
     }
@@ -878,9 +955,16 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
           }
         } else {
           for (uint32_t p = 0; p < npass; ++p) {
-            Regs r;
-            load_slot<PM, UM, MODE>(r, img, p * 64u + lane, fm);
-            store_slot<UM>(nsb, r.info, r.spos, eval_slot<PM, UM, MODE>(r, nullptr, img, csb, rs, fm));
+            if constexpr (ALIAS) {
+              Regs r;
+              load_slot<PM, UM, MODE>(r, img, p * 64u + lane, fm);
+              store_slot<UM>(nsb, r.info, r.spos, eval_slot<PM, UM, MODE>(r, nullptr, img, csb, rs, fm));
+            } else {
+              uint32_t spos;
+              bool table;
+              const uint32_t out = eval_stream<PM, UM, MODE>(img, p * 64u + lane, csb, rs, fm, spos, table);
+              store_slot<UM>(nsb, table ? PBN_SLOT_TABLE : 0u, spos, out);
+            }
           }
         }
         cur ^= 1u;
@@ -1261,6 +1345,207 @@ __global__ void __launch_bounds__(1024) k_simulate_multi(SimParams a) {
   run_multi<PM, NP>(m);
 }
 
+// Packed-bit state (plans built with state_bits): the trajectory state in LDS
+// is the packed state itself, two buffers of W words per wave (s(t), s(t+1)),
+// about an eighth of the byte layout's LDS, so a workgroup of up to 16 waves
+// keeps a large plan image in LDS beside them.  Parents are read as bits
+// (gather_lbits).  Pass p writes its own segment of s(t+1) as whole words: a
+// table pass (4 bits per lane) ORs the nibbles of 8 lanes with three
+// row-shift DPP steps and every eighth lane stores a word; a pass of FN slots
+// stores its output ballot (two words).  Keyed draws, slot data reloaded
+// every pass (any number of passes); MODE bit 1: global-address-space image
+// reads (not used by k_simulate_bits).
+template <int PM, int UM, int MODE>
+__device__ __forceinline__ void run_bits(const TrajArgs& a) {
+  constexpr int XW = Shape<PM, UM>::XW, TTW = Shape<PM, UM>::TTW;
+  constexpr int M = MODE | 16;   // state as bits
+  using Regs = SlotRegs<XW, TTW>;
+  const pbn_plan_header* H = reinterpret_cast<const pbn_plan_header*>(a.blob);
+  const pbn_pass_info* pinfo = reinterpret_cast<const pbn_pass_info*>(a.blob + H->pass_off);
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t n = H->n, npass = H->n_passes, njobs = H->n_jobs;
+  const uint32_t fill = H->fill_steps, zero_pos = H->zero_pos;
+  FnFmt fm;
+  fm.units = H->fn_units;
+  fm.jshift = H->fn_jshift;
+  fm.hoff = H->fn_hoff;
+  fm.zp2 = zero_pos | (zero_pos << 16);
+  fm.var = H->fn_var;
+  fm.sh = a.gshift;
+  const uint32_t W = H->state_words, Wp = (W + 3u) & ~3u;
+  uint32_t* buf[2] = {reinterpret_cast<uint32_t*>(a.wb), reinterpret_cast<uint32_t*>(a.wb) + Wp};
+  uint4* ring = reinterpret_cast<uint4*>(a.wb + 8u * Wp);
+  const uint32_t* blk = reinterpret_cast<const uint32_t*>(a.blob + H->blk_off);
+  const uint8_t* img = a.img;
+  const unsigned long long* Q = reinterpret_cast<const unsigned long long*>(img + H->q_img);
+  const uint32_t* o2p = reinterpret_cast<const uint32_t*>(img + H->o2p_img);
+  const uint32_t traj = a.traj;
+  const uint32_t k0 = uint32_t(a.seed), k1 = uint32_t(a.seed >> 32);
+
+  uint32_t* gst = a.state + size_t(a.tl) * W;
+  for (uint32_t w = lane; w < Wp; w += 64u) {
+    buf[0][w] = w < W ? gst[w] : 0u;
+    buf[1][w] = 0u;   // the zero word of s(t+1) stays 0: no pass writes it
+  }
+
+  const uint32_t npairs = a.tg->npairs, ntg = a.tg->ntargets;
+  const uint32_t my_pos = lane < npairs ? a.tg->pos[lane] : zero_pos;
+  const uint32_t my_val = lane < npairs ? a.tg->val[lane] : 0u;
+  const unsigned long long my_mask = lane < ntg ? a.tg->mask[lane] : 0ull;
+  auto target_z = [&](const uint32_t* words) -> bool {
+    const uint32_t b = (words[my_pos >> 5] >> (my_pos & 31u)) & 1u;
+    const unsigned long long mism = __ballot(b != my_val);   // lanes past npairs read the zero word
+    return (mism & my_mask) == 0ull;
+  };
+  wave_sync();
+
+  const bool small_jobs = njobs <= 64u;
+  const uint32_t bsteps = small_jobs ? min(fill, 32u) : 1u;
+  uint32_t my_s[kFillRounds], my_c2[kFillRounds], my_c3[kFillRounds];
+#pragma unroll
+  for (int r = 0; r < kFillRounds; ++r) {
+    const uint32_t idx = lane + 64u * uint32_t(r);
+    const uint32_t j = small_jobs ? idx % njobs : 0u;
+    my_s[r] = small_jobs ? idx / njobs : 0u;
+    my_c2[r] = j ? blk[j - 1] : 0u;
+    my_c3[r] = j ? PBN_STREAM_SEL : PBN_STREAM_PERT;
+  }
+  uint32_t stride0 = 1;
+  while (stride0 * 64u < n) stride0 *= 64u;
+  const unsigned long long Qn = Q[n];
+  const uint32_t qn_lo = uint32_t(Qn), qn_hi = uint32_t(Qn >> 32);
+  const uint32_t nib_shift = 4u * (lane & 7u);
+
+  uint32_t cur = 0;
+  uint32_t zlast = target_z(buf[0]) ? 1u : 0u;
+  uint32_t zacc = 0, nacc = 0, hits = 0, n01 = 0, n10 = 0;
+  uint32_t t = a.step0, tacc = t;
+  auto low_bits = [](long long m) -> uint32_t { return m <= 0 ? 0u : m >= 32 ? 0xFFFFFFFFu : (1u << m) - 1u; };
+  auto fold = [&]() {
+    if (nacc == 0u) return;
+    const long long newest = (long long)tacc + nacc - 1;
+    const uint32_t keep = low_bits(nacc);
+    const uint32_t hm = low_bits(newest - (long long)a.count_from + 1) & keep;
+    const uint32_t tm = low_bits(newest - (long long)a.count_from) & keep;
+    const uint32_t prev = (zacc >> 1) | (zlast << (nacc - 1u));
+    hits += __popc(zacc & hm);
+    n01 += __popc(~prev & zacc & tm);
+    n10 += __popc(prev & ~zacc & tm);
+    zlast = zacc & 1u;
+    zacc = 0u;
+    tacc += nacc;
+    nacc = 0u;
+  };
+
+  const uint32_t tend = a.step0 + a.nsteps;
+  while (t < tend) {
+    const uint32_t scount = small_jobs ? min(bsteps, tend - t) : 1u;
+    if (nacc + scount > 32u) fold();
+    if (small_jobs) {
+#pragma unroll
+      for (int r = 0; r < kFillRounds; ++r)
+        if (lane + 64u * uint32_t(r) < scount * njobs)
+          ring[lane + 64u * uint32_t(r)] = philox(traj, t + my_s[r], my_c2[r], my_c3[r], k0, k1);
+    } else {
+      for (uint32_t j = lane; j < njobs; j += 64u)
+        ring[j] = philox(traj, t, j ? blk[j - 1] : 0u, j ? PBN_STREAM_SEL : PBN_STREAM_PERT, k0, k1);
+    }
+    wave_sync();
+    for (uint32_t s = 0; s < scount; ++s, ++t) {
+      const uint8_t* rs = reinterpret_cast<const uint8_t*>(ring + s * njobs);
+      const uint2 pr = *reinterpret_cast<const uint2*>(rs);
+      const uint32_t ulo = uniform(pr.x), uhi = uniform(pr.y);
+      uint32_t* cw = buf[cur];
+      bool z;
+      if (uhi > qn_hi || (uhi == qn_hi && ulo >= qn_lo)) {
+        // perturbation-only step: flip the perturbed kept nodes' bits in place
+        unsigned long long unused = 0ull;
+        walk_chain<(MODE & 2) != 0, false, true>((static_cast<unsigned long long>(uhi) << 32) | ulo, n, stride0, Q,
+                                                 o2p, traj, t, k0, k1, lane, reinterpret_cast<uint8_t*>(cw), unused);
+        wave_sync();
+        z = target_z(cw);
+      } else {
+        uint32_t* nw = buf[cur ^ 1u];
+        uint32_t seg = 0;   // word offset of pass p's segment
+        for (uint32_t p = 0; p < npass; ++p) {
+          const uint32_t flags = uniform(pinfo[p].flags);
+          uint32_t spos;
+          bool table;
+          const uint32_t out = eval_stream<PM, UM, M>(img, p * 64u + lane, reinterpret_cast<const uint8_t*>(cw), rs, fm,
+                                                      spos, table);
+          if (flags & PBN_PASS_TABLE) {
+            // lane L's nibble at bits 4 (L mod 8) of word L / 8 of the segment
+            uint32_t v = out << nib_shift;
+            v |= __builtin_amdgcn_update_dpp(0u, v, 0x111, 0xF, 0xF, true);   // row_shr:1
+            v |= __builtin_amdgcn_update_dpp(0u, v, 0x112, 0xF, 0xF, true);   // row_shr:2
+            v |= __builtin_amdgcn_update_dpp(0u, v, 0x114, 0xF, 0xF, true);   // row_shr:4
+            if ((lane & 7u) == 7u) nw[seg + (lane >> 3)] = v;
+            seg += 8u;
+          } else {
+            const unsigned long long b = __ballot(out != 0u);
+            if (lane < 2u) nw[seg + lane] = lane ? uint32_t(b >> 32) : uint32_t(b);
+            seg += 2u;
+          }
+        }
+        cur ^= 1u;
+        wave_sync();
+        z = target_z(nw);
+      }
+      zacc = zacc + zacc + (z ? 1u : 0u);
+      ++nacc;
+    }
+    wave_sync();
+  }
+  fold();
+
+  if (lane < ntg) {
+    unsigned long long* c = a.counts + (size_t(lane) * a.ntraj + a.tl) * 3u;
+    c[0] += hits;
+    c[1] += n01;
+    c[2] += n10;
+  }
+  for (uint32_t w = lane; w < W; w += 64u) gst[w] = buf[cur][w];
+}
+
+// One network with a packed-bit state (run_bits): one wavefront per
+// trajectory, the plan image staged in LDS when it fits beside the waves'
+// states and rings.
+template <bool IMG_LDS, int PM, int UM>
+__global__ void __launch_bounds__(1024) k_simulate_bits(SimParams a) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  const pbn_plan_header* H = reinterpret_cast<const pbn_plan_header*>(a.blob);
+  const uint32_t wave = uniform(threadIdx.x >> 6);
+  const uint32_t img_bytes = H->image_bytes;
+  const uint8_t* gimg = a.blob + H->image_off;
+  uint32_t img_lds = 0;
+  if constexpr (IMG_LDS) {
+    for (uint32_t o = threadIdx.x * 16u; o < img_bytes; o += blockDim.x * 16u)
+      *reinterpret_cast<uint4*>(smem + o) = *reinterpret_cast<const uint4*>(gimg + o);
+    img_lds = (img_bytes + 15u) & ~15u;
+  }
+  __syncthreads();
+  const uint32_t tl = blockIdx.x * a.wpb + wave;
+  if (tl >= a.ntraj) return;
+  TrajArgs t;
+  t.blob = a.blob;
+  t.img = IMG_LDS ? smem : gimg;
+  t.wb = smem + img_lds + wave * a.wave_bytes;
+  t.seed = a.seed;
+  t.traj = a.traj0 + tl;
+  t.tl = tl;
+  t.ntraj = a.ntraj;
+  t.step0 = a.step0;
+  t.nsteps = a.nsteps;
+  t.count_from = a.count_from;
+  t.state = a.state;
+  t.counts = a.counts;
+  t.tg = &a.tg;
+  t.record = nullptr;
+  t.record_words = 0;
+  t.gshift = a.gshift;
+  run_bits<PM, UM, 0>(t);
+}
+
 // ---------------------------------------------------------------- batches
 // Many networks of uneven size in one persistent launch.  Work is cut into
 // tasks of `wpb` consecutive trajectories of one network, ordered by the host
@@ -1498,6 +1783,28 @@ pbn_status dispatch_pm(const SimParams& p, uint32_t pmax, uint32_t umax, uint32_
   return dispatch_um<IMG_LDS, 7, ALIAS>(p, umax, npass, reg, blocks, lds, s);
 }
 
+template <bool IMG_LDS, int PM, int UM>
+pbn_status launch_bits(const SimParams& p, uint32_t blocks, uint32_t lds, hipStream_t stream) {
+  auto* fn = k_simulate_bits<IMG_LDS, PM, UM>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       int(kLdsMax));
+    if (e != hipSuccess) return hip_check(e, "hipFuncSetAttribute");
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(fn, dim3(blocks), dim3(64u * p.wpb), lds, stream, p);
+  return hip_check(hipGetLastError(), "k_simulate_bits launch");
+}
+
+template <bool IMG_LDS, int PM>
+pbn_status dispatch_bits_um(const SimParams& p, uint32_t umax, uint32_t blocks, uint32_t lds, hipStream_t s) {
+  if (umax == 0) return launch_bits<IMG_LDS, PM, 0>(p, blocks, lds, s);
+  if (umax <= 6) return launch_bits<IMG_LDS, PM, 6>(p, blocks, lds, s);
+  if (umax <= 8) return launch_bits<IMG_LDS, PM, 8>(p, blocks, lds, s);
+  return launch_bits<IMG_LDS, PM, 16>(p, blocks, lds, s);
+}
+
 template <bool IMG_LDS, int PM, int NP>
 pbn_status launch_multi(const SimParams& p, uint32_t blocks, uint32_t lds, hipStream_t stream) {
   auto* fn = k_simulate_multi<IMG_LDS, PM, NP>;
@@ -1565,8 +1872,14 @@ pbn_status simulate_common(bool plain, const pbn_plan* plan, const void* d_plan,
       return fail(PBN_EINVAL, "traj_per_wave > 1 needs a keyed FN-only plan whose K slot sets fit 4 lane passes, "
                               "K n_jobs <= 64, K targets <= 64 and no recording (K <= 4)");
   }
+  const pbn_plan_header* ph = reinterpret_cast<const pbn_plan_header*>(plan->blob.data());
+  const bool bits = ph->state_bits != 0;
+  if (bits && (tpw > 1u || (launch && launch->d_record)))
+    return fail(PBN_EINVAL, "plans with the packed-bit state run one trajectory per wave without recording");
   const uint32_t mfill = tpw > 1u ? multi_fill_steps(plan->n_jobs, tpw) : 0u;
+  const uint32_t ring_bytes = 16u * (plan->n_jobs <= 64 ? std::min(plan->fill_steps, 32u) * plan->n_jobs : plan->n_jobs);
   const uint32_t wave_bytes = tpw > 1u ? tpw * 4u * ((plan->state_dwords + 3u) & ~3u) + 16u + 16u * mfill * tpw * plan->n_jobs
+                              : bits   ? 8u * ((ph->state_words + 3u) & ~3u) + ring_bytes
                                        : wave_lds_bytes(plan, plan->info.n_passes <= 2u);
   const bool img_lds = plan->info.image_in_lds != 0;
   const uint32_t img = img_lds ? ((plan->info.image_bytes + 15u) & ~15u) : 0u;
@@ -1607,6 +1920,11 @@ pbn_status simulate_common(bool plain, const pbn_plan* plan, const void* d_plan,
   if (pmax > 7 || umax > 16) return fail(PBN_ELDS, "plan exceeds the kernel's gather widths");
   const uint32_t units = reinterpret_cast<const pbn_plan_header*>(plan->blob.data())->fn_units;
   if (units != (pmax > 5 ? 2u : 1u)) return fail(PBN_EINVAL, "plan FN record format does not match its parent count");
+  if (bits) {
+    if (pmax <= 5)
+      return img_lds ? dispatch_bits_um<true, 5>(p, umax, blocks, lds, s) : dispatch_bits_um<false, 5>(p, umax, blocks, lds, s);
+    return img_lds ? dispatch_bits_um<true, 7>(p, umax, blocks, lds, s) : dispatch_bits_um<false, 7>(p, umax, blocks, lds, s);
+  }
   if (tpw > 1u) {
     const uint32_t nps = (tpw * plan->info.n_slots + 63u) / 64u;
     if (pmax <= 5)
@@ -1778,6 +2096,8 @@ pbn_status batch_shape(const pbn_plan* const* plans, uint32_t nitems, BatchShape
     const pbn_plan* p = plans[k];
     if (!p) return fail(PBN_EINVAL, "null plan in batch");
     if (p->sampling) return fail(PBN_EINVAL, "alias-sampling plans are not supported by the batch entry points");
+    if (reinterpret_cast<const pbn_plan_header*>(p->blob.data())->state_bits)
+      return fail(PBN_EINVAL, "plans with the packed-bit state are not supported by the batch entry points");
     if (p->info.max_fn_parents > 7 || p->info.max_union_bits > 16)
       return fail(PBN_ELDS, "plan exceeds the kernel's gather widths");
     if (p->info.max_fn_parents > 5) sh.pm = 7;

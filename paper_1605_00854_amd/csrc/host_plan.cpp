@@ -409,11 +409,25 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   const uint32_t ntab = uint32_t(std::count_if(slots.begin(), slots.end(), [](const Slot& s) { return s.table; }));
   const uint32_t fn_pos0 = 4 * ntab;
   const uint32_t fn_end = fn_pos0 + (ns - ntab);
-  const uint32_t zero_pos = (fn_end + 3) & ~3u;
+  // packed-bit layout (state_bits): pass p owns a segment of 256 bits when it
+  // holds a table slot (lane L's member k at 4 L + k), else 64 (lane L at L);
+  // the zero word follows the last segment.  Padded lanes own their segment
+  // bits and write zeros there.
+  const bool bits = o.state_bits != 0;
+  std::vector<uint32_t> seg(npass + 1, 0);
+  for (uint32_t p = 0; p < npass; ++p) {
+    const bool tab = 64 * p < ns && slots[64 * p].table;   // table slots come first
+    seg[p + 1] = seg[p] + (tab ? 256u : 64u);
+  }
+  auto seg_table = [&](uint32_t p) { return seg[p + 1] - seg[p] == 256u; };
+  const uint32_t zero_pos = bits ? seg[npass] : (fn_end + 3) & ~3u;
   const uint32_t pad_pos0 = zero_pos + 4;
-  const uint32_t state_words = (pad_pos0 + (npass * PBN_WAVE - ns) + 31) / 32;
+  const uint32_t state_words = bits ? zero_pos / 32 + 1 : (pad_pos0 + (npass * PBN_WAVE - ns) + 31) / 32;
   if (32ull * state_words > 65535) return fail(PBN_ELDS, "too many slots (%u) for 16-bit state positions", ns);
-  auto slot_pos = [&](uint32_t s, uint32_t k) { return s < ntab ? 4 * s + k : fn_pos0 + (s - ntab); };
+  auto slot_pos = [&](uint32_t s, uint32_t k) {
+    if (bits) return seg[s / 64] + (seg_table(s / 64) ? 4 * (s % 64) + k : s % 64);
+    return s < ntab ? 4 * s + k : fn_pos0 + (s - ntab);
+  };
 
   plan.node_pos.assign(n, PBN_NONE);
   plan.node_slot.assign(n, PBN_NONE);
@@ -548,7 +562,7 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   for (size_t s = ns; s < size_t(npass) * PBN_WAVE; ++s) {
     put32(s * 16 + 4, uint32_t(dummy_of(s)));
     put32(s * 16 + 8, uint32_t(default_choice));
-    put32(s * 16 + 12, uint32_t(pad_pos0 + (s - ns)));
+    put32(s * 16 + 12, uint32_t(bits ? slot_pos(uint32_t(s), 0) : pad_pos0 + (s - ns)));
   }
   size_t choice_cur = choice_base + 16, tab_cur = tab_base;
   std::vector<pbn_pass_info> passes(npass, pbn_pass_info{0, 0, 0, 0});
@@ -583,7 +597,7 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
       const uint32_t pm = max_phi(v);
       info |= pm << 6;
       y = uint32_t(fn_rec(s, 0));
-      w = fn_pos0 + (s - ntab);   // the slot's state byte
+      w = slot_pos(s, 0);   // the slot's state position
       for (uint32_t f = g.fn_off[v]; f < g.fn_off[v + 1]; ++f) {
         const size_t r = fn_rec(s, f - g.fn_off[v]);
         const uint32_t k = g.nparents(f);
@@ -736,6 +750,7 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   h.dummy_fn = uint32_t(dummy_fn);
   h.fn_units = units;
   h.fn_var = fn_var ? 1u : 0u;
+  h.state_bits = bits ? 1u : 0u;
   h.fn_jshift = uint32_t(__builtin_ctz(jstride));
   h.fn_hoff = hoff;
   h.q_img = uint32_t(q_img);
@@ -826,6 +841,8 @@ extern "C" pbn_status pbn_plan_build(const pbn_net* g, const uint32_t* interest,
     pbn_plan_opts_default(&o);
   if (o.reduce > 2) return fail(PBN_EINVAL, "reduce must be 0, 1 or 2");
   if (o.sampling > 1) return fail(PBN_EINVAL, "sampling must be 0 (keyed) or 1 (alias)");
+  if (o.state_bits > 1) return fail(PBN_EINVAL, "state_bits must be 0 or 1");
+  if (o.state_bits && o.sampling) return fail(PBN_EINVAL, "the packed-bit state layout takes keyed draws only");
   if (o.max_group_nodes < 1 || o.max_group_nodes > PBN_MAX_GROUP_NODES)
     return fail(PBN_EINVAL, "max_group_nodes must be 1..%d", PBN_MAX_GROUP_NODES);
   if (o.max_parent_bits > PBN_MAX_GROUP_PARENTS)

@@ -93,6 +93,10 @@ struct pbn_plan_header {
   uint32_t n_sel;          // slots that draw a (combined) predictor function
   uint32_t fn_var;         // 1: packed two-unit plan whose slots with <= 5 parents keep one-unit
                            // records (predictor stride 16 units of the slot)
+  uint32_t state_bits;     // 1: positions are bit indices of a packed state of pass segments
+                           // (256 bits for a pass holding a table slot: lane L's member k at
+                           // 4 L + k; else 64 bits: lane L at L), the zero word after the last
+                           // segment; 0: byte positions (the layout described above)
 };
 // Alias sampling draws, per step t: Philox(traj, t, c, PBN_STREAM_ALIAS) for
 // c = 0 .. n_jobs-1 give words w[0 .. 4 n_jobs) (word e of call c is w[4c+e]):

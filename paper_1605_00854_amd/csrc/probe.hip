@@ -73,12 +73,14 @@ __global__ void __launch_bounds__(kProbeThreads) k_probe_lds(uint32_t log2_bytes
   if (acc == 0x9E3779B9u) sink[0] = gid;   // keeps the reads; practically never stores
 }
 
-// Random 16-byte gathers from a global buffer of buf_bytes (a power of two,
-// at least 16): the vector-memory path a plan image in global memory takes.
+// Random gathers of WIDTH bytes (1 or 16) from a global buffer of 2^log2_bytes
+// bytes: the vector-memory path a plan image in global memory takes (16-byte
+// records, one-byte table entries).
+template <int WIDTH>
 __global__ void __launch_bounds__(kProbeThreads) k_probe_vmem(const uint8_t* __restrict__ img, uint32_t log2_bytes,
                                                              uint32_t iters, uint32_t* sink) {
   const uint32_t gid = blockIdx.x * kProbeThreads + threadIdx.x;
-  const uint32_t amask = ((1u << log2_bytes) - 1u) & ~15u;
+  const uint32_t amask = ((1u << log2_bytes) - 1u) & ~uint32_t(WIDTH - 1);
   uint32_t a[kProbeStreams];
 #pragma unroll
   for (int k = 0; k < kProbeStreams; ++k) a[k] = probe_hash(gid * kProbeStreams + k) & amask;
@@ -88,8 +90,12 @@ __global__ void __launch_bounds__(kProbeThreads) k_probe_vmem(const uint8_t* __r
     const uint32_t d = step & amask;
 #pragma unroll
     for (int k = 0; k < kProbeStreams; ++k) {
-      const uint4 v = *reinterpret_cast<const uint4*>(img + a[k]);
-      acc += v.x ^ v.y ^ v.z ^ v.w;
+      if constexpr (WIDTH == 16) {
+        const uint4 v = *reinterpret_cast<const uint4*>(img + a[k]);
+        acc += v.x ^ v.y ^ v.z ^ v.w;
+      } else {
+        acc += img[a[k]];
+      }
       a[k] ^= d;
     }
   }
@@ -122,13 +128,18 @@ extern "C" pbn_status pbn_probe_lds_gather(uint32_t log2_bytes, uint32_t width, 
   return e == hipSuccess ? PBN_OK : probe_fail(PBN_EHIP, std::string("probe launch: ") + hipGetErrorString(e));
 }
 
-extern "C" pbn_status pbn_probe_vmem_gather(const void* d_buf, uint32_t log2_bytes, uint32_t iters, uint32_t blocks,
-                                            uint32_t* d_sink, void* stream) {
+extern "C" pbn_status pbn_probe_vmem_gather(const void* d_buf, uint32_t log2_bytes, uint32_t width, uint32_t iters,
+                                            uint32_t blocks, uint32_t* d_sink, void* stream) {
   pbn::clear_error();
   if (!d_buf || !d_sink) return probe_fail(PBN_EINVAL, "null argument");
   if (log2_bytes < 4 || log2_bytes > 30 || blocks == 0) return probe_fail(PBN_EINVAL, "bad buffer size or block count");
-  hipLaunchKernelGGL(k_probe_vmem, dim3(blocks), dim3(kProbeThreads), 0, static_cast<hipStream_t>(stream),
-                     static_cast<const uint8_t*>(d_buf), log2_bytes, iters, d_sink);
+  if (width != 1 && width != 16) return probe_fail(PBN_EINVAL, "width must be 1 or 16 bytes");
+  if (width == 16)
+    hipLaunchKernelGGL(k_probe_vmem<16>, dim3(blocks), dim3(kProbeThreads), 0, static_cast<hipStream_t>(stream),
+                       static_cast<const uint8_t*>(d_buf), log2_bytes, iters, d_sink);
+  else
+    hipLaunchKernelGGL(k_probe_vmem<1>, dim3(blocks), dim3(kProbeThreads), 0, static_cast<hipStream_t>(stream),
+                       static_cast<const uint8_t*>(d_buf), log2_bytes, iters, d_sink);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? PBN_OK : probe_fail(PBN_EHIP, std::string("probe launch: ") + hipGetErrorString(e));
 }

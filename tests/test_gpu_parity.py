@@ -269,6 +269,39 @@ def test_autotune_candidates_are_bit_identical(name):
         assert np.array_equal(c, ref[2]), opts
 
 
+BITS = dict(reduce=1, group=0, state_bits=1)
+BITS_GROUPED = dict(reduce=1, group=1, state_bits=1, lds_budget_bytes=150000)
+BITS_TUNED = dict(reduce=1, group=1, state_bits=1, max_parent_bits=5, max_group_nodes=4, lds_budget_bytes=150000)
+BITS_MULTI = dict(MULTI_GROUPS, state_bits=1)
+BITS_GLOBAL = dict(reduce=1, group=1, state_bits=1, lds_budget_bytes=0)
+BITS_PLAIN = dict(reduce=0, group=0, state_bits=1)
+
+BITS_CASES = [
+    # (network, plan, seed, traj0, ntraj, chunks, count_from, plain, wpb)
+    ("c2", "BITS", 51, 0, 70, (150, 113), 40, True, 4),                 # FN passes only: ballot words
+    ("c2", "BITS_GROUPED", 52, 5, 67, (263,), 0, False, 8),             # table passes: DPP-combined nibbles
+    ("c2_hot", "BITS_GROUPED", 53, 0, 45, (120, 80), 30, False, 4),     # chains flip bits most steps
+    ("multi400", "BITS_MULTI", 54, 0, 20, (60, 40), 10, False, 2),      # combined tables of several members
+    ("c3_slice", "BITS_TUNED", 55, 0, 24, (90, 70), 20, False, 16),     # many passes, a mixed table/FN pass
+    ("c3_slice", "BITS_GLOBAL", 56, 3, 11, (100,), 0, False, 4),        # image in global memory
+    ("sparse120", "BITS_GROUPED", 57, 0, 33, (200,), 50, False, 4),
+    ("wide40", "BITS", 58, 0, 29, (120, 33), 15, True, 4),              # predictors of up to 7 parents
+    ("c1", "BITS_PLAIN", 59, 0, 9, (300,), 0, True, 4),
+    ("modules", "BITS_GROUPED", 60, 0, 40, (160,), 20, False, 4),
+]
+
+
+@pytest.mark.parametrize("case", BITS_CASES, ids=lambda c: f"{c[0]}-{c[1]}")
+def test_packed_bit_state_matches_the_oracle(case):
+    """Plans built with the packed-bit state (parents read as bits, each pass's
+    results written as whole words): every kept node and every counter equals
+    the oracle's."""
+    name, opts, seed, traj0, ntraj, chunks, count_from, plain, wpb = case
+    plan = check(name, globals()[opts], seed, traj0, ntraj, chunks, count_from, plain, wpb)
+    if opts in ("BITS_GROUPED", "BITS_TUNED", "BITS_MULTI") and name != "c2_hot":
+        assert plan.info["n_table_slots"] > 0
+
+
 MULTI_CASES = [
     # (network, plan, trajectories per wave, seed, traj0, ntraj, chunks, count_from, plain, wpb)
     ("c2", "REDUCED", 2, 41, 0, 131, (150, 113), 40, True, 0),      # 170 virtual slots: 3 passes
