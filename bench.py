@@ -107,6 +107,112 @@ def slot_work(net, plan):
     return out
 
 
+def lds_work(net, plan, slots_desc):
+    """LDS and image lookups one trajectory-step must make (the gather model).
+
+    A step without perturbation gathers every slot's parent bits (one state
+    byte each), writes one state byte per kept node, reads one drawn word per
+    selecting slot, one combined-table entry per table slot and one 16-byte
+    predictor record per multi-predictor FN slot (a one-predictor slot's
+    record can stay in registers).  Returns per-trajectory-step counts:
+    u8 (random byte gathers and stores), w4 (drawn words), rec16 (records) and
+    tab8 (table entries), and where records and tables live ("lds" or
+    "global")."""
+    n, p = net["n"], net["p"]
+    f = (1.0 - p) ** n
+    slot, is_table = plan.slots()
+    bits = bool(plan.opts.state_bits)
+    gathers = sum(bits for bits, _ in slots_desc)
+    n_multi_fn = sum(1 for (bits, nm), t in zip(slots_desc, is_table) if not t and nm)
+    n_sel = sum(1 for (_, nm) in slots_desc if nm)
+    n_tab = int(np.count_nonzero(is_table))
+    return {"u8": f * (gathers + plan.info["n_kept"]), "w4": f * n_sel, "rec16": f * n_multi_fn,
+            "tab8": f * n_tab, "image": "lds" if plan.info["image_in_lds"] else "global",
+            "state": "bits" if bits else "bytes"}
+
+
+def measure_gather_rates(api, torch, plan):
+    """Chip-wide lane-lookup rates of the probe kernels (lookups/s): random byte
+    gathers from an LDS buffer the size of the plan's state bytes, swizzled
+    4- and 16-byte reads, and random 16-byte reads of a global buffer the size
+    of the plan image."""
+    from paper_1605_00854_amd import _lib
+    L = api.lib()
+    stream = torch.cuda.current_stream()
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    blocks, iters = 2048, 2048
+    per_launch = blocks * 256 * iters * 8
+    # the LDS buffer gathers read: one byte per node, or 4 bytes per 32 nodes
+    # for packed-bit plans (whose gathers read words)
+    lds_state = plan.info["state_bytes"] // (8 if plan.opts.state_bits else 1)
+    state_bytes = max(128, 1 << int(math.ceil(math.log2(max(1, lds_state)))))
+    img_log2 = max(7, int(math.ceil(math.log2(max(16, plan.info["image_bytes"])))))
+    buf = torch.zeros(1 << img_log2, dtype=torch.uint8, device="cuda")
+
+    def timed(fn):
+        fn()                                   # warm-up
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        e1.synchronize()
+        return per_launch / (e0.elapsed_time(e1) * 1e-3)
+
+    sp = _lib.C.c_void_p(stream.cuda_stream)
+    dsink = _lib.C.c_void_p(sink.data_ptr())
+    out = {}
+    for name, (lg, width, pattern) in {"u8_random": (int(math.log2(state_bytes)), 1, 0),
+                                       "w4_random": (int(math.log2(state_bytes)), 4, 0),
+                                       "w4_swizzled": (int(math.log2(state_bytes)), 4, 1),
+                                       "rec16_swizzled": (min(16, img_log2), 16, 1),
+                                       "rec16_random": (min(16, img_log2), 16, 0)}.items():
+        def lds_probe(lg=lg, width=width, pattern=pattern):
+            api.check(L.pbn_probe_lds_gather(lg, width, pattern, iters, blocks, dsink, sp))
+        out[name] = timed(lds_probe)
+
+    for name, width in (("global16_random", 16), ("global1_random", 1)):
+        def vmem_probe(width=width):
+            api.check(L.pbn_probe_vmem_gather(_lib.C.c_void_p(buf.data_ptr()), img_log2, width, iters // 4, blocks,
+                                              dsink, sp))
+        out[name] = timed(vmem_probe) / 4    # a quarter of the iterations per launch
+    out["state_buffer_bytes"] = state_bytes
+    out["image_buffer_bytes"] = 1 << img_log2
+    return out
+
+
+def roofline_head(ceil, alu_achieved, traj_steps_per_s):
+    """bound / achieved / peak / unit / frac of the binding resource: the VALU
+    in int32 lane-operations per second, LDS or vector memory in
+    trajectory-steps per second at the ceiling the probes measured."""
+    b = ceil["bound"]
+    if b == "alu":
+        return {"bound": "alu", "achieved": alu_achieved / 1e12, "peak": PEAK_ALU / 1e12,
+                "unit": "Tops/s (int32 VALU lane-ops)", "frac": alu_achieved / PEAK_ALU}
+    peak = 1.0 / ceil[b]["seconds_per_traj_step"]
+    return {"bound": b, "achieved": traj_steps_per_s, "peak": peak,
+            "unit": f"trajectory-steps/s ({'LDS' if b == 'lds' else 'vector-memory'} gather ceiling from the probes)",
+            "frac": traj_steps_per_s / peak}
+
+
+def ceilings(w_ops, work, rates, traj_steps_per_s):
+    """Fractions of the VALU, LDS and vector-memory ceilings the kernel reaches.
+    Each resource's time per trajectory-step at its measured (or nominal VALU)
+    rate; the binding resource is the one with the largest fraction."""
+    t_alu = w_ops / PEAK_ALU
+    gather_rate = rates["w4_random"] if work.get("state") == "bits" else rates["u8_random"]
+    t_lds = (work["u8"] / gather_rate + work["w4"] / rates["w4_swizzled"]
+             + (work["rec16"] / rates["rec16_swizzled"] + work["tab8"] / rates["u8_random"]
+                if work["image"] == "lds" else 0.0))
+    t_vmem = (work["rec16"] / rates["global16_random"] + work["tab8"] / rates["global1_random"]
+              if work["image"] == "global" else 0.0)
+    out = {}
+    for name, t in (("alu", t_alu), ("lds", t_lds), ("vmem", t_vmem)):
+        if t > 0:
+            out[name] = {"seconds_per_traj_step": t, "frac": t * traj_steps_per_s}
+    out["bound"] = max((k for k in out), key=lambda k: out[k]["frac"])
+    return out
+
+
 # ------------------------------------------------------------ CPU baseline
 
 def _oracle_worker(args):
@@ -118,7 +224,10 @@ def _oracle_worker(args):
 
 
 def cpu_baseline(cfg_name, ntraj, steps):
-    """The oracle as it stands, one worker per host core, on a bounded sample."""
+    """The oracle as it stands, one worker per host core of this process's CPU
+    share, on a bounded sample.  The share is the affinity set, at most 16
+    cores: the GPU machine grants one GPU's job 16 cores whatever the machine
+    shows."""
     import multiprocessing as mp
     cores = max(1, min(16, len(os.sched_getaffinity(0))))
     chunks = [c.tolist() for c in np.array_split(np.arange(ntraj), cores) if c.size]
@@ -129,13 +238,15 @@ def cpu_baseline(cfg_name, ntraj, steps):
     dt = time.perf_counter() - t0
     n = ps.config(cfg_name).net["n"]
     return {"value": ntraj * steps * n / dt, "unit": "node-updates/s", "cores": len(chunks),
+            "host_cores_visible": os.cpu_count(), "affinity_cores": len(os.sched_getaffinity(0)),
             "kind": "oracle", "sample": f"{cfg_name}: {ntraj} trajectories x {steps} steps "
-                                        f"(numpy oracle, unreduced network), {dt:.1f} s wall"}
+                                        f"(numpy oracle, unreduced network, one worker per core), "
+                                        f"{dt:.1f} s wall"}
 
 
 # --------------------------------------------------------------- GPU path
 
-def run_step(api, torch, cfg, opts, plain, chunk, events, wpb=0):
+def run_step(api, torch, cfg, opts, plain, chunk, events, wpb=0, tpw=1):
     """One pass of the hot path.  Returns (estimate, half-width, prep seconds)."""
     net = cfg.net
     interest = sorted({a for tg in cfg.targets for a, _ in tg})
@@ -155,15 +266,14 @@ def run_step(api, torch, cfg, opts, plain, chunk, events, wpb=0):
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         api.simulate(plan, cfg.seed, state, counts, tg, step, c, count_from=cfg.burn_in, plain=plain,
-                     waves_per_block=wpb)
+                     waves_per_block=wpb, traj_per_wave=tpw)
         e1.record(stream)
         events.append((e0, e1, c))
         step += c
-    hits = counts[0, :, 0].cpu().numpy().astype(np.float64)    # synchronises
-    means = hits / cfg.steps
-    p_hat = float(means.mean())
-    hw = 1.96 * float(means.std(ddof=1)) / math.sqrt(means.size) if means.size > 1 else float("nan")
-    return plan, p_hat, hw, prep
+    # steady-state estimate of the first target through the library's
+    # estimator (t interval over the trajectories' means)
+    est = api.estimate(counts[0].cpu().numpy(), cfg.steps, conf=0.95)    # synchronises
+    return plan, est["p_hat"], est["half_width"], prep
 
 
 def tuned_opts_for(api, torch, nets, seed, ntraj=256, sample=4):
@@ -186,6 +296,58 @@ def tuned_opts_for(api, torch, nets, seed, ntraj=256, sample=4):
         v[1] += rate
     best = max(votes.items(), key=lambda kv: (kv[1][0], kv[1][1]))
     return dict(best[0]), best[1][2]
+
+
+def config_compare(api, torch, name, chunk, tag=None):
+    """One full run of a fixed-length workload with the autotuned plan, then
+    the reduction-only and the plain kernel on the same workload; the product
+    kernel's launch times (HIP events on its stream) give its roofline."""
+    from paper_1605_00854_amd import autotune
+    cfg = ps.config(name)
+    net = cfg.net
+    n = net["n"]
+    interest = sorted({a for tg in cfg.targets for a, _ in tg})
+    t0 = time.perf_counter()
+    opts, wpb, trials = autotune.tune(net, interest, cfg.targets, cfg.ntraj, seed=cfg.seed, quick=True)
+    tpw = autotune.best_launch(trials)[1]
+    t_tune = time.perf_counter() - t0
+    work = cfg.ntraj * (cfg.burn_in + cfg.steps) * n
+    out = {"workload": f"{name}: random PBN n={n}, p={net['p']}, {cfg.ntraj} trajectories x {cfg.steps} steps "
+                       f"(+{cfg.burn_in} burn-in)", "autotune_seconds": t_tune, "autotune_trials": len(trials)}
+    legs = {"product": (opts, not opts.get("group", 0), wpb, tpw), "reduction": (PLANS["reduction"], True, 0, 1),
+            "plain": (PLANS["plain"], True, 0, 1)}
+    for label, (o, plain, w, k) in legs.items():
+        ev = []
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        plan, p_hat, hw, _ = run_step(api, torch, cfg, o, plain, chunk, ev, w, k)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        kt = sum(e0.elapsed_time(e1) * 1e-3 for e0, e1, _ in ev)
+        leg = {"node_updates_per_s": work / dt, "kernel_node_updates_per_s": work / kt, "seconds": dt,
+               "plan": o, "waves_per_block": w or 4, "traj_per_wave": k, "n_kept": plan.info["n_kept"],
+               "slots": plan.info["n_slots"],
+               "table_slots": plan.info["n_table_slots"], "passes": plan.info["n_passes"],
+               "image_in_lds": plan.info["image_in_lds"], "estimate": {"p_hat": p_hat, "half_width_95": hw}}
+        if label == "product":
+            durs = [(e0.elapsed_time(e1) * 1e-3, c) for e0, e1, c in ev]
+            avg_launch = sum(d for d, _ in durs) / len(durs)
+            avg_steps = sum(c for _, c in durs) / len(durs)
+            npairs = sum(len(t) for t in cfg.targets)
+            sd = slot_work(net, plan)
+            w_step = algorithmic_ops(net, plan.info, sd, len(cfg.targets), npairs)
+            rates = measure_gather_rates(api, torch, plan)
+            ceil = ceilings(w_step, lds_work(net, plan, sd), rates, cfg.ntraj * avg_steps / avg_launch)
+            leg["roofline"] = {**roofline_head(ceil, w_step * cfg.ntraj * avg_steps / avg_launch,
+                                               cfg.ntraj * avg_steps / avg_launch),
+                               "alu_frac": ceil["alu"]["frac"], "ceilings": ceil, "gather_rates": rates,
+                               "kernel": "k_simulate", "ops_per_traj_step": w_step,
+                               "avg_launch_ms": avg_launch * 1e3, "steps_per_launch": avg_steps}
+        out[label] = leg
+    out["product_over_plain"] = out["product"]["node_updates_per_s"] / out["plain"]["node_updates_per_s"]
+    out["product_over_reduction"] = out["product"]["node_updates_per_s"] / out["reduction"]["node_updates_per_s"]
+    out["reduction_over_plain"] = out["reduction"]["node_updates_per_s"] / out["plain"]["node_updates_per_s"]
+    return out
 
 
 def bench_batch(args):
@@ -239,13 +401,11 @@ def bench_batch(args):
     print(json.dumps(out))
 
 
-def bench_serve(args):
-    """C5: Poisson stream of 2000 queries at 200/s over 64 resident networks."""
-    import torch
-    from paper_1605_00854_amd import api, serve
-    torch.cuda.set_device(0)
+def serve_compare(api, torch, nq, query_chunk):
+    """C5 served by the autotuned product plan and by the plain kernel: p50/p99
+    latency from arrival to result and node-updates/s of each."""
+    from paper_1605_00854_amd import serve
     nets = ps.served_c5()
-    nq = args.queries
     results = {}
     for label in ("product", "plain"):
         if label == "product":
@@ -253,12 +413,22 @@ def bench_serve(args):
         else:
             opts, wpb = dict(reduce=0, group=0), 4
         srv = serve.Server(nets, [1005000 + k for k in range(len(nets))], plan_opts=opts, traj_per_query=256,
-                           chunk=args.query_chunk, burn_in=1000, min_counted=1000, max_steps=200000,
+                           chunk=query_chunk, burn_in=1000, min_counted=1000, max_steps=200000,
                            waves_per_block=wpb)
         qs = serve.poisson_queries(nets, nq, rate=200.0, seed=2005)
         m = srv.run(qs, realtime=True)
         m["plan"] = opts
         results[label] = m
+    return results
+
+
+def bench_serve(args):
+    """C5: Poisson stream of 2000 queries at 200/s over 64 resident networks."""
+    import torch
+    from paper_1605_00854_amd import api
+    torch.cuda.set_device(0)
+    nq = args.queries
+    results = serve_compare(api, torch, nq, args.query_chunk)
     out = {"metric": "p50/p99 query latency and node-updates/sec on 1 MI355X (served queries)",
            "value": results["product"]["p99_latency_s"], "unit": "s (p99 latency)", "n_gpus": 1,
            "higher_is_better": False, "dtype": "u32", "data": "synthetic",
@@ -390,15 +560,22 @@ def main():
     ap.add_argument("--config", default="C2")
     ap.add_argument("--chunk", type=int, default=250000, help="simulation steps per kernel launch")
     ap.add_argument("--sim-steps", type=int, default=0, help="override T (for quick runs)")
+    ap.add_argument("--ntraj", type=int, default=0, help="override the trajectory count (launch-shape studies)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the plain and reduction kernels")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default run only: skip the C3 and C5 legs (grouped product at n = 2000, served queries)")
     ap.add_argument("--wpb", type=int, default=0)
+    ap.add_argument("--tpw", type=int, default=0, help="trajectories per wavefront (default: the autotuner's)")
     ap.add_argument("--quick-tune", action="store_true")
     ap.add_argument("--queries", type=int, default=2000, help="C5: number of served queries")
     ap.add_argument("--query-chunk", type=int, default=500,
                     help="C5: steps every admitted query advances per server tick")
     ap.add_argument("--plan", default="auto", choices=["auto", "plain", "reduction", "cone", "grouped", "alias"],
                     help="product plan: autotuned, or a fixed preparation (profiling runs)")
+    ap.add_argument("--plan-opts", default="",
+                    help="product plan options as JSON (e.g. '{\"reduce\": 1, \"group\": 1, \"max_parent_bits\": 5}'), "
+                         "instead of the autotuner (profiling runs)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB copied once by a plain device copy (HBM counter calibration in profiles)")
     ap.add_argument("--planner-fit", type=int, default=0,
@@ -429,10 +606,13 @@ def main():
     cfg = ps.config(args.config)
     if args.sim_steps:
         cfg.steps = args.sim_steps
+    if args.ntraj:
+        cfg.ntraj = args.ntraj
     cpu = None
     if not args.no_cpu:
         # before any GPU initialisation: the pool forks
-        sample = {"C1": (1, 20000), "C2": (512, 400), "C2X": (256, 400), "C3": (32, 40)}[args.config]
+        # samples of about 10-20 s wall on 16 cores
+        sample = {"C1": (1, 200000), "C2": (4096, 2000), "C2X": (2048, 1600), "C3": (256, 200)}[args.config]
         cpu = cpu_baseline(args.config, *sample)
 
     import torch
@@ -452,25 +632,32 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     t_tune = time.perf_counter()
-    if args.plan == "auto":
+    best_tpw = 1
+    if args.plan_opts:
+        best_opts, best_wpb, trials = json.loads(args.plan_opts), 4, []
+    elif args.plan == "auto":
         best_opts, best_wpb, trials = autotune.tune(net, interest, cfg.targets, cfg.ntraj, seed=cfg.seed,
                                                     quick=args.quick_tune)
+        best_tpw = autotune.best_launch(trials)[1]
     else:
         best_opts, best_wpb, trials = PLANS[args.plan], 4, []
     t_tune = time.perf_counter() - t_tune
     if args.wpb:
         best_wpb = args.wpb
+    if args.tpw:
+        best_tpw = args.tpw
     grouped_trials = [t for t in trials if t.get("opts", {}).get("group") and "node_updates_per_s" in t]
     best_grouped = max(grouped_trials, key=lambda t: t["node_updates_per_s"]) if grouped_trials else None
     product_plain = not best_opts.get("group", 0)
 
     for _ in range(args.warmup):
-        run_step(api, torch, cfg, best_opts, product_plain, args.chunk, [], best_wpb)
+        run_step(api, torch, cfg, best_opts, product_plain, args.chunk, [], best_wpb, best_tpw)
     torch.cuda.synchronize()
     events = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        plan, p_hat, hw, prep = run_step(api, torch, cfg, best_opts, product_plain, args.chunk, events, best_wpb)
+        plan, p_hat, hw, prep = run_step(api, torch, cfg, best_opts, product_plain, args.chunk, events, best_wpb,
+                                         best_tpw)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_per_step = 1e3 * dt / args.steps
@@ -481,9 +668,12 @@ def main():
     avg_launch = sum(d for d, _ in durs) / len(durs)
     avg_steps = sum(c for _, c in durs) / len(durs)
     npairs = sum(len(t) for t in cfg.targets)
-    w_step = algorithmic_ops(net, plan.info, slot_work(net, plan), len(cfg.targets), npairs)
+    sd = slot_work(net, plan)
+    w_step = algorithmic_ops(net, plan.info, sd, len(cfg.targets), npairs)
     achieved = w_step * cfg.ntraj * avg_steps / avg_launch
     kernel_rate = cfg.ntraj * avg_steps * n / avg_launch
+    rates = measure_gather_rates(api, torch, plan)
+    ceil = ceilings(w_step, lds_work(net, plan, sd), rates, cfg.ntraj * avg_steps / avg_launch)
 
     compare = {}
     if not args.no_compare:
@@ -536,11 +726,14 @@ def main():
                    "sim_steps": cfg.steps, "burn_in": cfg.burn_in,
                    "function_step_fraction": (1 - net["p"]) ** n,
                    "density": ps.density(net), "prep_seconds": prep,
-                   "plan": best_opts, "waves_per_block": best_wpb, "autotune_seconds": t_tune,
+                   "plan": best_opts, "waves_per_block": best_wpb, "traj_per_wave": best_tpw,
+                   "autotune_seconds": t_tune,
                    "autotune_trials": len(trials),
                    "estimate": {"p_hat": p_hat, "half_width_95": hw}},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_ALU / 1e12,
-                     "unit": "Tops/s (int32 VALU lane-ops)", "frac": achieved / PEAK_ALU,
+        "roofline": {**roofline_head(ceil, achieved, cfg.ntraj * avg_steps / avg_launch),
+                     "ceilings": ceil, "gather_rates": rates,
+                     "alu": {"achieved": achieved / 1e12, "peak": PEAK_ALU / 1e12, "frac": achieved / PEAK_ALU,
+                             "unit": "Tops/s (int32 VALU lane-ops)", "philox_slots_per_call": PHILOX_SLOTS},
                      "traffic": measured_traffic(args.config) if best_opts == PLANS["reduction"] else None,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "k_simulate", "ops_per_traj_step": w_step,
@@ -549,6 +742,17 @@ def main():
         "compare": compare,
         "cpu_baseline": cpu,
     }
+    if args.config == "C2" and not args.no_extras:
+        # the metric's other halves: the grouped product at the large workload
+        # (C3) and served-query latency (C5), each against the plain kernel
+        print("[bench] C3 product vs reduction vs plain", file=sys.stderr, flush=True)
+        out["extra"] = {"C3": config_compare(api, torch, "C3", args.chunk)}
+        print("[bench] C5 served queries", file=sys.stderr, flush=True)
+        c5 = serve_compare(api, torch, args.queries, args.query_chunk)
+        out["extra"]["C5"] = {"workload": f"C5: {args.queries} queries, Poisson 200/s, 64 resident PBNs "
+                                          f"n~U[50,3000], {args.query_chunk} steps per tick",
+                              **{k: {m: v[m] for m in ("p50_latency_s", "p99_latency_s", "node_updates_per_s",
+                                                       "plan") if m in v} for k, v in c5.items()}}
     print(json.dumps(out))
 
 

@@ -1373,7 +1373,10 @@ __device__ __forceinline__ void run_bits(const TrajArgs& a) {
   fm.var = H->fn_var;
   fm.sh = a.gshift;
   const uint32_t W = H->state_words, Wp = (W + 3u) & ~3u;
-  uint32_t* buf[2] = {reinterpret_cast<uint32_t*>(a.wb), reinterpret_cast<uint32_t*>(a.wb) + Wp};
+  // the two buffers, chosen by a select (an indexed pointer array would hide
+  // from the compiler that both lie in LDS, and turn their reads into flat loads)
+  uint32_t* const buf0 = reinterpret_cast<uint32_t*>(a.wb);
+  uint32_t* const buf1 = buf0 + Wp;
   uint4* ring = reinterpret_cast<uint4*>(a.wb + 8u * Wp);
   const uint32_t* blk = reinterpret_cast<const uint32_t*>(a.blob + H->blk_off);
   const uint8_t* img = a.img;
@@ -1384,8 +1387,8 @@ __device__ __forceinline__ void run_bits(const TrajArgs& a) {
 
   uint32_t* gst = a.state + size_t(a.tl) * W;
   for (uint32_t w = lane; w < Wp; w += 64u) {
-    buf[0][w] = w < W ? gst[w] : 0u;
-    buf[1][w] = 0u;   // the zero word of s(t+1) stays 0: no pass writes it
+    buf0[w] = w < W ? gst[w] : 0u;
+    buf1[w] = 0u;   // the zero word of s(t+1) stays 0: no pass writes it
   }
 
   const uint32_t npairs = a.tg->npairs, ntg = a.tg->ntargets;
@@ -1417,7 +1420,7 @@ __device__ __forceinline__ void run_bits(const TrajArgs& a) {
   const uint32_t nib_shift = 4u * (lane & 7u);
 
   uint32_t cur = 0;
-  uint32_t zlast = target_z(buf[0]) ? 1u : 0u;
+  uint32_t zlast = target_z(buf0) ? 1u : 0u;
   uint32_t zacc = 0, nacc = 0, hits = 0, n01 = 0, n10 = 0;
   uint32_t t = a.step0, tacc = t;
   auto low_bits = [](long long m) -> uint32_t { return m <= 0 ? 0u : m >= 32 ? 0xFFFFFFFFu : (1u << m) - 1u; };
@@ -1455,7 +1458,7 @@ __device__ __forceinline__ void run_bits(const TrajArgs& a) {
       const uint8_t* rs = reinterpret_cast<const uint8_t*>(ring + s * njobs);
       const uint2 pr = *reinterpret_cast<const uint2*>(rs);
       const uint32_t ulo = uniform(pr.x), uhi = uniform(pr.y);
-      uint32_t* cw = buf[cur];
+      uint32_t* cw = cur ? buf1 : buf0;
       bool z;
       if (uhi > qn_hi || (uhi == qn_hi && ulo >= qn_lo)) {
         // perturbation-only step: flip the perturbed kept nodes' bits in place
@@ -1465,7 +1468,7 @@ __device__ __forceinline__ void run_bits(const TrajArgs& a) {
         wave_sync();
         z = target_z(cw);
       } else {
-        uint32_t* nw = buf[cur ^ 1u];
+        uint32_t* nw = cur ? buf0 : buf1;
         uint32_t seg = 0;   // word offset of pass p's segment
         for (uint32_t p = 0; p < npass; ++p) {
           const uint32_t flags = uniform(pinfo[p].flags);
@@ -1504,7 +1507,7 @@ __device__ __forceinline__ void run_bits(const TrajArgs& a) {
     c[1] += n01;
     c[2] += n10;
   }
-  for (uint32_t w = lane; w < W; w += 64u) gst[w] = buf[cur][w];
+  for (uint32_t w = lane; w < W; w += 64u) gst[w] = cur ? buf1[w] : buf0[w];
 }
 
 // One network with a packed-bit state (run_bits): one wavefront per

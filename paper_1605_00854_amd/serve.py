@@ -13,6 +13,16 @@ Every tick advances all admitted queries by one chunk in a single persistent
 batched launch (pbn_batch_launch): queries that arrived while others were on
 the device join at the next tick as soon as their footprint (resident waves,
 LDS bytes, HBM bytes) fits, and leave when their precision is met.
+
+The device never waits for the host between ticks: tick k is enqueued (launch,
+then an asynchronous copy of every active query's counters into pinned host
+memory, then an event) before the host reads tick k-1's counters.  A query
+that meets its precision at tick k-1 is decided from that tick's copy and
+leaves before tick k+1 (the chunk it runs at tick k is discarded).  The work
+items, task list and control block stay on the device and are rewritten only
+when the set of active queries changes; the control block's step window
+advances on the device after each launch, and each item's step offset is
+fixed at the tick its query joined.
 """
 import hashlib
 import time
@@ -45,6 +55,14 @@ def query_seed(net_seed, qid):
     return int.from_bytes(h[:8], "little")
 
 
+def non_sink_nodes(net):
+    """Nodes that some predictor reads (at least one child): the interest set
+    of a resident plan, so Definition 1 removes exactly the network's sinks."""
+    used = np.zeros(int(net["n"]), dtype=bool)
+    used[np.asarray(net["parents"], dtype=np.int64)] = True
+    return frozenset(np.nonzero(used)[0].tolist())
+
+
 class Footprint:
     """Device budget for admission: resident waves, LDS bytes, HBM bytes."""
 
@@ -65,6 +83,33 @@ class Footprint:
         self.used -= need
 
 
+class _Resident:
+    """Device buffers that outlive ticks: work items, tasks, first trajectory
+    of each task, control block; grown (never shrunk) by doubling."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.items = torch.zeros(0, dtype=torch.uint8, device="cuda")
+        self.tasks = torch.zeros(0, dtype=torch.int32, device="cuda")
+        self.first = torch.zeros(0, dtype=torch.int32, device="cuda")
+
+    def _fit(self, buf, nelem, dtype):
+        if buf.numel() >= nelem:
+            return buf
+        return self.torch.zeros(max(nelem, 2 * buf.numel()), dtype=dtype, device="cuda")
+
+    def upload(self, works, tasks, first):
+        torch = self.torch
+        raw = np.frombuffer(bytes(works), dtype=np.uint8)
+        self.items = self._fit(self.items, raw.size, torch.uint8)
+        self.tasks = self._fit(self.tasks, tasks.size, torch.int32)
+        self.first = self._fit(self.first, first.size, torch.int32)
+        # stream-ordered copies: they run after the launches already enqueued
+        self.items[:raw.size].copy_(torch.from_numpy(raw.copy()).pin_memory(), non_blocking=True)
+        self.tasks[:tasks.size].copy_(torch.from_numpy(tasks.astype(np.int32)).pin_memory(), non_blocking=True)
+        self.first[:first.size].copy_(torch.from_numpy(first.astype(np.int32)).pin_memory(), non_blocking=True)
+
+
 class Server:
     def __init__(self, nets, net_seeds, *, plan_opts=None, traj_per_query=256, chunk=1000, burn_in=1000,
                  min_counted=1000, max_steps=400000, waves_per_block=4, footprint=None):
@@ -81,21 +126,25 @@ class Server:
         self.wpb = int(waves_per_block)
         self.fp = footprint or Footprint()
         self.plans = {}
-        for k, net in enumerate(nets):
+        self.base_interest = [non_sink_nodes(net) for net in nets]
+        for k in range(len(nets)):
             self._plan(k, ())
         self.queue, self.active, self.done = [], [], []
         self.node_updates = 0
         self.ticks = 0
+        self.res = _Resident(torch)
         self.ctl = torch.tensor([0, 0, self.chunk, 0], dtype=torch.int32, device="cuda")
+        self.window = 0            # host mirror of the control block's step window
+        self.dirty = True          # the active set changed since the items were written
+        self.ntasks = 0
+        self.inflight = None       # (queries, steps after the tick, pinned counts, event)
 
-    # -- resident plans: interest = every node a query may read
+    # -- resident plans: interest = every node some predictor reads, plus the
+    # nodes of queries that asked for a removed node
     def _plan(self, k, extra):
-        net = self.nets[k]
-        leaves = set(int(x) for x in net.get("designated_leaves", []))
-        base = frozenset(i for i in range(net["n"]) if i not in leaves)
-        key = (k, base | frozenset(extra))
+        key = (k, self.base_interest[k] | frozenset(extra))
         if key not in self.plans:
-            plan = api.Plan(net, interest=sorted(key[1]), **self.opts)
+            plan = api.Plan(self.nets[k], interest=sorted(key[1]), **self.opts)
             plan.device()
             self.plans[key] = plan
         return self.plans[key]
@@ -133,7 +182,6 @@ class Server:
         self.queue.append(q)
 
     def _admit(self, now):
-        torch = self.torch
         while self.queue and self.fp.fits(self.queue[0]._need):
             q = self.queue.pop(0)
             self.fp.take(q._need)
@@ -143,51 +191,68 @@ class Server:
             q._counts = api.new_counts(1, self.ntraj)
             q._tg_dev = api._to_device_bytes(q._tg)
             self.active.append(q)
+            self.dirty = True
 
-    def _launch(self):
-        torch = self.torch
+    def _write_items(self):
+        """Work items and tasks of the active set into the resident buffers.
+        Item k's step offset makes its steps (offset + window) continue from
+        the query's own step count."""
         act = self.active
         works = (_lib.pbn_work * len(act))()
         for k, q in enumerate(act):
+            off = (q.steps - self.window) & 0xFFFFFFFF
             works[k] = _lib.pbn_work(q._plan.device().data_ptr(), q._tg_dev.data_ptr(), q._state.data_ptr(),
-                                     q._counts.data_ptr(), q._seed, 0, self.ntraj, self.burn_in, q.steps)
-        items_dev = api._to_device_bytes(works)
-        plans = (api.C.c_void_p * len(act))(*[q._plan.handle.value for q in act])
+                                     q._counts.data_ptr(), q._seed, 0, self.ntraj, self.burn_in, off)
+        self._plans_arr = (api.C.c_void_p * len(act))(*[q._plan.handle.value for q in act])
         ntraj = np.full(len(act), self.ntraj, dtype=np.uint32)
         nt = api.C.c_uint32()
         L = _lib.lib()
-        _lib.check(L.pbn_batch_tasks(plans, api._ptr(ntraj, api.C.c_uint32), len(act), self.wpb, None, None,
-                                     api.C.byref(nt)))
+        _lib.check(L.pbn_batch_tasks(self._plans_arr, api._ptr(ntraj, api.C.c_uint32), len(act), self.wpb, None,
+                                     None, api.C.byref(nt)))
         tasks = np.zeros(nt.value, dtype=np.uint32)
         first = np.zeros(nt.value, dtype=np.uint32)
-        _lib.check(L.pbn_batch_tasks(plans, api._ptr(ntraj, api.C.c_uint32), len(act), self.wpb,
+        _lib.check(L.pbn_batch_tasks(self._plans_arr, api._ptr(ntraj, api.C.c_uint32), len(act), self.wpb,
                                      api._ptr(tasks, api.C.c_uint32), api._ptr(first, api.C.c_uint32),
                                      api.C.byref(nt)))
-        tasks_dev = torch.from_numpy(tasks.astype(np.int32)).to("cuda")
-        first_dev = torch.from_numpy(first.astype(np.int32)).to("cuda")
-        self.ctl.copy_(torch.tensor([0, 0, self.chunk, 0], dtype=torch.int32))
-        _lib.check(L.pbn_batch_launch(plans, len(act), api._dptr(items_dev), api._dptr(tasks_dev),
-                                      api._dptr(first_dev), nt.value, api._dptr(self.ctl), self.wpb,
-                                      api._stream(None)))
-        return items_dev, tasks_dev, first_dev        # keep alive until the sync
+        self.res.upload(works, tasks, first)
+        self.ntasks = nt.value
+        self.dirty = False
 
-    def tick(self, now_fn):
-        """Admit, advance every active query by one chunk, retire finished ones."""
+    def _enqueue(self):
+        """Tick: one batched launch of every active query, then an asynchronous
+        copy of their counters and an event."""
         torch = self.torch
-        self._admit(now_fn())
-        if not self.active:
-            return False
-        keep = self._launch()
-        counts = torch.cat([q._counts.view(-1) for q in self.active]).cpu().numpy()   # synchronises
-        del keep
-        now = now_fn()
-        self.ticks += 1
-        per = 3 * self.ntraj
-        still = []
-        for k, q in enumerate(self.active):
+        if self.dirty:
+            self._write_items()
+        act = list(self.active)
+        L = _lib.lib()
+        _lib.check(L.pbn_batch_launch(self._plans_arr, len(act), api._dptr(self.res.items),
+                                      api._dptr(self.res.tasks), api._dptr(self.res.first), self.ntasks,
+                                      api._dptr(self.ctl), self.wpb, api._stream(None)))
+        self.window = (self.window + self.chunk) & 0xFFFFFFFF
+        for q in act:
             q.steps += self.chunk
             self.node_updates += self.ntraj * self.chunk * q._plan.n
-            counted = q.steps - self.burn_in
+        counts = torch.cat([q._counts.view(-1) for q in act])
+        host = torch.empty(counts.shape, dtype=counts.dtype, pin_memory=True)
+        host.copy_(counts, non_blocking=True)
+        ev = torch.cuda.Event()
+        ev.record()
+        self.ticks += 1
+        return act, [q.steps for q in act], host, ev
+
+    def _decide(self, tick, now_fn):
+        """Decisions on one finished tick's counters; finished queries leave."""
+        act, steps, host, ev = tick
+        ev.synchronize()
+        now = now_fn()
+        counts = host.numpy()
+        per = 3 * self.ntraj
+        leaving = set()
+        for k, (q, st) in enumerate(zip(act, steps)):
+            if q.status != "running":
+                continue
+            counted = st - self.burn_in
             c = counts[k * per:(k + 1) * per].reshape(self.ntraj, 3)
             finished = False
             if counted >= self.min_counted:
@@ -196,20 +261,32 @@ class Server:
                 if est["half_width"] <= q.precision:
                     q.status = "done"
                     finished = True
-                elif q.steps >= self.max_steps:
+                elif st >= self.max_steps:
                     q.status = "max_steps"
                     finished = True
             if finished:
                 q.finished = now
+                q.steps = st                 # the decision's step count (a later chunk may have run)
                 q.result["counts"] = c.copy()
                 self.fp.give(q._need)
-                for name in ("_state", "_counts", "_tg_dev"):
-                    setattr(q, name, None)
                 self.done.append(q)
-            else:
-                still.append(q)
-        self.active = still
-        return True
+                leaving.add(id(q))
+        if leaving:
+            for q in self.active:
+                if id(q) in leaving:
+                    for name in ("_state", "_counts", "_tg_dev"):
+                        setattr(q, name, None)
+            self.active = [q for q in self.active if id(q) not in leaving]
+            self.dirty = True
+
+    def tick(self, now_fn):
+        """Admit, enqueue the next tick, then decide on the previous one."""
+        self._admit(now_fn())
+        nxt = self._enqueue() if self.active else None
+        if self.inflight is not None:
+            self._decide(self.inflight, now_fn)
+        self.inflight = nxt
+        return nxt is not None
 
     def run(self, queries, realtime=True):
         """Serve `queries` (arrival times in seconds).  Returns the metrics dict."""
@@ -217,13 +294,14 @@ class Server:
         t0 = time.perf_counter()
         now = (lambda: time.perf_counter() - t0) if realtime else (lambda: float(self.ticks))
         i = 0
-        while i < len(pending) or self.queue or self.active:
+        while i < len(pending) or self.queue or self.active or self.inflight is not None:
             tnow = now()
             while i < len(pending) and (pending[i].arrival <= tnow or not realtime):
                 self.submit(pending[i], tnow)
                 i += 1
             if not self.tick(now) and i < len(pending) and realtime:
                 time.sleep(max(0.0, min(0.01, pending[i].arrival - now())))
+        self.torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         return self.metrics(wall)
 

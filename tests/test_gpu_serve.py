@@ -64,6 +64,29 @@ def test_results_identical_alone_and_in_mix():
         assert a.result["p_hat"] == b.result["p_hat"]
 
 
+def test_resident_plans_follow_the_network_not_generator_metadata():
+    """The resident plan's interest set is every node some predictor reads, so
+    Definition 1 removes the sinks whether or not the network carries the
+    generator's list of designated leaves; results do not depend on it."""
+    nets = small_nets()[:2]
+    bare = [{k: v for k, v in net.items() if k != "designated_leaves"} for net in nets]
+    assert all("designated_leaves" not in net for net in bare)
+    template = queries(nets, 4, 11)       # the same queries for both pools
+    runs = []
+    for pool in (nets, bare):
+        srv = make_server(pool)
+        for k, net in enumerate(pool):
+            plan = srv._plan(k, ())
+            sinks = set(range(net["n"])) - set(int(x) for x in net["parents"])
+            assert plan.info["n_kept"] == net["n"] - len(sinks)
+        qs = [serve.Query(q.qid, q.net, list(q.targets), q.precision, q.conf, q.arrival) for q in template]
+        srv.run(qs, realtime=False)
+        runs.append({q.qid: q for q in srv.done})
+    for qid, a in runs[0].items():
+        b = runs[1][qid]
+        assert a.steps == b.steps and np.array_equal(a.result["counts"], b.result["counts"]), qid
+
+
 def test_admission_respects_budget_and_rejects_oversize():
     nets = small_nets()
     big = ps.medium_c2(n=3000, p=1e-4, seed=9)
