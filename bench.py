@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 import pbn_synth as ps  # noqa: E402
 
 PEAK_ALU = 256 * 64 * 2.4e9        # int32 VALU lane-operations per second (256 CUs x 64 lanes x 2.4 GHz)
+L1_PROBE_LOG2 = 14                 # 16 KiB global probe buffer: fits the vector L1 of a CU
 PHILOX_SLOTS = 60                  # 10 rounds x (2 full-rate 32x32->64 multiplies + 4 two-input xors)
 
 # HBM bytes per k_simulate launch of the C2 workload (reduction plan), from two
@@ -40,17 +41,24 @@ PHILOX_SLOTS = 60                  # 10 rounds x (2 full-rate 32x32->64 multipli
 # boundaries (states, counters, plan tables), so a launch of any length moves
 # the same bytes.  Valid only for the kernel source it was measured on.
 MEASURED_TRAFFIC = {
-    "C2": {"kernel_source_sha256": "69404cde5780388f6844765afef7dc8f407ce02efbe22ad680618c562a1c96fa",
-           "fetch_kib": 307.375, "fetch_factor": 2.0, "write_kib": 192.0, "write_factor": 1.0},
+    # per launch of the product plan: FETCH_SIZE and WRITE_SIZE (KiB per
+    # dispatch) of one rocprofv3 --pmc run each, and the factors a 256 MiB
+    # device copy reads for them (fetch 131 088 KiB, write 262 144 KiB)
+    "C2": {"kernel_source_sha256": "d4c1bcff77951b220e5f10d1991d7d7d8350c3808951bff4afc065db21cb02f5",
+           "plan": {"group": 0, "reduce": 1},
+           "fetch_kib": 244.0, "fetch_factor": 2.0, "write_kib": 176.0, "write_factor": 1.0},
+    "C3": {"kernel_source_sha256": "d4c1bcff77951b220e5f10d1991d7d7d8350c3808951bff4afc065db21cb02f5",
+           "plan": {"group": 1, "max_group_nodes": 4, "max_parent_bits": 5, "reduce": 1},
+           "fetch_kib": 13226.9, "fetch_factor": 2.0, "write_kib": 22528.0, "write_factor": 1.0},
 }
 
 
-def measured_traffic(cfg_name):
+def measured_traffic(cfg_name, opts):
     """Scaled HBM bytes per launch, or None when not measured for this
-    workload or the kernel source has changed since."""
+    workload and plan or the kernel source has changed since."""
     import hashlib
     m = MEASURED_TRAFFIC.get(cfg_name)
-    if m is None:
+    if m is None or dict(opts) != m["plan"]:
         return None
     src = os.path.join(ROOT, "paper_1605_00854_amd", "csrc", "device.hip")
     with open(src, "rb") as f:
@@ -117,7 +125,7 @@ def lds_work(net, plan, slots_desc):
     record can stay in registers).  Returns per-trajectory-step counts:
     u8 (random byte gathers and stores), w4 (drawn words), rec16 (records) and
     tab8 (table entries), and where records and tables live ("lds" or
-    "global")."""
+    "global"); for a global image, the vector-memory reads of vmem_work."""
     n, p = net["n"], net["p"]
     f = (1.0 - p) ** n
     slot, is_table = plan.slots()
@@ -128,7 +136,95 @@ def lds_work(net, plan, slots_desc):
     n_tab = int(np.count_nonzero(is_table))
     return {"u8": f * (gathers + plan.info["n_kept"]), "w4": f * n_sel, "rec16": f * n_multi_fn,
             "tab8": f * n_tab, "image": "lds" if plan.info["image_in_lds"] else "global",
-            "state": "bits" if bits else "bytes"}
+            "state": "bits" if bits else "bytes",
+            "vmem": None if plan.info["image_in_lds"] else vmem_work(net, plan)}
+
+
+# plan blob header words (pbn_plan_header, uint32 little-endian)
+_H_N_PASSES, _H_IMAGE_BYTES, _H_IMAGE_OFF = 7, 12, 13
+_H_FN_UNITS, _H_FN_JSHIFT, _H_FN_HOFF, _H_FN_VAR = 26, 27, 28, 39
+_SLOT_TABLE, _SLOT_INLINE = 0x40000000, 0x20000000
+
+
+def vmem_work(net, plan, samples=32, seed=1):
+    """Vector-L1 accesses (64-byte units) one trajectory-step makes when the
+    plan image stays in global memory, from the plan's own slot records and
+    addresses.  Plans of more than two lane passes (streaming evaluation):
+    every pass reads its 64 lanes' 16-byte slot records (16 units); table
+    lanes read one table byte each, at a state-dependent offset (drawn
+    uniformly here), plus union words and choice records when the slot record
+    does not carry them; FN lanes and padded lanes read a choice record when
+    they select, then one or two 16-byte units of the chosen predictor record
+    (the choice drawn from the record's own thresholds).  Lanes of one read
+    that fall in the same unit make one access.  Plans of one or two passes
+    keep slot data in registers and skip the slot-record read.  Steps with a
+    perturbation (1 - f of them) read only Q words, not counted.  Returns
+    per-step accesses and wave-level read instructions."""
+    rng = np.random.default_rng(seed)
+    f = (1.0 - net["p"]) ** net["n"]
+    blob = plan.blob()
+    hdr = np.frombuffer(blob[:4 * 41].tobytes(), dtype="<u4").astype(np.int64)
+    n_passes, img, img_bytes = int(hdr[_H_N_PASSES]), int(hdr[_H_IMAGE_OFF]), int(hdr[_H_IMAGE_BYTES])
+    fn_units, fn_jshift, fn_hoff, fn_var = (int(hdr[i]) for i in (_H_FN_UNITS, _H_FN_JSHIFT, _H_FN_HOFF, _H_FN_VAR))
+    image = np.frombuffer(blob[img:img + img_bytes].tobytes(), dtype=np.uint8)
+    words = np.frombuffer(image[:image.size // 4 * 4].tobytes(), dtype="<u4").astype(np.int64)
+    rec = words[:256 * n_passes].reshape(-1, 4)          # 64 slot records of 16 bytes per pass
+    info, y, z = rec[:, 0], rec[:, 1], rec[:, 2]
+    table = (info & _SLOT_TABLE) != 0
+    inline = (info & _SLOT_INLINE) != 0
+    nmulti = (info >> 3) & 7
+    nu = (info >> 6) & 31
+    two = (nu > 5) if fn_var else np.full(info.shape, fn_units == 2)
+    jshift = np.where(two, 5, 4) if fn_var else np.full(info.shape, fn_jshift)
+    hoff = np.where(two, 16, 0) if fn_var else np.full(info.shape, fn_hoff)
+    streaming = n_passes > 2 or plan.opts.state_bits
+
+    def units(addr):
+        return len(np.unique(np.asarray(addr) // 64))
+
+    def choose(off):
+        w = words[off // 4: off // 4 + 4]
+        thr = w[1:1 + max(0, int(w[0] >> 24) - 1)]
+        return int(np.count_nonzero(int(rng.integers(0, 1 << 32)) >= thr))
+
+    acc = ins = 0.0
+    for p in range(n_passes):
+        sl = np.arange(64 * p, 64 * p + 64)
+        if streaming:
+            acc += units(16 * sl)
+            ins += 1
+        tl, fl = sl[table[sl]], sl[~table[sl]]
+        for _ in range(samples):
+            a = k = 0
+            if tl.size:
+                c = np.zeros(tl.size, dtype=np.int64)
+                wide = tl[~inline[tl]]
+                if wide.size:                 # union words, then members' choice records
+                    uw = int(np.max((nu[wide] + 1) // 2))
+                    for q in range(uw):
+                        a, k = a + units(y[wide] + 4 * q), k + 1
+                    for m in range(int(np.max(nmulti[wide]))):
+                        has = wide[nmulti[wide] > m]
+                        a, k = a + units(z[has] + 16 * m), k + 1
+                        for i, s_ in enumerate(has):
+                            c[np.searchsorted(tl, s_)] += choose(int(z[s_] + 16 * m)) * \
+                                ((int(rec[s_, 3]) >> (8 * m)) & 0xFF)
+                x = rng.integers(0, 1 << nu[tl])
+                a, k = a + units(y[tl] + 32 + (c << nu[tl]) + x), k + 1
+            if fl.size:
+                j = np.zeros(fl.size, dtype=np.int64)
+                sel = fl[nmulti[fl] > 0]
+                if sel.size:
+                    a, k = a + units(z[sel]), k + 1
+                    j[nmulti[fl] > 0] = [choose(int(z[s_])) for s_ in sel]
+                ua = y[fl] + (j << jshift[fl])
+                a, k = a + units(ua), k + 1
+                tw = two[fl]
+                if tw.any():
+                    a, k = a + units(ua[tw] + hoff[fl][tw]), k + 1
+            acc += a / samples
+            ins += k / samples
+    return {"accesses": f * acc, "instructions": f * ins}
 
 
 def measure_gather_rates(api, torch, plan):
@@ -146,7 +242,7 @@ def measure_gather_rates(api, torch, plan):
     # for packed-bit plans (whose gathers read words)
     lds_state = plan.info["state_bytes"] // (8 if plan.opts.state_bits else 1)
     state_bytes = max(128, 1 << int(math.ceil(math.log2(max(1, lds_state)))))
-    img_log2 = max(7, int(math.ceil(math.log2(max(16, plan.info["image_bytes"])))))
+    img_log2 = max(L1_PROBE_LOG2, int(math.ceil(math.log2(max(16, plan.info["image_bytes"])))))
     buf = torch.zeros(1 << img_log2, dtype=torch.uint8, device="cuda")
 
     def timed(fn):
@@ -170,12 +266,22 @@ def measure_gather_rates(api, torch, plan):
             api.check(L.pbn_probe_lds_gather(lg, width, pattern, iters, blocks, dsink, sp))
         out[name] = timed(lds_probe)
 
-    for name, width in (("global16_random", 16), ("global1_random", 1)):
-        def vmem_probe(width=width):
-            api.check(L.pbn_probe_vmem_gather(_lib.C.c_void_p(buf.data_ptr()), img_log2, width, iters // 4, blocks,
-                                              dsink, sp))
+    # global reads: a buffer that fits the vector L1 (every read hits: the
+    # ceiling), and one the size of the plan image (reads spread over all of it)
+    for name, (lg, width, pattern) in {"global16_rows": (L1_PROBE_LOG2, 16, 1),
+                                       "global16_random": (L1_PROBE_LOG2, 16, 0),
+                                       "global1_random": (L1_PROBE_LOG2, 1, 0),
+                                       "global16_image_random": (img_log2, 16, 0)}.items():
+        def vmem_probe(lg=lg, width=width, pattern=pattern):
+            api.check(L.pbn_probe_vmem_gather(_lib.C.c_void_p(buf.data_ptr()), lg, width, pattern, iters // 4,
+                                              blocks, dsink, sp))
         out[name] = timed(vmem_probe) / 4    # a quarter of the iterations per launch
+    # the random 16-byte probe in accesses (64-byte units) per second: its 64
+    # lanes fall in 64 random units of the L1-resident buffer, some shared
+    units_l1 = (1 << L1_PROBE_LOG2) // 64
+    out["l1_accesses"] = out["global16_random"] / 64 * units_l1 * (1 - (1 - 1 / units_l1) ** 64)
     out["state_buffer_bytes"] = state_bytes
+    out["l1_buffer_bytes"] = 1 << L1_PROBE_LOG2
     out["image_buffer_bytes"] = 1 << img_log2
     return out
 
@@ -203,8 +309,8 @@ def ceilings(w_ops, work, rates, traj_steps_per_s):
     t_lds = (work["u8"] / gather_rate + work["w4"] / rates["w4_swizzled"]
              + (work["rec16"] / rates["rec16_swizzled"] + work["tab8"] / rates["u8_random"]
                 if work["image"] == "lds" else 0.0))
-    t_vmem = (work["rec16"] / rates["global16_random"] + work["tab8"] / rates["global1_random"]
-              if work["image"] == "global" else 0.0)
+    vm = work.get("vmem")
+    t_vmem = vm["accesses"] / rates["l1_accesses"] if work["image"] == "global" and vm else 0.0
     out = {}
     for name, t in (("alu", t_alu), ("lds", t_lds), ("vmem", t_vmem)):
         if t > 0:
@@ -278,11 +384,14 @@ def run_step(api, torch, cfg, opts, plain, chunk, events, wpb=0, tpw=1):
 
 def tuned_opts_for(api, torch, nets, seed, ntraj=256, sample=4):
     """Autotune on a few networks spread over the size range; the options that
-    win most often are used for all of them (ties: the faster total)."""
+    win most often are used for all of them (ties: the faster total).  Also
+    returns, per sampled network, the fastest trial with one trajectory per
+    wavefront against the fastest with several (the batch kernel runs one)."""
     from paper_1605_00854_amd import autotune
     order = sorted(range(len(nets)), key=lambda k: nets[k]["n"])
     picks = [order[int(round(i * (len(order) - 1) / max(1, sample - 1)))] for i in range(sample)]
     votes = {}
+    tpw_trials = []
     for k in picks:
         net = nets[k]
         tg = [ps.non_leaf_targets(net, 2)]
@@ -290,12 +399,21 @@ def tuned_opts_for(api, torch, nets, seed, ntraj=256, sample=4):
         best, wpb, trials = autotune.tune(net, interest, tg, ntraj, seed=seed, probe_steps=500, quick=True,
                                           key=("multi", k, seed))
         key = tuple(sorted(best.items()))
-        rate = max(t["node_updates_per_s"] for t in trials if "node_updates_per_s" in t)
+        ok = [t for t in trials if "node_updates_per_s" in t]
+        rate = max(t["node_updates_per_s"] for t in ok)
         v = votes.setdefault(key, [0, 0.0, wpb])
         v[0] += 1
         v[1] += rate
+        one = max((t for t in ok if t.get("tpw", 1) == 1), key=lambda t: t["node_updates_per_s"])
+        many = [t for t in ok if t.get("tpw", 1) > 1]
+        row = {"n": int(net["n"]), "passes": one["passes"], "tpw1": one["node_updates_per_s"]}
+        if many:
+            m = max(many, key=lambda t: t["node_updates_per_s"])
+            row.update({"best_tpw": m["tpw"], "tpw_rate": m["node_updates_per_s"],
+                        "tpw_over_1": m["node_updates_per_s"] / one["node_updates_per_s"]})
+        tpw_trials.append(row)
     best = max(votes.items(), key=lambda kv: (kv[1][0], kv[1][1]))
-    return dict(best[0]), best[1][2]
+    return dict(best[0]), best[1][2], tpw_trials
 
 
 def config_compare(api, torch, name, chunk, tag=None):
@@ -341,6 +459,9 @@ def config_compare(api, torch, name, chunk, tag=None):
             leg["roofline"] = {**roofline_head(ceil, w_step * cfg.ntraj * avg_steps / avg_launch,
                                                cfg.ntraj * avg_steps / avg_launch),
                                "alu_frac": ceil["alu"]["frac"], "ceilings": ceil, "gather_rates": rates,
+                               "traffic": measured_traffic(name, o),
+                               "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                               "copy-calibrated)",
                                "kernel": "k_simulate", "ops_per_traj_step": w_step,
                                "avg_launch_ms": avg_launch * 1e3, "steps_per_launch": avg_steps}
         out[label] = leg
@@ -368,7 +489,7 @@ def bench_batch(args):
     results = {}
     for label, opts in (("product", None), ("plain", dict(reduce=0, group=0))):
         if opts is None:
-            opts, wpb = tuned_opts_for(api, torch, nets, 4)
+            opts, wpb, tpw_trials = tuned_opts_for(api, torch, nets, 4)
         else:
             wpb = 4
         t0 = time.perf_counter()
@@ -397,7 +518,8 @@ def bench_batch(args):
            "config": {"workload": f"C4: 512 random PBNs n~U[20,1500], 256 trajectories each, "
                                   f"{T} steps + {burn} burn-in, hipGraph of {passes} persistent passes"},
            "compare": results,
-           "product_over_plain": results["product"]["node_updates_per_s"] / results["plain"]["node_updates_per_s"]}
+           "product_over_plain": results["product"]["node_updates_per_s"] / results["plain"]["node_updates_per_s"],
+           "traj_per_wave_trials": tpw_trials}
     print(json.dumps(out))
 
 
@@ -409,15 +531,17 @@ def serve_compare(api, torch, nq, query_chunk):
     results = {}
     for label in ("product", "plain"):
         if label == "product":
-            opts, wpb = tuned_opts_for(api, torch, nets, 5)
+            opts, wpb, tpw_trials = tuned_opts_for(api, torch, nets, 5)
         else:
-            opts, wpb = dict(reduce=0, group=0), 4
+            opts, wpb, tpw_trials = dict(reduce=0, group=0), 4, None
         srv = serve.Server(nets, [1005000 + k for k in range(len(nets))], plan_opts=opts, traj_per_query=256,
                            chunk=query_chunk, burn_in=1000, min_counted=1000, max_steps=200000,
                            waves_per_block=wpb)
         qs = serve.poisson_queries(nets, nq, rate=200.0, seed=2005)
         m = srv.run(qs, realtime=True)
         m["plan"] = opts
+        if tpw_trials is not None:
+            m["traj_per_wave_trials"] = tpw_trials
         results[label] = m
     return results
 
@@ -734,7 +858,7 @@ def main():
                      "ceilings": ceil, "gather_rates": rates,
                      "alu": {"achieved": achieved / 1e12, "peak": PEAK_ALU / 1e12, "frac": achieved / PEAK_ALU,
                              "unit": "Tops/s (int32 VALU lane-ops)", "philox_slots_per_call": PHILOX_SLOTS},
-                     "traffic": measured_traffic(args.config) if best_opts == PLANS["reduction"] else None,
+                     "traffic": measured_traffic(args.config, best_opts),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "k_simulate", "ops_per_traj_step": w_step,
                      "avg_launch_ms": avg_launch * 1e3, "steps_per_launch": avg_steps,

@@ -535,15 +535,17 @@ pbn_status pbn_graph_destroy(pbn_graph* graph);
  *   2^log2_bytes-byte LDS buffer (7 <= log2_bytes <= 16) per workgroup;
  *   pattern 0: random aligned addresses (bank conflicts as they fall),
  *   pattern 1: the lanes of a wave read bank-distinct words of random rows.
- * pbn_probe_vmem_gather: random gathers of `width` bytes (1 or 16) from the
+ * pbn_probe_vmem_gather: gathers of `width` bytes (1 or 16) from the
  *   caller's device buffer of at least 2^log2_bytes bytes (4 <= log2_bytes <=
- *   30) through the vector L1 and L2.
+ *   30) through the vector L1 and L2; pattern 0: random aligned addresses,
+ *   pattern 1: lane L reads unit L of a random row of 64 x width bytes (a
+ *   coalesced read; the buffer must hold one row).
  * d_sink: one device word, written only by an improbable value (keeps the
  * reads).  Errors: PBN_EINVAL for out-of-range arguments, PBN_EHIP.         */
 pbn_status pbn_probe_lds_gather(uint32_t log2_bytes, uint32_t width, uint32_t pattern, uint32_t iters,
                                 uint32_t blocks, uint32_t* d_sink, void* stream);
-pbn_status pbn_probe_vmem_gather(const void* d_buf, uint32_t log2_bytes, uint32_t width, uint32_t iters,
-                                 uint32_t blocks, uint32_t* d_sink, void* stream);
+pbn_status pbn_probe_vmem_gather(const void* d_buf, uint32_t log2_bytes, uint32_t width, uint32_t pattern,
+                                 uint32_t iters, uint32_t blocks, uint32_t* d_sink, void* stream);
 
 #ifdef __cplusplus
 }

@@ -476,11 +476,10 @@ __device__ __forceinline__ uint32_t eval_slot(const SlotRegs<Shape<PM, UM>::XW, 
 // chosen predictor record, a one-predictor node's record); returns the
 // slot's output (member k in bit k) and the state position it writes.
 template <int PM, int UM, int MODE>
-__device__ __forceinline__ uint32_t eval_stream(const uint8_t* img, uint32_t slot, const uint8_t* cs, const uint8_t* rs,
-                                                const FnFmt& fm, uint32_t& spos, bool& table) {
+__device__ __forceinline__ uint32_t eval_stream(const uint4 rec, const uint8_t* img, uint32_t slot, const uint8_t* cs,
+                                                const uint8_t* rs, const FnFmt& fm, uint32_t& spos, bool& table) {
   constexpr int PW = Shape<PM, UM>::PW, TTW = Shape<PM, UM>::TTW, UW = Shape<PM, UM>::UW;
   constexpr bool G = (MODE & 2) != 0, LB = (MODE & 16) != 0;
-  const uint4 rec = img_u4<G>(img + 16u * slot);
   table = UM > 0 && (rec.x & PBN_SLOT_TABLE);
   if (UM > 0 && (rec.x & PBN_SLOT_TABLE)) {
     spos = 4u * slot;
@@ -544,6 +543,24 @@ __device__ __forceinline__ void store_slot(uint8_t* ns, uint32_t info, uint32_t 
     *reinterpret_cast<uint32_t*>(ns + spos) = __umul24(out, 0x204081u) & 0x01010101u;   // bit k -> byte k
   else
     ns[spos] = uint8_t(out);
+}
+
+// The keyed draws of one step of a plan with more than 64 Philox jobs per
+// step, 64 at a time (job j: the first chain word for j = 0, else SEL block
+// blk[j - 1]).  Job 0 is in the first round, and a step whose first chain
+// word makes it perturbation-only (u >= Q[n]) reads no selection draw, so
+// the later rounds are left out for it.
+__device__ __forceinline__ void fill_step_keyed(uint4* ring, const uint32_t* blk, uint32_t njobs, uint32_t traj,
+                                                uint32_t t, uint32_t lane, uint32_t k0, uint32_t k1, uint32_t qn_lo,
+                                                uint32_t qn_hi) {
+  for (uint32_t j = lane; j < njobs; j += 64u) {
+    const uint4 x = philox(traj, t, j ? blk[j - 1u] : 0u, j ? PBN_STREAM_SEL : PBN_STREAM_PERT, k0, k1);
+    ring[j] = x;
+    if (j < 64u) {   // the first round: every lane takes part (njobs > 64), lane 0 holds job 0
+      const uint32_t ulo = uniform(x.x), uhi = uniform(x.y);
+      if (uhi > qn_hi || (uhi == qn_hi && ulo >= qn_lo)) break;
+    }
+  }
 }
 
 // A perturbation-only step (u >= Q[n], Eq. 1): walk the skip chain over all
@@ -627,11 +644,14 @@ struct TrajArgs {
 // keyed draws; bit 3, the state held as one 64-bit wave-uniform word (bit b =
 // state byte b) instead of bytes in LDS: one-pass FN-only plans whose slot
 // bytes and zero word lie below 64, where s(t+1) is the pass's output ballot
-// (padded lanes output 0, so the zero word stays 0).
+// (padded lanes output 0, so the zero word stays 0); bit 5, with NREG = 0,
+// each lane pass's slot records are read while the previous pass evaluates
+// (one dependent global read less per pass for four more VGPRs).
 template <int PM, int UM, int NREG, int MODE>
 __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   constexpr int XW = Shape<PM, UM>::XW, TTW = Shape<PM, UM>::TTW;
   constexpr bool ALIAS = (MODE & 4) != 0;
+  constexpr bool kPrefetch = (MODE & 32) != 0 && NREG == 0 && !ALIAS;
   constexpr bool kCached = NREG == 1 || NREG == 2;
   constexpr bool kSingle = NREG != 0;   // one state buffer, updated in place
   constexpr int NR = kCached ? NREG : 1;
@@ -838,10 +858,10 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
       for (int r = 0; r < kFillRounds; ++r)
         if (lane + 64u * uint32_t(r) < scount * njobs)
           ring[lane + 64u * uint32_t(r)] = philox(traj, t + my_s[r], my_c2[r], my_c3[r], k0, k1);
+    } else if constexpr (ALIAS) {
+      for (uint32_t j = lane; j < njobs; j += 64u) ring[j] = philox(traj, t, j, PBN_STREAM_ALIAS, k0, k1);
     } else {
-      for (uint32_t j = lane; j < njobs; j += 64u)
-        ring[j] = ALIAS ? philox(traj, t, j, PBN_STREAM_ALIAS, k0, k1)
-                        : philox(traj, t, j ? blk[j - 1] : 0u, j ? PBN_STREAM_SEL : PBN_STREAM_PERT, k0, k1);
+      fill_step_keyed(ring, blk, njobs, traj, t, lane, k0, k1, qn_lo, qn_hi);
     }
     wave_sync();
     if constexpr (ALIAS) {
@@ -954,15 +974,24 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
             z = !never && mism == 0u;
           }
         } else {
+          constexpr bool G = (MODE & 2) != 0;
+          uint4 nrec = kPrefetch ? img_u4<G>(img + 16u * lane) : uint4{};
           for (uint32_t p = 0; p < npass; ++p) {
             if constexpr (ALIAS) {
               Regs r;
               load_slot<PM, UM, MODE>(r, img, p * 64u + lane, fm);
               store_slot<UM>(nsb, r.info, r.spos, eval_slot<PM, UM, MODE>(r, nullptr, img, csb, rs, fm));
             } else {
+              uint4 rec;
+              if constexpr (kPrefetch) {
+                rec = nrec;
+                if (p + 1u < npass) nrec = img_u4<G>(img + 16u * ((p + 1u) * 64u + lane));
+              } else {
+                rec = img_u4<G>(img + 16u * (p * 64u + lane));
+              }
               uint32_t spos;
               bool table;
-              const uint32_t out = eval_stream<PM, UM, MODE>(img, p * 64u + lane, csb, rs, fm, spos, table);
+              const uint32_t out = eval_stream<PM, UM, MODE>(rec, img, p * 64u + lane, csb, rs, fm, spos, table);
               store_slot<UM>(nsb, table ? PBN_SLOT_TABLE : 0u, spos, out);
             }
           }
@@ -1303,7 +1332,7 @@ __global__ void __launch_bounds__(1024) k_simulate(SimParams a) {
   t.record = a.record && tl < a.record_traj ? a.record + size_t(tl) * a.record_words : nullptr;
   t.record_words = a.record_words;
   t.gshift = a.gshift;
-  run_traj<PM, UM, NREG, (ALIAS ? 4 : 0) | (REGSTATE ? 8 : 0)>(t);
+  run_traj<PM, UM, NREG, (ALIAS ? 4 : 0) | (REGSTATE ? 8 : 0) | 32>(t);
 }
 
 // One network, K = a.tpw trajectories per wavefront (run_multi); NP lane
@@ -1450,8 +1479,7 @@ __device__ __forceinline__ void run_bits(const TrajArgs& a) {
         if (lane + 64u * uint32_t(r) < scount * njobs)
           ring[lane + 64u * uint32_t(r)] = philox(traj, t + my_s[r], my_c2[r], my_c3[r], k0, k1);
     } else {
-      for (uint32_t j = lane; j < njobs; j += 64u)
-        ring[j] = philox(traj, t, j ? blk[j - 1] : 0u, j ? PBN_STREAM_SEL : PBN_STREAM_PERT, k0, k1);
+      fill_step_keyed(ring, blk, njobs, traj, t, lane, k0, k1, qn_lo, qn_hi);
     }
     wave_sync();
     for (uint32_t s = 0; s < scount; ++s, ++t) {
@@ -1474,8 +1502,9 @@ __device__ __forceinline__ void run_bits(const TrajArgs& a) {
           const uint32_t flags = uniform(pinfo[p].flags);
           uint32_t spos;
           bool table;
-          const uint32_t out = eval_stream<PM, UM, M>(img, p * 64u + lane, reinterpret_cast<const uint8_t*>(cw), rs, fm,
-                                                      spos, table);
+          const uint4 rec = img_u4<(M & 2) != 0>(img + 16u * (p * 64u + lane));
+          const uint32_t out = eval_stream<PM, UM, M>(rec, img, p * 64u + lane, reinterpret_cast<const uint8_t*>(cw), rs,
+                                                      fm, spos, table);
           if (flags & PBN_PASS_TABLE) {
             // lane L's nibble at bits 4 (L mod 8) of word L / 8 of the segment
             uint32_t v = out << nib_shift;
@@ -1605,6 +1634,8 @@ __global__ void __launch_bounds__(1024) k_batch(BatchParams a, const pbn_work* _
       t.record = nullptr;
       t.record_words = 0;
       t.gshift = a.gshift;
+      // no slot-record prefetch (MODE bit 5): its four VGPRs would take
+      // this kernel from five to four waves per SIMD
       run_traj<PM, UM, 0, (PM == 7 ? 1 : 0) | 2>(t);
     }
   }

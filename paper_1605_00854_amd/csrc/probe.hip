@@ -73,21 +73,31 @@ __global__ void __launch_bounds__(kProbeThreads) k_probe_lds(uint32_t log2_bytes
   if (acc == 0x9E3779B9u) sink[0] = gid;   // keeps the reads; practically never stores
 }
 
-// Random gathers of WIDTH bytes (1 or 16) from a global buffer of 2^log2_bytes
-// bytes: the vector-memory path a plan image in global memory takes (16-byte
-// records, one-byte table entries).
+// Gathers of WIDTH bytes (1 or 16) from a global buffer of 2^log2_bytes bytes
+// through the vector L1 and L2: the path a plan image in global memory takes.
+// pattern 0: every lane reads a random aligned address (16-byte records,
+// one-byte table entries of scattered slots); pattern 1: lane L reads unit L
+// of a random row of 64 WIDTH bytes, the coalesced read of a pass's slot
+// records.  A buffer that fits the vector L1 gives the rate at which every
+// read hits it.
 template <int WIDTH>
 __global__ void __launch_bounds__(kProbeThreads) k_probe_vmem(const uint8_t* __restrict__ img, uint32_t log2_bytes,
-                                                             uint32_t iters, uint32_t* sink) {
+                                                             uint32_t pattern, uint32_t iters, uint32_t* sink) {
   const uint32_t gid = blockIdx.x * kProbeThreads + threadIdx.x;
+  const uint32_t lane = threadIdx.x & 63u;
+  constexpr uint32_t kRow = 64u * WIDTH;
   const uint32_t amask = ((1u << log2_bytes) - 1u) & ~uint32_t(WIDTH - 1);
+  const uint32_t rmask = pattern ? amask & ~(kRow - 1u) : amask;   // pattern 1: random row
   uint32_t a[kProbeStreams];
 #pragma unroll
-  for (int k = 0; k < kProbeStreams; ++k) a[k] = probe_hash(gid * kProbeStreams + k) & amask;
+  for (int k = 0; k < kProbeStreams; ++k) {
+    const uint32_t h = probe_hash(gid * kProbeStreams + k) & amask;
+    a[k] = pattern ? (h & rmask) | (lane * uint32_t(WIDTH)) : h;
+  }
   uint32_t acc = 0, step = probe_hash(blockIdx.x);
   for (uint32_t it = 0; it < iters; ++it) {
     step = step * 1664525u + 1013904223u;
-    const uint32_t d = step & amask;
+    const uint32_t d = step & rmask;
 #pragma unroll
     for (int k = 0; k < kProbeStreams; ++k) {
       if constexpr (WIDTH == 16) {
@@ -96,7 +106,7 @@ __global__ void __launch_bounds__(kProbeThreads) k_probe_vmem(const uint8_t* __r
       } else {
         acc += img[a[k]];
       }
-      a[k] ^= d;
+      a[k] ^= d;                              // stays aligned and in range; a row stays a row
     }
   }
   if (acc == 0x9E3779B9u) sink[0] = gid;
@@ -128,18 +138,21 @@ extern "C" pbn_status pbn_probe_lds_gather(uint32_t log2_bytes, uint32_t width, 
   return e == hipSuccess ? PBN_OK : probe_fail(PBN_EHIP, std::string("probe launch: ") + hipGetErrorString(e));
 }
 
-extern "C" pbn_status pbn_probe_vmem_gather(const void* d_buf, uint32_t log2_bytes, uint32_t width, uint32_t iters,
-                                            uint32_t blocks, uint32_t* d_sink, void* stream) {
+extern "C" pbn_status pbn_probe_vmem_gather(const void* d_buf, uint32_t log2_bytes, uint32_t width, uint32_t pattern,
+                                            uint32_t iters, uint32_t blocks, uint32_t* d_sink, void* stream) {
   pbn::clear_error();
   if (!d_buf || !d_sink) return probe_fail(PBN_EINVAL, "null argument");
   if (log2_bytes < 4 || log2_bytes > 30 || blocks == 0) return probe_fail(PBN_EINVAL, "bad buffer size or block count");
   if (width != 1 && width != 16) return probe_fail(PBN_EINVAL, "width must be 1 or 16 bytes");
+  if (pattern > 1) return probe_fail(PBN_EINVAL, "bad pattern");
+  if (pattern == 1 && (1u << log2_bytes) < 64u * width)
+    return probe_fail(PBN_EINVAL, "pattern 1 needs a buffer of at least one row (64 x width bytes)");
   if (width == 16)
     hipLaunchKernelGGL(k_probe_vmem<16>, dim3(blocks), dim3(kProbeThreads), 0, static_cast<hipStream_t>(stream),
-                       static_cast<const uint8_t*>(d_buf), log2_bytes, iters, d_sink);
+                       static_cast<const uint8_t*>(d_buf), log2_bytes, pattern, iters, d_sink);
   else
     hipLaunchKernelGGL(k_probe_vmem<1>, dim3(blocks), dim3(kProbeThreads), 0, static_cast<hipStream_t>(stream),
-                       static_cast<const uint8_t*>(d_buf), log2_bytes, iters, d_sink);
+                       static_cast<const uint8_t*>(d_buf), log2_bytes, pattern, iters, d_sink);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? PBN_OK : probe_fail(PBN_EHIP, std::string("probe launch: ") + hipGetErrorString(e));
 }

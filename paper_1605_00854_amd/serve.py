@@ -9,20 +9,22 @@ trajectories) whether its precision is met.  Because the keying and the chunk
 schedule depend only on the query, its result is bit-identical whether it runs
 alone or mixed with others; the mix only changes latency.
 
-Every tick advances all admitted queries by one chunk in a single persistent
-batched launch (pbn_batch_launch): queries that arrived while others were on
-the device join at the next tick as soon as their footprint (resident waves,
-LDS bytes, HBM bytes) fits, and leave when their precision is met.
-
-The device never waits for the host between ticks: tick k is enqueued (launch,
-then an asynchronous copy of every active query's counters into pinned host
-memory, then an event) before the host reads tick k-1's counters.  A query
-that meets its precision at tick k-1 is decided from that tick's copy and
-leaves before tick k+1 (the chunk it runs at tick k is discarded).  The work
-items, task list and control block stay on the device and are rewritten only
-when the set of active queries changes; the control block's step window
+Queries advance in lanes.  A lane holds the admitted queries of one chunk
+length and moves all of them by one chunk per persistent batched launch
+(pbn_batch_launch) on its own stream; lanes run concurrently and each starts
+its next launch as soon as the host has decided on its previous one, so a
+query on a small network never waits for the step latency of a large one.  A
+query's chunk is fixed by its own plan: the base chunk times the power of two
+(up to 2^(chunk_classes - 1)) that brings its estimated step cost closest to,
+without exceeding, that of the costliest resident network, so lanes take
+about equally long per launch.  Queries that arrive while others are on the
+device join their lane at its next launch as soon as their footprint
+(resident waves, LDS bytes, HBM bytes) fits, and leave when their precision
+is met.  A lane's work items, task list and control block stay on the device
+and are rewritten only when its set of queries changes; its step window
 advances on the device after each launch, and each item's step offset is
-fixed at the tick its query joined.
+fixed at the launch its query joined.  Counters come back through an
+asynchronous copy into pinned host memory and an event the host polls.
 """
 import hashlib
 import time
@@ -110,9 +112,35 @@ class _Resident:
         self.first[:first.size].copy_(torch.from_numpy(first.astype(np.int32)).pin_memory(), non_blocking=True)
 
 
+# Estimated cost of a perturbation-only step, in lane passes of an
+# unperturbed one: the skip-chain walk with its reads of Q and of the
+# position map (served networks: about 8 passes' worth per step)
+PERT_PASSES = 8.0
+
+
+class _Lane:
+    """Queries of one chunk length: one batched launch of `chunk` steps at a
+    time on the lane's own stream, with resident work items, task list and
+    control block."""
+
+    def __init__(self, torch, chunk):
+        self.chunk = int(chunk)
+        self.stream = torch.cuda.Stream()           # default priority
+        with torch.cuda.stream(self.stream):
+            self.res = _Resident(torch)
+            self.ctl = torch.tensor([0, 0, self.chunk, 0], dtype=torch.int32, device="cuda")
+        self.window = 0            # host mirror of the control block's step window
+        self.dirty = True          # the lane's query set changed since its items were written
+        self.active = []
+        self.ntasks = 0
+        self.plans_arr = None
+        self.inflight = None       # (queries, steps after the launch, pinned counts, event)
+        self.launches = 0
+
+
 class Server:
     def __init__(self, nets, net_seeds, *, plan_opts=None, traj_per_query=256, chunk=1000, burn_in=1000,
-                 min_counted=1000, max_steps=400000, waves_per_block=4, footprint=None):
+                 min_counted=1000, max_steps=400000, waves_per_block=4, footprint=None, chunk_classes=3):
         import torch
         self.torch = torch
         self.nets = nets
@@ -120,6 +148,7 @@ class Server:
         self.opts = dict(plan_opts or dict(reduce=1, group=0))
         self.ntraj = int(traj_per_query)
         self.chunk = int(chunk)
+        self.max_mult = 1 << max(0, int(chunk_classes) - 1)
         self.burn_in = int(burn_in)
         self.min_counted = int(min_counted)
         self.max_steps = int(max_steps)
@@ -127,17 +156,11 @@ class Server:
         self.fp = footprint or Footprint()
         self.plans = {}
         self.base_interest = [non_sink_nodes(net) for net in nets]
-        for k in range(len(nets)):
-            self._plan(k, ())
-        self.queue, self.active, self.done = [], [], []
+        self.cost_max = max(self._cost(k, self._plan(k, ())) for k in range(len(nets)))
+        self.queue, self.done = [], []
+        self.lanes = {}
         self.node_updates = 0
         self.ticks = 0
-        self.res = _Resident(torch)
-        self.ctl = torch.tensor([0, 0, self.chunk, 0], dtype=torch.int32, device="cuda")
-        self.window = 0            # host mirror of the control block's step window
-        self.dirty = True          # the active set changed since the items were written
-        self.ntasks = 0
-        self.inflight = None       # (queries, steps after the tick, pinned counts, event)
 
     # -- resident plans: interest = every node some predictor reads, plus the
     # nodes of queries that asked for a removed node
@@ -157,6 +180,22 @@ class Server:
             # a query on a node the reduction removed: prepare with that node kept
             plan = self._plan(k, [a for a, _ in targets])
             return plan, plan.targets([targets])
+
+    def _cost(self, k, plan):
+        """Estimated time of one trajectory-step, in lane passes: a step
+        without perturbation (probability (1-p)^n) evaluates every pass."""
+        net = self.nets[k]
+        f = (1.0 - float(net["p"])) ** int(net["n"])
+        return f * plan.info["n_passes"] + (1.0 - f) * PERT_PASSES
+
+    def chunk_of(self, k, plan):
+        """The query's chunk: the base chunk times the largest power of two
+        (at most max_mult) whose multiple of this plan's step cost stays
+        within the costliest resident network's."""
+        m, c = 1, self._cost(k, plan)
+        while 2 * m <= self.max_mult and 2 * m * c <= self.cost_max:
+            m *= 2
+        return self.chunk * m
 
     def footprint(self, plan):
         ring = plan.info["n_jobs"]
@@ -179,7 +218,13 @@ class Server:
             self.done.append(q)
             return
         q._plan, q._tg, q._need = plan, tg, need
+        q._chunk = self.chunk_of(q.net, plan)
         self.queue.append(q)
+
+    def _lane(self, chunk):
+        if chunk not in self.lanes:
+            self.lanes[chunk] = _Lane(self.torch, chunk)
+        return self.lanes[chunk]
 
     def _admit(self, now):
         while self.queue and self.fp.fits(self.queue[0]._need):
@@ -187,71 +232,76 @@ class Server:
             self.fp.take(q._need)
             q.status, q.admitted = "running", now
             q._seed = query_seed(self.net_seeds[q.net], q.qid)
+            # initial states and zero counters on the current stream; a lane
+            # waits for it before its next launch
             q._state = api.state_init(q._plan, q._seed, self.ntraj)
             q._counts = api.new_counts(1, self.ntraj)
             q._tg_dev = api._to_device_bytes(q._tg)
-            self.active.append(q)
-            self.dirty = True
+            lane = self._lane(q._chunk)
+            lane.active.append(q)
+            lane.dirty = True
 
-    def _write_items(self):
-        """Work items and tasks of the active set into the resident buffers.
-        Item k's step offset makes its steps (offset + window) continue from
-        the query's own step count."""
-        act = self.active
+    def _write_items(self, lane):
+        """Work items and tasks of the lane's queries into its resident
+        buffers.  Item k's step offset makes its steps (offset + window)
+        continue from the query's own step count."""
+        act = lane.active
         works = (_lib.pbn_work * len(act))()
         for k, q in enumerate(act):
-            off = (q.steps - self.window) & 0xFFFFFFFF
+            off = (q.steps - lane.window) & 0xFFFFFFFF
             works[k] = _lib.pbn_work(q._plan.device().data_ptr(), q._tg_dev.data_ptr(), q._state.data_ptr(),
                                      q._counts.data_ptr(), q._seed, 0, self.ntraj, self.burn_in, off)
-        self._plans_arr = (api.C.c_void_p * len(act))(*[q._plan.handle.value for q in act])
+        lane.plans_arr = (api.C.c_void_p * len(act))(*[q._plan.handle.value for q in act])
         ntraj = np.full(len(act), self.ntraj, dtype=np.uint32)
         nt = api.C.c_uint32()
         L = _lib.lib()
-        _lib.check(L.pbn_batch_tasks(self._plans_arr, api._ptr(ntraj, api.C.c_uint32), len(act), self.wpb, None,
+        _lib.check(L.pbn_batch_tasks(lane.plans_arr, api._ptr(ntraj, api.C.c_uint32), len(act), self.wpb, None,
                                      None, api.C.byref(nt)))
         tasks = np.zeros(nt.value, dtype=np.uint32)
         first = np.zeros(nt.value, dtype=np.uint32)
-        _lib.check(L.pbn_batch_tasks(self._plans_arr, api._ptr(ntraj, api.C.c_uint32), len(act), self.wpb,
+        _lib.check(L.pbn_batch_tasks(lane.plans_arr, api._ptr(ntraj, api.C.c_uint32), len(act), self.wpb,
                                      api._ptr(tasks, api.C.c_uint32), api._ptr(first, api.C.c_uint32),
                                      api.C.byref(nt)))
-        self.res.upload(works, tasks, first)
-        self.ntasks = nt.value
-        self.dirty = False
+        lane.res.upload(works, tasks, first)
+        lane.ntasks = nt.value
+        lane.dirty = False
 
-    def _enqueue(self):
-        """Tick: one batched launch of every active query, then an asynchronous
-        copy of their counters and an event."""
+    def _enqueue(self, lane):
+        """One launch of the lane: every query of it advances one chunk; then an
+        asynchronous copy of their counters and an event, all on its stream."""
         torch = self.torch
-        if self.dirty:
-            self._write_items()
-        act = list(self.active)
-        L = _lib.lib()
-        _lib.check(L.pbn_batch_launch(self._plans_arr, len(act), api._dptr(self.res.items),
-                                      api._dptr(self.res.tasks), api._dptr(self.res.first), self.ntasks,
-                                      api._dptr(self.ctl), self.wpb, api._stream(None)))
-        self.window = (self.window + self.chunk) & 0xFFFFFFFF
-        for q in act:
-            q.steps += self.chunk
-            self.node_updates += self.ntraj * self.chunk * q._plan.n
-        counts = torch.cat([q._counts.view(-1) for q in act])
-        host = torch.empty(counts.shape, dtype=counts.dtype, pin_memory=True)
-        host.copy_(counts, non_blocking=True)
-        ev = torch.cuda.Event()
-        ev.record()
+        lane.stream.wait_stream(torch.cuda.current_stream())   # states of newly admitted queries
+        with torch.cuda.stream(lane.stream):
+            if lane.dirty:
+                self._write_items(lane)
+            act = list(lane.active)
+            L = _lib.lib()
+            _lib.check(L.pbn_batch_launch(lane.plans_arr, len(act), api._dptr(lane.res.items),
+                                          api._dptr(lane.res.tasks), api._dptr(lane.res.first), lane.ntasks,
+                                          api._dptr(lane.ctl), self.wpb, api._stream(lane.stream)))
+            lane.window = (lane.window + lane.chunk) & 0xFFFFFFFF
+            for q in act:
+                q.steps += lane.chunk
+                self.node_updates += self.ntraj * lane.chunk * q._plan.n
+            counts = torch.cat([q._counts.view(-1) for q in act])
+            host = torch.empty(counts.shape, dtype=counts.dtype, pin_memory=True)
+            host.copy_(counts, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(lane.stream)
+        lane.launches += 1
         self.ticks += 1
-        return act, [q.steps for q in act], host, ev
+        lane.inflight = (act, [q.steps for q in act], host, ev)
 
-    def _decide(self, tick, now_fn):
-        """Decisions on one finished tick's counters; finished queries leave."""
-        act, steps, host, ev = tick
+    def _decide(self, lane, now_fn):
+        """Decisions on the lane's finished launch; finished queries leave."""
+        act, steps, host, ev = lane.inflight
+        lane.inflight = None
         ev.synchronize()
         now = now_fn()
         counts = host.numpy()
         per = 3 * self.ntraj
         leaving = set()
         for k, (q, st) in enumerate(zip(act, steps)):
-            if q.status != "running":
-                continue
             counted = st - self.burn_in
             c = counts[k * per:(k + 1) * per].reshape(self.ntraj, 3)
             finished = False
@@ -266,27 +316,40 @@ class Server:
                     finished = True
             if finished:
                 q.finished = now
-                q.steps = st                 # the decision's step count (a later chunk may have run)
                 q.result["counts"] = c.copy()
                 self.fp.give(q._need)
                 self.done.append(q)
                 leaving.add(id(q))
+                for name in ("_state", "_counts", "_tg_dev"):
+                    setattr(q, name, None)
         if leaving:
-            for q in self.active:
-                if id(q) in leaving:
-                    for name in ("_state", "_counts", "_tg_dev"):
-                        setattr(q, name, None)
-            self.active = [q for q in self.active if id(q) not in leaving]
-            self.dirty = True
+            lane.active = [q for q in lane.active if id(q) not in leaving]
+            lane.dirty = True
 
-    def tick(self, now_fn):
-        """Admit, enqueue the next tick, then decide on the previous one."""
+    def busy(self):
+        return any(lane.active or lane.inflight is not None for lane in self.lanes.values())
+
+    def tick(self, now_fn, wait=False):
+        """One scheduling round: decide on every lane whose launch has
+        finished (with wait, on the oldest one in flight whatever its state),
+        admit queued queries that fit, launch every idle lane that holds
+        queries.  Returns whether a decision was taken or a launch made."""
+        moved = False
+        if wait:
+            flying = [lane for lane in self.lanes.values() if lane.inflight is not None]
+            if flying:
+                self._decide(min(flying, key=lambda ln: ln.launches), now_fn)
+                moved = True
+        for lane in self.lanes.values():
+            if lane.inflight is not None and lane.inflight[3].query():
+                self._decide(lane, now_fn)
+                moved = True
         self._admit(now_fn())
-        nxt = self._enqueue() if self.active else None
-        if self.inflight is not None:
-            self._decide(self.inflight, now_fn)
-        self.inflight = nxt
-        return nxt is not None
+        for lane in self.lanes.values():
+            if lane.inflight is None and lane.active:
+                self._enqueue(lane)
+                moved = True
+        return moved
 
     def run(self, queries, realtime=True):
         """Serve `queries` (arrival times in seconds).  Returns the metrics dict."""
@@ -294,13 +357,17 @@ class Server:
         t0 = time.perf_counter()
         now = (lambda: time.perf_counter() - t0) if realtime else (lambda: float(self.ticks))
         i = 0
-        while i < len(pending) or self.queue or self.active or self.inflight is not None:
+        while i < len(pending) or self.queue or self.busy():
             tnow = now()
             while i < len(pending) and (pending[i].arrival <= tnow or not realtime):
                 self.submit(pending[i], tnow)
                 i += 1
-            if not self.tick(now) and i < len(pending) and realtime:
-                time.sleep(max(0.0, min(0.01, pending[i].arrival - now())))
+            moved = self.tick(now, wait=not realtime)
+            if realtime and not moved:
+                # nothing finished and nothing to launch: a short pause, or
+                # until the next arrival when the device is idle
+                pause = 1e-4 if self.busy() or i >= len(pending) else pending[i].arrival - now()
+                time.sleep(max(0.0, min(0.01, pause)))
         self.torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         return self.metrics(wall)
@@ -317,6 +384,7 @@ class Server:
             "node_updates_per_s": self.node_updates / wall if wall > 0 else None,
             "wall_s": wall,
             "ticks": self.ticks,
+            "lanes": {str(c): lane.launches for c, lane in sorted(self.lanes.items())},
         }
 
 

@@ -64,6 +64,29 @@ def test_results_identical_alone_and_in_mix():
         assert a.result["p_hat"] == b.result["p_hat"]
 
 
+def test_chunk_lanes_results_identical_alone_and_in_mix():
+    """With a large network resident, queries on the small ones take longer
+    chunks (their own lanes, launched concurrently on separate streams); each
+    query's chunk depends only on its plan, so results stay the same alone."""
+    nets = small_nets() + [ps.medium_c2(n=1500, p=1e-4, seed=5)]
+    srv = make_server(nets)
+    chunks = {k: srv.chunk_of(k, srv._plan(k, ())) for k in range(len(nets))}
+    assert chunks[4] == 400 and len(set(chunks.values())) >= 2, chunks
+    qs = serve.poisson_queries(nets, 14, rate=1000.0, seed=12, precisions=(0.04, 0.06))
+    say("[gpu] serving 14 queries over chunk lanes")
+    m = srv.run(qs, realtime=False)
+    assert m["done"] + m["max_steps"] == 14, m
+    assert len(m["lanes"]) >= 2, m
+    mixed = {q.qid: q for q in srv.done}
+    for q in serve.poisson_queries(nets, 14, rate=1000.0, seed=12, precisions=(0.04, 0.06)):
+        alone = make_server(nets)
+        alone.run([q], realtime=False)
+        a, b = alone.done[0], mixed[q.qid]
+        assert a._chunk == b._chunk and a.steps == b.steps and a.steps % a._chunk == 0, (q.qid, a.steps, a._chunk)
+        assert np.array_equal(a.result["counts"], b.result["counts"]), q.qid
+        assert a.result["p_hat"] == b.result["p_hat"], q.qid
+
+
 def test_resident_plans_follow_the_network_not_generator_metadata():
     """The resident plan's interest set is every node some predictor reads, so
     Definition 1 removes the sinks whether or not the network carries the
@@ -96,8 +119,8 @@ def test_admission_respects_budget_and_rejects_oversize():
     seen = []
     orig_tick = srv.tick
 
-    def tick(now_fn):
-        r = orig_tick(now_fn)
+    def tick(now_fn, **kw):
+        r = orig_tick(now_fn, **kw)
         seen.append(srv.fp.used.copy())
         assert np.all(srv.fp.used <= cap + 1e-9)
         return r
