@@ -766,7 +766,9 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   wave_sync();
 
   // fixed Philox job of this lane when one fill covers several steps
-  const bool small_jobs = njobs <= 64u;
+  // plans whose slot data stay in registers have at most 64 jobs per step
+  // (the host runs larger ones in the streaming form)
+  const bool small_jobs = kCached || njobs <= 64u;
   const uint32_t bsteps = small_jobs ? min(fill, 32u) : 1u;   // steps per fill
   // a fill takes up to kFillRounds calls per lane: call lane + 64 r of a fill
   // is job (lane + 64 r) mod n_jobs of step (lane + 64 r) / n_jobs
@@ -1788,33 +1790,35 @@ pbn_status launch_sim(const SimParams& p, uint32_t blocks, uint32_t lds, hipStre
 }
 
 // Instantiation choice: the smallest gather widths that cover the plan.
+// nreg: 1 or 2, the lane passes whose slot data stay in registers; 0, the
+// streaming form.
 template <bool IMG_LDS, int PM, int UM, bool ALIAS>
-pbn_status dispatch_nreg(const SimParams& p, uint32_t npass, bool reg, uint32_t blocks, uint32_t lds, hipStream_t s) {
+pbn_status dispatch_nreg(const SimParams& p, uint32_t nreg, bool reg, uint32_t blocks, uint32_t lds, hipStream_t s) {
   if constexpr (UM == 0 && !ALIAS) {
     // one pass, every state byte below 64: the state lives in a register
     if (reg) return launch_sim<IMG_LDS, PM, 0, 1, false, true>(p, blocks, lds, s);
   }
-  if (npass == 1) return launch_sim<IMG_LDS, PM, UM, 1, ALIAS>(p, blocks, lds, s);
-  if (npass == 2) return launch_sim<IMG_LDS, PM, UM, 2, ALIAS>(p, blocks, lds, s);
+  if (nreg == 1) return launch_sim<IMG_LDS, PM, UM, 1, ALIAS>(p, blocks, lds, s);
+  if (nreg == 2) return launch_sim<IMG_LDS, PM, UM, 2, ALIAS>(p, blocks, lds, s);
   return launch_sim<IMG_LDS, PM, UM, 0, ALIAS>(p, blocks, lds, s);
 }
 
 template <bool IMG_LDS, int PM, bool ALIAS>
-pbn_status dispatch_um(const SimParams& p, uint32_t umax, uint32_t npass, bool reg, uint32_t blocks, uint32_t lds,
+pbn_status dispatch_um(const SimParams& p, uint32_t umax, uint32_t nreg, bool reg, uint32_t blocks, uint32_t lds,
                        hipStream_t s) {
-  if (umax == 0) return dispatch_nreg<IMG_LDS, PM, 0, ALIAS>(p, npass, reg, blocks, lds, s);
+  if (umax == 0) return dispatch_nreg<IMG_LDS, PM, 0, ALIAS>(p, nreg, reg, blocks, lds, s);
   if constexpr (!ALIAS) {
-    if (umax <= 6) return dispatch_nreg<IMG_LDS, PM, 6, ALIAS>(p, npass, false, blocks, lds, s);
+    if (umax <= 6) return dispatch_nreg<IMG_LDS, PM, 6, ALIAS>(p, nreg, false, blocks, lds, s);
   }
-  if (umax <= 8) return dispatch_nreg<IMG_LDS, PM, 8, ALIAS>(p, npass, false, blocks, lds, s);
-  return dispatch_nreg<IMG_LDS, PM, 16, ALIAS>(p, npass, false, blocks, lds, s);
+  if (umax <= 8) return dispatch_nreg<IMG_LDS, PM, 8, ALIAS>(p, nreg, false, blocks, lds, s);
+  return dispatch_nreg<IMG_LDS, PM, 16, ALIAS>(p, nreg, false, blocks, lds, s);
 }
 
 template <bool IMG_LDS, bool ALIAS>
-pbn_status dispatch_pm(const SimParams& p, uint32_t pmax, uint32_t umax, uint32_t npass, bool reg, uint32_t blocks,
+pbn_status dispatch_pm(const SimParams& p, uint32_t pmax, uint32_t umax, uint32_t nreg, bool reg, uint32_t blocks,
                        uint32_t lds, hipStream_t s) {
-  if (pmax <= 5) return dispatch_um<IMG_LDS, 5, ALIAS>(p, umax, npass, reg, blocks, lds, s);
-  return dispatch_um<IMG_LDS, 7, ALIAS>(p, umax, npass, reg, blocks, lds, s);
+  if (pmax <= 5) return dispatch_um<IMG_LDS, 5, ALIAS>(p, umax, nreg, reg, blocks, lds, s);
+  return dispatch_um<IMG_LDS, 7, ALIAS>(p, umax, nreg, reg, blocks, lds, s);
 }
 
 template <bool IMG_LDS, int PM, int UM>
@@ -1911,10 +1915,13 @@ pbn_status simulate_common(bool plain, const pbn_plan* plan, const void* d_plan,
   if (bits && (tpw > 1u || (launch && launch->d_record)))
     return fail(PBN_EINVAL, "plans with the packed-bit state run one trajectory per wave without recording");
   const uint32_t mfill = tpw > 1u ? multi_fill_steps(plan->n_jobs, tpw) : 0u;
+  // slot data of plans of one or two lane passes stay in registers, unless a
+  // step needs more than 64 Philox jobs (then the streaming form runs them)
+  const bool cached = plan->info.n_passes <= 2u && plan->n_jobs <= 64u;
   const uint32_t ring_bytes = 16u * (plan->n_jobs <= 64 ? std::min(plan->fill_steps, 32u) * plan->n_jobs : plan->n_jobs);
   const uint32_t wave_bytes = tpw > 1u ? tpw * 4u * ((plan->state_dwords + 3u) & ~3u) + 16u + 16u * mfill * tpw * plan->n_jobs
                               : bits   ? 8u * ((ph->state_words + 3u) & ~3u) + ring_bytes
-                                       : wave_lds_bytes(plan, plan->info.n_passes <= 2u);
+                                       : wave_lds_bytes(plan, cached);
   const bool img_lds = plan->info.image_in_lds != 0;
   const uint32_t img = img_lds ? ((plan->info.image_bytes + 15u) & ~15u) : 0u;
   uint32_t wpb = launch && launch->waves_per_block ? launch->waves_per_block : 4u;
@@ -1969,12 +1976,13 @@ pbn_status simulate_common(bool plain, const pbn_plan* plan, const void* d_plan,
   // keep the state in a register (padded lanes' bytes, above the zero word,
   // are never read and stay 0)
   const uint32_t zero_pos = reinterpret_cast<const pbn_plan_header*>(plan->blob.data())->zero_pos;
-  const bool reg = npass == 1 && umax == 0 && !plan->sampling && zero_pos + 4u <= 64u;
+  const bool reg = cached && npass == 1 && umax == 0 && !plan->sampling && zero_pos + 4u <= 64u;
+  const uint32_t nreg = cached ? npass : 0u;
   if (plan->sampling)
-    return img_lds ? dispatch_pm<true, true>(p, pmax, umax, npass, false, blocks, lds, s)
-                   : dispatch_pm<false, true>(p, pmax, umax, npass, false, blocks, lds, s);
-  return img_lds ? dispatch_pm<true, false>(p, pmax, umax, npass, reg, blocks, lds, s)
-                 : dispatch_pm<false, false>(p, pmax, umax, npass, reg, blocks, lds, s);
+    return img_lds ? dispatch_pm<true, true>(p, pmax, umax, nreg, false, blocks, lds, s)
+                   : dispatch_pm<false, true>(p, pmax, umax, nreg, false, blocks, lds, s);
+  return img_lds ? dispatch_pm<true, false>(p, pmax, umax, nreg, reg, blocks, lds, s)
+                 : dispatch_pm<false, false>(p, pmax, umax, nreg, reg, blocks, lds, s);
 }
 
 }  // namespace

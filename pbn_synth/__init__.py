@@ -172,6 +172,36 @@ def with_detached_modules(core, modules, size, seed, nparents=(2, 4)):
     return net
 
 
+def interleaved_cone(n_core=100, n_other=400, p=2e-3, seed=19):
+    """A core of n_core nodes whose predictors read only core nodes, and
+    n_other nodes that read the core and one another, their ids interleaved
+    at random (ids 0, 1, 2 are in the core).  Every node has 2-3 predictors of
+    1-3 parents.  The cone of influence of core targets lies in the core,
+    while the core's multi-predictor nodes are spread over the whole rank
+    order, so their selection-draw blocks are many."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = n_core + n_other
+    rest = rng.permutation(np.arange(3, n))
+    core = np.sort(np.concatenate([np.arange(3), rest[:n_core - 3]]))
+    is_core = np.zeros(n, dtype=bool)
+    is_core[core] = True
+    everyone = np.arange(n)
+    functions = []
+    for i in range(n):
+        l = int(rng.integers(2, 4))
+        probs = rng.dirichlet(np.ones(l))
+        pool = core if is_core[i] else everyone
+        fl = []
+        for j in range(l):
+            k = int(rng.integers(1, 4))
+            parents = rng.choice(pool, size=k, replace=False)
+            fl.append((probs[j], parents.tolist(), _draw_table(rng, k)))
+        functions.append(fl)
+    net = assemble(n, p, functions)
+    net["designated_leaves"] = np.zeros(0, dtype=np.uint32)
+    return net
+
+
 def planner_population(count, seed):
     """Networks spread over the ranges of the paper's experiments (Section
     4.1): n ~ U[100, 1500], leaf fraction ~ U[0, 0.9], 1..lmax predictors of

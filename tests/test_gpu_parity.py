@@ -65,6 +65,7 @@ NETS = {
     "modules": lambda: ps.with_detached_modules(ps.medium_c2(n=60, p=3e-3, seed=16), 3, 20, seed=17),
     "wide40": lambda: ps.random_pbn(40, 1e-2, 18, nfn=lambda r: int(r.integers(1, 4)),
                                     nparents=lambda r: int(r.integers(1, 8)), leaf_frac=0.1),
+    "interleaved": ps.interleaved_cone,
 }
 
 
@@ -300,6 +301,17 @@ def test_packed_bit_state_matches_the_oracle(case):
     plan = check(name, globals()[opts], seed, traj0, ntraj, chunks, count_from, plain, wpb)
     if opts in ("BITS_GROUPED", "BITS_TUNED", "BITS_MULTI") and name != "c2_hot":
         assert plan.info["n_table_slots"] > 0
+
+
+@pytest.mark.parametrize("opts,seed,traj0,ntraj,chunks,count_from,plain,wpb",
+                         [(CONE, 20, 0, 24, (300,), 0, True, 0), (CONE_GROUPED, 21, 3, 17, (150, 90), 40, False, 2)],
+                         ids=["cone", "cone-grouped"])
+def test_short_plans_with_many_draw_blocks_match_the_oracle(opts, seed, traj0, ntraj, chunks, count_from, plain, wpb):
+    """Plans of one or two lane passes whose steps need more than 64 Philox
+    calls (kept nodes spread over the rank order of a larger network) run in
+    the streaming form: trajectories and counters equal the oracle's."""
+    plan = check("interleaved", opts, seed, traj0, ntraj, chunks, count_from, plain, wpb)
+    assert plan.info["n_passes"] <= 2 and plan.info["n_jobs"] > 64, plan.info
 
 
 MULTI_CASES = [
