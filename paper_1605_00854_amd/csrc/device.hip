@@ -525,13 +525,19 @@ __device__ __forceinline__ uint32_t eval_stream(const uint4 rec, const uint8_t* 
 // of its chosen predictor (one-predictor lanes and padded lanes choose 0: their
 // thresholds are never reached), with no branch between lanes that select and
 // lanes that do not, so the loads of several passes can be in flight together.
-template <int PM, int UM, int MODE>
+// SEL false: a pass without multi-predictor slots, where every lane takes
+// predictor 0 without reading a drawn word.
+template <int PM, int UM, int MODE, bool SEL = true>
 __device__ __forceinline__ uint32_t eval_fn_all(const SlotRegs<Shape<PM, UM>::XW, Shape<PM, UM>::TTW>& r,
                                                 const NegThr& nt, const uint8_t* img, const uint8_t* cs,
                                                 const uint8_t* rs, const FnFmt& fm, unsigned long long st = 0ull,
                                                 const uint32_t* pre = nullptr) {
-  const uint32_t w = pre ? *pre : *reinterpret_cast<const uint32_t*>(rs + (r.draw & 0xFFFFFFu));
-  const auto f = load_fn<PM, UM, MODE>(img, r.base, choose_neg(w, nt), fm, r.info);
+  uint32_t j = 0u;
+  if constexpr (SEL) {
+    const uint32_t w = pre ? *pre : *reinterpret_cast<const uint32_t*>(rs + (r.draw & 0xFFFFFFu));
+    j = choose_neg(w, nt);
+  }
+  const auto f = load_fn<PM, UM, MODE>(img, r.base, j, fm, r.info);
   return eval_fn<PM, UM, (MODE & 8) != 0>(f, cs, fm.sh, st);
 }
 
@@ -646,13 +652,16 @@ struct TrajArgs {
 // bytes and zero word lie below 64, where s(t+1) is the pass's output ballot
 // (padded lanes output 0, so the zero word stays 0); bit 5, with NREG = 0,
 // each lane pass's slot records are read while the previous pass evaluates
-// (one dependent global read less per pass for four more VGPRs).
+// (one dependent global read less per pass for four more VGPRs); bit 7, with
+// NREG = 1 or 2 and FN-only keyed plans, the last register-held pass holds no
+// multi-predictor slot (no drawn word read, no threshold compare there).
 template <int PM, int UM, int NREG, int MODE>
 __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   constexpr int XW = Shape<PM, UM>::XW, TTW = Shape<PM, UM>::TTW;
   constexpr bool ALIAS = (MODE & 4) != 0;
   constexpr bool kPrefetch = (MODE & 32) != 0 && NREG == 0 && !ALIAS;
   constexpr bool kCached = NREG == 1 || NREG == 2;
+  constexpr bool kLastNoSel = (MODE & 128) != 0 && kCached && UM == 0 && !ALIAS;
   constexpr bool kSingle = NREG != 0;   // one state buffer, updated in place
   constexpr int NR = kCached ? NREG : 1;
   // FN-only plans with register-held slots read target values from the pass
@@ -953,8 +962,10 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
 #pragma unroll
           for (int p = 0; p < NREG; ++p) {
             if constexpr (UM == 0 && !ALIAS)
-              out[p] = eval_fn_all<PM, UM, MODE>(cached[p], nthr[p], img, csb, rs, fm, rst,
-                                                 kRegState ? &wcur : nullptr);
+              out[p] = kLastNoSel && p == NREG - 1   // constant once the loop is unrolled
+                           ? eval_fn_all<PM, UM, MODE, false>(cached[p], nthr[p], img, csb, rs, fm, rst)
+                           : eval_fn_all<PM, UM, MODE>(cached[p], nthr[p], img, csb, rs, fm, rst,
+                                                       kRegState ? &wcur : nullptr);
             else
               out[p] = eval_slot<PM, UM, MODE>(cached[p], &nthr[p], img, csb, rs, fm);
           }
@@ -1298,7 +1309,7 @@ __device__ __forceinline__ void run_multi(const MultiArgs& a) {
 // One network: one wavefront per trajectory, the plan image staged in LDS when
 // it fits (IMG_LDS), shared by the workgroup's waves.  ALIAS: the plan's alias
 // sampling draws.
-template <bool IMG_LDS, int PM, int UM, int NREG, bool ALIAS, bool REGSTATE = false>
+template <bool IMG_LDS, int PM, int UM, int NREG, bool ALIAS, bool REGSTATE = false, bool NOSEL = false>
 __global__ void __launch_bounds__(1024) k_simulate(SimParams a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   const pbn_plan_header* H = reinterpret_cast<const pbn_plan_header*>(a.blob);
@@ -1334,7 +1345,7 @@ __global__ void __launch_bounds__(1024) k_simulate(SimParams a) {
   t.record = a.record && tl < a.record_traj ? a.record + size_t(tl) * a.record_words : nullptr;
   t.record_words = a.record_words;
   t.gshift = a.gshift;
-  run_traj<PM, UM, NREG, (ALIAS ? 4 : 0) | (REGSTATE ? 8 : 0) | 32>(t);
+  run_traj<PM, UM, NREG, (ALIAS ? 4 : 0) | (REGSTATE ? 8 : 0) | 32 | (NOSEL ? 128 : 0)>(t);
 }
 
 // One network, K = a.tpw trajectories per wavefront (run_multi); NP lane
@@ -1775,9 +1786,9 @@ uint32_t wave_lds_bytes(const pbn_plan* plan, bool single) {
   return (single ? 4u : 8u) * ((plan->state_dwords + 3u) & ~3u) + 16u * ring;
 }
 
-template <bool IMG_LDS, int PM, int UM, int NREG, bool ALIAS, bool REGSTATE = false>
+template <bool IMG_LDS, int PM, int UM, int NREG, bool ALIAS, bool REGSTATE = false, bool NOSEL = false>
 pbn_status launch_sim(const SimParams& p, uint32_t blocks, uint32_t lds, hipStream_t stream) {
-  auto* fn = k_simulate<IMG_LDS, PM, UM, NREG, ALIAS, REGSTATE>;
+  auto* fn = k_simulate<IMG_LDS, PM, UM, NREG, ALIAS, REGSTATE, NOSEL>;
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1791,12 +1802,16 @@ pbn_status launch_sim(const SimParams& p, uint32_t blocks, uint32_t lds, hipStre
 
 // Instantiation choice: the smallest gather widths that cover the plan.
 // nreg: 1 or 2, the lane passes whose slot data stay in registers; 0, the
-// streaming form.
+// streaming form.  lastsel: the last of the nreg passes holds a
+// multi-predictor slot.
 template <bool IMG_LDS, int PM, int UM, bool ALIAS>
-pbn_status dispatch_nreg(const SimParams& p, uint32_t nreg, bool reg, uint32_t blocks, uint32_t lds, hipStream_t s) {
+pbn_status dispatch_nreg(const SimParams& p, uint32_t nreg, bool lastsel, bool reg, uint32_t blocks, uint32_t lds,
+                         hipStream_t s) {
   if constexpr (UM == 0 && !ALIAS) {
     // one pass, every state byte below 64: the state lives in a register
     if (reg) return launch_sim<IMG_LDS, PM, 0, 1, false, true>(p, blocks, lds, s);
+    if (!lastsel && nreg == 1) return launch_sim<IMG_LDS, PM, 0, 1, false, false, true>(p, blocks, lds, s);
+    if (!lastsel && nreg == 2) return launch_sim<IMG_LDS, PM, 0, 2, false, false, true>(p, blocks, lds, s);
   }
   if (nreg == 1) return launch_sim<IMG_LDS, PM, UM, 1, ALIAS>(p, blocks, lds, s);
   if (nreg == 2) return launch_sim<IMG_LDS, PM, UM, 2, ALIAS>(p, blocks, lds, s);
@@ -1804,21 +1819,21 @@ pbn_status dispatch_nreg(const SimParams& p, uint32_t nreg, bool reg, uint32_t b
 }
 
 template <bool IMG_LDS, int PM, bool ALIAS>
-pbn_status dispatch_um(const SimParams& p, uint32_t umax, uint32_t nreg, bool reg, uint32_t blocks, uint32_t lds,
-                       hipStream_t s) {
-  if (umax == 0) return dispatch_nreg<IMG_LDS, PM, 0, ALIAS>(p, nreg, reg, blocks, lds, s);
+pbn_status dispatch_um(const SimParams& p, uint32_t umax, uint32_t nreg, bool lastsel, bool reg, uint32_t blocks,
+                       uint32_t lds, hipStream_t s) {
+  if (umax == 0) return dispatch_nreg<IMG_LDS, PM, 0, ALIAS>(p, nreg, lastsel, reg, blocks, lds, s);
   if constexpr (!ALIAS) {
-    if (umax <= 6) return dispatch_nreg<IMG_LDS, PM, 6, ALIAS>(p, nreg, false, blocks, lds, s);
+    if (umax <= 6) return dispatch_nreg<IMG_LDS, PM, 6, ALIAS>(p, nreg, true, false, blocks, lds, s);
   }
-  if (umax <= 8) return dispatch_nreg<IMG_LDS, PM, 8, ALIAS>(p, nreg, false, blocks, lds, s);
-  return dispatch_nreg<IMG_LDS, PM, 16, ALIAS>(p, nreg, false, blocks, lds, s);
+  if (umax <= 8) return dispatch_nreg<IMG_LDS, PM, 8, ALIAS>(p, nreg, true, false, blocks, lds, s);
+  return dispatch_nreg<IMG_LDS, PM, 16, ALIAS>(p, nreg, true, false, blocks, lds, s);
 }
 
 template <bool IMG_LDS, bool ALIAS>
-pbn_status dispatch_pm(const SimParams& p, uint32_t pmax, uint32_t umax, uint32_t nreg, bool reg, uint32_t blocks,
-                       uint32_t lds, hipStream_t s) {
-  if (pmax <= 5) return dispatch_um<IMG_LDS, 5, ALIAS>(p, umax, nreg, reg, blocks, lds, s);
-  return dispatch_um<IMG_LDS, 7, ALIAS>(p, umax, nreg, reg, blocks, lds, s);
+pbn_status dispatch_pm(const SimParams& p, uint32_t pmax, uint32_t umax, uint32_t nreg, bool lastsel, bool reg,
+                       uint32_t blocks, uint32_t lds, hipStream_t s) {
+  if (pmax <= 5) return dispatch_um<IMG_LDS, 5, ALIAS>(p, umax, nreg, lastsel, reg, blocks, lds, s);
+  return dispatch_um<IMG_LDS, 7, ALIAS>(p, umax, nreg, lastsel, reg, blocks, lds, s);
 }
 
 template <bool IMG_LDS, int PM, int UM>
@@ -1978,11 +1993,14 @@ pbn_status simulate_common(bool plain, const pbn_plan* plan, const void* d_plan,
   const uint32_t zero_pos = reinterpret_cast<const pbn_plan_header*>(plan->blob.data())->zero_pos;
   const bool reg = cached && npass == 1 && umax == 0 && !plan->sampling && zero_pos + 4u <= 64u;
   const uint32_t nreg = cached ? npass : 0u;
+  // does the last register-held pass select a predictor anywhere?
+  const pbn_pass_info* pinfo = reinterpret_cast<const pbn_pass_info*>(plan->blob.data() + ph->pass_off);
+  const bool lastsel = nreg == 0u || (pinfo[nreg - 1u].flags & PBN_PASS_MULTI) != 0u;
   if (plan->sampling)
-    return img_lds ? dispatch_pm<true, true>(p, pmax, umax, nreg, false, blocks, lds, s)
-                   : dispatch_pm<false, true>(p, pmax, umax, nreg, false, blocks, lds, s);
-  return img_lds ? dispatch_pm<true, false>(p, pmax, umax, nreg, reg, blocks, lds, s)
-                 : dispatch_pm<false, false>(p, pmax, umax, nreg, reg, blocks, lds, s);
+    return img_lds ? dispatch_pm<true, true>(p, pmax, umax, nreg, true, false, blocks, lds, s)
+                   : dispatch_pm<false, true>(p, pmax, umax, nreg, true, false, blocks, lds, s);
+  return img_lds ? dispatch_pm<true, false>(p, pmax, umax, nreg, lastsel, reg, blocks, lds, s)
+                 : dispatch_pm<false, false>(p, pmax, umax, nreg, lastsel, reg, blocks, lds, s);
 }
 
 }  // namespace

@@ -66,6 +66,7 @@ NETS = {
     "wide40": lambda: ps.random_pbn(40, 1e-2, 18, nfn=lambda r: int(r.integers(1, 4)),
                                     nparents=lambda r: int(r.integers(1, 8)), leaf_frac=0.1),
     "interleaved": ps.interleaved_cone,
+    "single64": lambda: all_single(64, 27, p=2e-3),
 }
 
 
@@ -148,6 +149,7 @@ CASES = [
     ("c3_slice", GROUPED, 8, 0, 3, (25,), 0, False, 0),
     ("modules", CONE, 18, 0, 20, (400,), 0, True, 0),
     ("modules", CONE_GROUPED, 18, 0, 20, (250, 150), 100, False, 2),
+    ("single64", REDUCED, 22, 0, 30, (200, 123), 60, True, 0),    # one pass, no selection: predictor 0 undrawn
 ]
 
 
@@ -159,6 +161,9 @@ def test_trajectories_bit_exact(case):
         assert plan.info["n_multi_groups"] > 0, "case must exercise multi-member tables"
     if opts is GLOBAL_IMAGE:
         assert plan.info["image_in_lds"] == 0
+    if name == "single64":
+        # one pass of more than 60 slots: state bytes in LDS, not the 64-bit register form
+        assert plan.info["n_passes"] == 1 and plan.info["n_kept"] > 60, plan.info
     if opts is CONE:
         # the cone reduction removes the detached modules, which Definition 1 keeps
         leaf = api.Plan(net_of(name), interest=sorted({a for tg in targets_of(net_of(name)) for a, _ in tg}),
