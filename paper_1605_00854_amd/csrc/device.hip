@@ -1609,7 +1609,11 @@ struct BatchParams {
   pbn_batch_ctl* ctl;              // device: task counter and the step window
 };
 
-template <int PM, int UM>
+// PF: each pass's slot records are read while the previous pass evaluates
+// (run_traj MODE bit 5): launches too small to fill the chip at four waves
+// per SIMD, where its four VGPRs cost no occupancy and the step latency of
+// one trajectory is what counts (served queries).
+template <int PM, int UM, bool PF>
 __global__ void __launch_bounds__(1024) k_batch(BatchParams a, const pbn_work* __restrict__ items) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   uint32_t& claimed = *reinterpret_cast<uint32_t*>(smem);   // first 16 bytes: the claimed task
@@ -1647,9 +1651,9 @@ __global__ void __launch_bounds__(1024) k_batch(BatchParams a, const pbn_work* _
       t.record = nullptr;
       t.record_words = 0;
       t.gshift = a.gshift;
-      // no slot-record prefetch (MODE bit 5): its four VGPRs would take
+      // large launches run without the prefetch: its four VGPRs would take
       // this kernel from five to four waves per SIMD
-      run_traj<PM, UM, 0, (PM == 7 ? 1 : 0) | 2>(t);
+      run_traj<PM, UM, 0, (PM == 7 ? 1 : 0) | 2 | (PF ? 32 : 0)>(t);
     }
   }
 }
@@ -2176,10 +2180,14 @@ struct NoAllocSched {
 
 template <int PM, int UM>
 pbn_status launch_batch_t(const BatchParams& p, uint32_t lds, hipStream_t s, const NoAllocSched* sched = nullptr) {
-  auto* fn = k_batch<PM, UM>;
   int dev = 0, ncu = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_check(e, "batch device query");
+  // the slot-record prefetch when every wave of the launch fits the chip at
+  // four waves per SIMD (four SIMDs per CU)
+  const uint64_t waves = uint64_t(sched ? sched->ntasks : p.ntasks) * p.wpb;
+  auto* fn = waves <= uint64_t(ncu) * 16u ? k_batch<PM, UM, true> : k_batch<PM, UM, false>;
   if (e == hipSuccess)
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize, int(kLdsMax));
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, int(64u * p.wpb), lds);
