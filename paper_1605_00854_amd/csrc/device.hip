@@ -525,19 +525,27 @@ __device__ __forceinline__ uint32_t eval_stream(const uint4 rec, const uint8_t* 
 // of its chosen predictor (one-predictor lanes and padded lanes choose 0: their
 // thresholds are never reached), with no branch between lanes that select and
 // lanes that do not, so the loads of several passes can be in flight together.
-// SEL false: a pass without multi-predictor slots, where every lane takes
-// predictor 0 without reading a drawn word.
-template <int PM, int UM, int MODE, bool SEL = true>
+template <int PM, int UM, int MODE>
 __device__ __forceinline__ uint32_t eval_fn_all(const SlotRegs<Shape<PM, UM>::XW, Shape<PM, UM>::TTW>& r,
                                                 const NegThr& nt, const uint8_t* img, const uint8_t* cs,
                                                 const uint8_t* rs, const FnFmt& fm, unsigned long long st = 0ull,
                                                 const uint32_t* pre = nullptr) {
-  uint32_t j = 0u;
-  if constexpr (SEL) {
-    const uint32_t w = pre ? *pre : *reinterpret_cast<const uint32_t*>(rs + (r.draw & 0xFFFFFFu));
-    j = choose_neg(w, nt);
-  }
-  const auto f = load_fn<PM, UM, MODE>(img, r.base, j, fm, r.info);
+  const uint32_t w = pre ? *pre : *reinterpret_cast<const uint32_t*>(rs + (r.draw & 0xFFFFFFu));
+  const auto f = load_fn<PM, UM, MODE>(img, r.base, choose_neg(w, nt), fm, r.info);
+  return eval_fn<PM, UM, (MODE & 8) != 0>(f, cs, fm.sh, st);
+}
+
+// A pass whose lanes all hold one-predictor slots (or padding): the record
+// load_slot keeps in registers is the one every step uses.
+template <int PM, int UM, int MODE>
+__device__ __forceinline__ uint32_t eval_fn_held(const SlotRegs<Shape<PM, UM>::XW, Shape<PM, UM>::TTW>& r,
+                                                 const uint8_t* cs, const FnFmt& fm, unsigned long long st = 0ull) {
+  constexpr int PW = Shape<PM, UM>::PW, TTW = Shape<PM, UM>::TTW;
+  FnRec<PW, TTW> f;
+#pragma unroll
+  for (int k = 0; k < PW; ++k) f.pw[k] = r.pw[k];
+#pragma unroll
+  for (int k = 0; k < TTW; ++k) f.tt[k] = r.tt[k];
   return eval_fn<PM, UM, (MODE & 8) != 0>(f, cs, fm.sh, st);
 }
 
@@ -654,7 +662,8 @@ struct TrajArgs {
 // each lane pass's slot records are read while the previous pass evaluates
 // (one dependent global read less per pass for four more VGPRs); bit 7, with
 // NREG = 1 or 2 and FN-only keyed plans, the last register-held pass holds no
-// multi-predictor slot (no drawn word read, no threshold compare there).
+// multi-predictor slot (no drawn word read, no threshold compare, and its
+// records stay in registers).
 template <int PM, int UM, int NREG, int MODE>
 __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   constexpr int XW = Shape<PM, UM>::XW, TTW = Shape<PM, UM>::TTW;
@@ -963,7 +972,7 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
           for (int p = 0; p < NREG; ++p) {
             if constexpr (UM == 0 && !ALIAS)
               out[p] = kLastNoSel && p == NREG - 1   // constant once the loop is unrolled
-                           ? eval_fn_all<PM, UM, MODE, false>(cached[p], nthr[p], img, csb, rs, fm, rst)
+                           ? eval_fn_held<PM, UM, MODE>(cached[p], csb, fm, rst)
                            : eval_fn_all<PM, UM, MODE>(cached[p], nthr[p], img, csb, rs, fm, rst,
                                                        kRegState ? &wcur : nullptr);
             else
