@@ -487,19 +487,22 @@ def bench_batch(args):
     passes = (total + chunk - 1) // chunk
     total = passes * chunk
     results = {}
+    from paper_1605_00854_amd import autotune
     for label, opts in (("product", None), ("plain", dict(reduce=0, group=0))):
         if opts is None:
-            opts, wpb, tpw_trials = tuned_opts_for(api, torch, nets, 4)
-        else:
-            wpb = 4
+            opts, _, tpw_trials = tuned_opts_for(api, torch, nets, 4)
         t0 = time.perf_counter()
         items = []
         for k, net in enumerate(nets):
             tg = [ps.non_leaf_targets(net, 3)]
             plan = api.Plan(net, interest=[a for a, _ in tg[0]], **opts)
             items.append((plan, 1004000 + k, ntraj, tg))
-        b = api.Batch(items, count_from=burn, waves_per_block=wpb)
         prep = time.perf_counter() - t0
+        # the launch shape, timed on the batch itself (every leg alike)
+        wpb, wpb_trials = autotune.batch_waves_per_block(items, count_from=burn)
+        if args.wpb:
+            wpb = args.wpb
+        b = api.Batch(items, count_from=burn, waves_per_block=wpb)
         b.init_states()
         b.set_window(0, chunk)
         g = b.graph(passes)
@@ -510,7 +513,8 @@ def bench_batch(args):
         dt = time.perf_counter() - t1
         work = sum(ntraj * total * net["n"] for net in nets)
         results[label] = {"node_updates_per_s": work / dt, "seconds": dt, "prep_seconds": prep,
-                          "plan": opts, "waves_per_block": wpb, "graph_passes": passes, "chunk": chunk}
+                          "plan": opts, "waves_per_block": wpb, "wpb_trials": wpb_trials, "graph_passes": passes,
+                          "chunk": chunk}
         del g, b, items
     out = {"metric": "node-updates/sec on 1 MI355X (batched uneven networks, one graph replay)",
            "value": results["product"]["node_updates_per_s"], "unit": "node-updates/s", "n_gpus": 1,

@@ -85,6 +85,33 @@ def _probe(torch, plan, tg, seed, ntraj, steps, wpb, plain, tpw=1):
     return e0.elapsed_time(e1) * 1e-3
 
 
+def batch_waves_per_block(items, count_from=0, wpbs=(2, 4, 8), probe_steps=200):
+    """Waves per workgroup of a batched persistent launch (api.Batch items),
+    timed on the batch itself: how many networks share a CU, and its vector
+    L1, depends on the workgroup size, which single-network probes cannot
+    see.  Returns (the fastest, trials)."""
+    import torch
+    trials = []
+    for wpb in wpbs:
+        b = api.Batch(items, count_from=count_from, waves_per_block=wpb)
+        b.init_states()
+        b.set_window(0, probe_steps)
+        b.launch()                                  # warm-up: caches, first touch
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        b.set_window(probe_steps, probe_steps)
+        e0.record(stream)
+        b.launch()
+        e1.record(stream)
+        e1.synchronize()
+        trials.append({"wpb": wpb, "seconds": e0.elapsed_time(e1) * 1e-3})
+        del b
+    best = min(trials, key=lambda t: t["seconds"])
+    return best["wpb"], trials
+
+
 def tune(net, interest, target_sets, ntraj, seed=1, probe_steps=2000, wpbs=(2, 4, 8), quick=False,
          key=None, verbose=False):
     """Return (best plan options, best waves_per_block, list of trials).

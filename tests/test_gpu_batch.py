@@ -244,3 +244,25 @@ def test_batch_mixes_wide_and_narrow_predictor_records():
         kept = plan.node_pos() != NONE
         assert np.array_equal(orig[:, kept], ref["state"][:, kept]), f"network {k}"
         assert np.array_equal(b.counts[k].cpu().numpy()[:, :, 0], ref["hits"]), f"network {k}"
+
+
+def test_batch_launch_shape_probe_leaves_results_unchanged():
+    """The batch autotuner times the batch itself for each workgroup size; a
+    batch run with whichever size it picks gives the same states and
+    counters as one with the default."""
+    from paper_1605_00854_amd import autotune
+    items, _ = make_items(12, 21, 20, 400, [64, 33], False)
+    say("[gpu] batch launch-shape probe")
+    wpb, trials = autotune.batch_waves_per_block(items, count_from=20, wpbs=(2, 4, 8), probe_steps=100)
+    assert wpb in (2, 4, 8) and [t["wpb"] for t in trials] == [2, 4, 8]
+    assert all(t["seconds"] > 0 for t in trials)
+    runs = []
+    for w in (4, wpb):
+        b = api.Batch(items, count_from=20, waves_per_block=w)
+        b.init_states()
+        b.set_window(0, 150)
+        b.launch()
+        torch.cuda.synchronize()
+        runs.append(([s.cpu().numpy() for s in b.states], [c.cpu().numpy() for c in b.counts]))
+    for k in range(len(items)):
+        assert np.array_equal(runs[0][0][k], runs[1][0][k]) and np.array_equal(runs[0][1][k], runs[1][1][k]), k
