@@ -210,7 +210,8 @@ def vmem_work(net, plan, samples=32, seed=1):
                             c[np.searchsorted(tl, s_)] += choose(int(z[s_] + 16 * m)) * \
                                 ((int(rec[s_, 3]) >> (8 * m)) & 0xFF)
                 x = rng.integers(0, 1 << nu[tl])
-                a, k = a + units(y[tl] + 32 + (c << nu[tl]) + x), k + 1
+                lst = np.where(inline[tl], 0, 32)      # inline slots: no union list before the table
+                a, k = a + units(y[tl] + lst + (c << nu[tl]) + x), k + 1
             if fl.size:
                 j = np.zeros(fl.size, dtype=np.int64)
                 sel = fl[nmulti[fl] > 0]

@@ -440,7 +440,8 @@ __device__ __forceinline__ uint32_t eval_table(const SlotRegs<Shape<PM, UM>::XW,
     x = gather_lbits<(UM > 0 ? UM : 1)>(reinterpret_cast<const uint32_t*>(cs), r.pw, sh);
   else
     x = gather<(UM > 0 ? UM : 1)>(cs, r.pw, sh);
-  const uint32_t v = img_u8<G>(img + (r.base + 32u + (c << PBN_SLOT_NU(r.info)) + x));
+  const uint32_t list = (r.info & PBN_SLOT_INLINE) ? 0u : 32u;   // inline slots: the table at base
+  const uint32_t v = img_u8<G>(img + (r.base + list + (c << PBN_SLOT_NU(r.info)) + x));
   return v;   // member k's output in bit k
 }
 
@@ -506,7 +507,8 @@ __device__ __forceinline__ uint32_t eval_stream(const uint4 rec, const uint8_t* 
       x = gather_lbits<(UM > 0 ? UM : 1)>(reinterpret_cast<const uint32_t*>(cs), pw, fm.sh);
     else
       x = gather<(UM > 0 ? UM : 1)>(cs, pw, fm.sh);
-    return img_u8<G>(img + (rec.y + 32u + (c << PBN_SLOT_NU(rec.x)) + x));
+    const uint32_t list = (rec.x & PBN_SLOT_INLINE) ? 0u : 32u;   // inline slots: the table at y
+    return img_u8<G>(img + (rec.y + list + (c << PBN_SLOT_NU(rec.x)) + x));
   }
   spos = rec.w;   // FN slot or padded lane: its state position
   uint32_t j = 0;

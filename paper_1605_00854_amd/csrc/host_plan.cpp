@@ -496,11 +496,19 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   const size_t slot_bytes = size_t(npass) * PBN_WAVE * 16;
   size_t nchoice = 0, tab_bytes = 0, nfnrec = 0;
   uint32_t fn_phi = 0;
+  // a table slot without multi-predictor members and with at most 5 union
+  // bits carries its union positions in its slot record: no union list
+  auto inline_table = [&](const Slot& s) {
+    if (s.uni.size() > 5) return false;
+    for (uint32_t v : s.members)
+      if (g.nfn(v) > 1) return false;
+    return true;
+  };
   for (const auto& s : slots) {
     for (uint32_t v : s.members)
       if (g.nfn(v) > 1) ++nchoice;
     if (s.table) {
-      tab_bytes += align16(32 + size_t(table_entries(s.members)));
+      tab_bytes += align16((inline_table(s) ? 0 : 32) + size_t(table_entries(s.members)));
     } else {
       fn_phi = std::max(fn_phi, max_phi(s.members[0]));
       nfnrec += g.nfn(s.members[0]);
@@ -616,8 +624,11 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
     } else {
       const uint32_t nu = uint32_t(sl.uni.size());
       info |= PBN_SLOT_TABLE | (nu << 6);
+      const bool inl = inline_table(sl);
+      const size_t list_bytes = inl ? 0 : 32;   // union list before the table (none for inline slots)
       y = uint32_t(tab_cur);
-      for (uint32_t b = 0; b < 16; ++b) put16(tab_cur + 2 * b, uint16_t(b < nu ? plan.node_pos[sl.uni[b]] : zero_pos));
+      if (!inl)
+        for (uint32_t b = 0; b < 16; ++b) put16(tab_cur + 2 * b, uint16_t(b < nu ? plan.node_pos[sl.uni[b]] : zero_pos));
       // mixed radix: member k's digit weight = product of l over later members
       std::vector<uint32_t> radix(sl.members.size(), 1);
       for (int k = int(sl.members.size()) - 2; k >= 0; --k) radix[k] = radix[k + 1] * g.nfn(sl.members[k + 1]);
@@ -628,7 +639,7 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
       uint32_t ncomb = 1;
       for (uint32_t v : sl.members) ncomb *= g.nfn(v);
       std::vector<std::vector<uint32_t>> map;   // per member predictor: parent -> union bit
-      const size_t tbl = tab_cur + 32;
+      const size_t tbl = tab_cur + list_bytes;
       std::vector<uint32_t> digits(sl.members.size());
       for (uint32_t c = 0; c < ncomb; ++c) {
         uint32_t rest = c;
@@ -651,14 +662,14 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
           img[tbl + (size_t(c) << nu) + x] = uint8_t(out);
         }
       }
-      if (nmulti == 0 && nu <= 5) {
+      if (inl) {
         // the union positions in the record itself (no union-list read)
         auto upos = [&](uint32_t b) { return b < nu ? plan.node_pos[sl.uni[b]] : zero_pos; };
         info |= PBN_SLOT_INLINE | (upos(4) << 11);
         z = upos(0) | (upos(1) << 16);
         w = upos(2) | (upos(3) << 16);
       }
-      tab_cur += align16(32 + (size_t(ncomb) << nu));
+      tab_cur += align16(list_bytes + (size_t(ncomb) << nu));
       pi.flags |= PBN_PASS_TABLE;
       pi.umax = std::max(pi.umax, nu);
       pi.mmax = std::max(pi.mmax, nmulti);

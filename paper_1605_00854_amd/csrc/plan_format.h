@@ -139,7 +139,8 @@ struct pbn_pass_info {
 //     The dummy records (all positions the zero word, table 0) come first.
 //   tables:                   TABLE slot: 16 uint16 union-parent positions
 //                             (unused = zero position), then the byte table
-//                             T[c * 2^nu + x]
+//                             T[c * 2^nu + x]; a PBN_SLOT_INLINE slot has the
+//                             table alone (its positions are in its record)
 //   alias records (alias sampling only, see below)
 //   Q[0..n] (uint64) and the orig -> position map (uint32[n]), copies of the
 //   blob's, at q_img / o2p_img
@@ -149,8 +150,9 @@ struct pbn_pass_info {
 // Slot record (uint4):
 //   x = info word (PBN_SLOT_*)
 //   y = FN: image offset of the fn record of predictor 0 (predictor j at +32 j)
-//       TABLE: image offset of the union-parent list (table follows at +32;
-//       with PBN_SLOT_INLINE the list is also in z, w and the info word)
+//       TABLE: image offset of the union-parent list (table follows at +32);
+//       with PBN_SLOT_INLINE the offset of the table itself (the positions
+//       are in z, w and the info word)
 //   z = FN: image offset of the slot's choice record (one-predictor nodes and
 //       padded lanes: the default record {ring offset 0, l = 1, no thresholds},
 //       the first choice record of the image);
