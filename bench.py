@@ -44,12 +44,12 @@ MEASURED_TRAFFIC = {
     # per launch of the product plan: FETCH_SIZE and WRITE_SIZE (KiB per
     # dispatch) of one rocprofv3 --pmc run each, and the factors a 256 MiB
     # device copy reads for them (fetch 131 088 KiB, write 262 144 KiB)
-    "C2": {"kernel_source_sha256": "9dd10502ff2c40843cec7b1b9df1c0ce5b050c48296c47bc2a774fe7ad115923",
+    "C2": {"kernel_source_sha256": "79193dfed508c472ff4c1b2678b471834b729c31c2ab3c6db004ce17ca08851f",
            "plan": {"group": 0, "reduce": 1},
            "fetch_kib": 234.125, "fetch_factor": 2.0, "write_kib": 176.0, "write_factor": 1.0},
-    "C3": {"kernel_source_sha256": "9dd10502ff2c40843cec7b1b9df1c0ce5b050c48296c47bc2a774fe7ad115923",
+    "C3": {"kernel_source_sha256": "79193dfed508c472ff4c1b2678b471834b729c31c2ab3c6db004ce17ca08851f",
            "plan": {"group": 1, "max_group_nodes": 4, "max_parent_bits": 5, "reduce": 1},
-           "fetch_kib": 12197.56, "fetch_factor": 2.0, "write_kib": 22016.0, "write_factor": 1.0},
+           "fetch_kib": 12135.69, "fetch_factor": 2.0, "write_kib": 22016.0, "write_factor": 1.0},
 }
 
 
