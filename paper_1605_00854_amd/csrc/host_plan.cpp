@@ -575,6 +575,17 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   size_t choice_cur = choice_base + 16, tab_cur = tab_base;
   std::vector<pbn_pass_info> passes(npass, pbn_pass_info{0, 0, 0, 0});
   uint32_t max_fn_parents = 0, max_union = 0, multi_groups = 0;
+  // LDS words read so far by each gather instruction (union bit k) of each
+  // pass, per bank (32 banks of 4 bytes): a table slot's union bits are
+  // ordered so that its lanes' parent bytes fall on banks the pass's other
+  // lanes leave free, gather by gather (lanes reading one word share it)
+  constexpr uint32_t kBanks = 32;
+  std::vector<std::vector<std::vector<uint32_t>>> bank_words(
+      size_t(npass) * PBN_MAX_GROUP_PARENTS, std::vector<std::vector<uint32_t>>(kBanks));
+  auto bank_cost = [&](const std::vector<std::vector<uint32_t>>& bw, uint32_t word) -> size_t {
+    const auto& b = bw[word % kBanks];
+    return std::find(b.begin(), b.end(), word) != b.end() ? 0 : b.size();
+  };
   for (uint32_t s = 0; s < ns; ++s) {
     const Slot& sl = slots[s];
     const size_t rec = size_t(s) * 16;
@@ -627,8 +638,31 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
       const bool inl = inline_table(sl);
       const size_t list_bytes = inl ? 0 : 32;   // union list before the table (none for inline slots)
       y = uint32_t(tab_cur);
+      // table index bit b reads union parent sl.uni[ord[b]] (inv: the reverse)
+      std::vector<uint32_t> ord(nu), inv(nu);
+      for (uint32_t b = 0; b < nu; ++b) ord[b] = b;
+      if (!bits) {
+        std::vector<bool> taken(nu, false);
+        for (uint32_t b = 0; b < nu; ++b) {
+          auto& bw = bank_words[size_t(s / PBN_WAVE) * PBN_MAX_GROUP_PARENTS + b];
+          uint32_t best = nu;
+          size_t best_cost = 0;
+          for (uint32_t i = 0; i < nu; ++i) {
+            if (taken[i]) continue;
+            const size_t c = bank_cost(bw, plan.node_pos[sl.uni[i]] / 4);
+            if (best == nu || c < best_cost) best = i, best_cost = c;
+          }
+          taken[best] = true;
+          ord[b] = best;
+          const uint32_t word = plan.node_pos[sl.uni[best]] / 4;
+          auto& bank = bw[word % kBanks];
+          if (std::find(bank.begin(), bank.end(), word) == bank.end()) bank.push_back(word);
+        }
+      }
+      for (uint32_t b = 0; b < nu; ++b) inv[ord[b]] = b;
+      auto upos = [&](uint32_t b) { return b < nu ? plan.node_pos[sl.uni[ord[b]]] : zero_pos; };
       if (!inl)
-        for (uint32_t b = 0; b < 16; ++b) put16(tab_cur + 2 * b, uint16_t(b < nu ? plan.node_pos[sl.uni[b]] : zero_pos));
+        for (uint32_t b = 0; b < 16; ++b) put16(tab_cur + 2 * b, uint16_t(upos(b)));
       // mixed radix: member k's digit weight = product of l over later members
       std::vector<uint32_t> radix(sl.members.size(), 1);
       for (int k = int(sl.members.size()) - 2; k >= 0; --k) radix[k] = radix[k + 1] * g.nfn(sl.members[k + 1]);
@@ -655,7 +689,7 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
             for (uint32_t b = 0; b < g.nparents(f); ++b) {
               const uint32_t par = g.parents[g.par_off[f] + b];
               const uint32_t ub = uint32_t(std::lower_bound(sl.uni.begin(), sl.uni.end(), par) - sl.uni.begin());
-              idx |= ((x >> ub) & 1u) << b;
+              idx |= ((x >> inv[ub]) & 1u) << b;
             }
             out |= g.eval(f, idx) << k;
           }
@@ -664,7 +698,6 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
       }
       if (inl) {
         // the union positions in the record itself (no union-list read)
-        auto upos = [&](uint32_t b) { return b < nu ? plan.node_pos[sl.uni[b]] : zero_pos; };
         info |= PBN_SLOT_INLINE | (upos(4) << 11);
         z = upos(0) | (upos(1) << 16);
         w = upos(2) | (upos(3) << 16);
