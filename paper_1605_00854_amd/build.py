@@ -18,6 +18,9 @@ HOST_SOURCES = ["host_net.cpp", "host_plan.cpp", "host_stats.cpp"]
 DEVICE_SOURCES = ["device.hip", "probe.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall", "-Wno-unused-function"]
+# host-only sources: plain C++ (hipcc would otherwise also compile them for a
+# default device target)
+HOST_FLAGS = ["-x", "c++"]
 # never emit packed FP32 instructions (none are needed: the path is integer only)
 DEVICE_FLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
                 "-packed-fp32-ops", "-munsafe-fp-atomics"]
@@ -37,7 +40,7 @@ def build(verbose=False, jobs=4):
         procs, objs = [], []
         for src in HOST_SOURCES + DEVICE_SOURCES:
             obj = os.path.join(tmp, src + ".o")
-            cmd = [cc] + COMMON + (DEVICE_FLAGS if src.endswith(".hip") else []) + \
+            cmd = [cc] + COMMON + (DEVICE_FLAGS if src.endswith(".hip") else HOST_FLAGS) + \
                   ["-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)

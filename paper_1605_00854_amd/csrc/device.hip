@@ -1410,9 +1410,7 @@ __global__ void __launch_bounds__(1024) k_simulate_multi(SimParams a) {
 // reads (not used by k_simulate_bits).
 template <int PM, int UM, int MODE>
 __device__ __forceinline__ void run_bits(const TrajArgs& a) {
-  constexpr int XW = Shape<PM, UM>::XW, TTW = Shape<PM, UM>::TTW;
   constexpr int M = MODE | 16;   // state as bits
-  using Regs = SlotRegs<XW, TTW>;
   const pbn_plan_header* H = reinterpret_cast<const pbn_plan_header*>(a.blob);
   const pbn_pass_info* pinfo = reinterpret_cast<const pbn_pass_info*>(a.blob + H->pass_off);
   const uint32_t lane = threadIdx.x & 63u;

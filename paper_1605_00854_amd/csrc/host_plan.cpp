@@ -494,7 +494,7 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
   // more than 5 parents (fn_var), the others keep one (a slot record's parent
   // count tells the kernel which).
   const size_t slot_bytes = size_t(npass) * PBN_WAVE * 16;
-  size_t nchoice = 0, tab_bytes = 0, nfnrec = 0;
+  size_t nchoice = 0, tab_bytes = 0;
   uint32_t fn_phi = 0;
   // a table slot without multi-predictor members and with at most 5 union
   // bits carries its union positions in its slot record: no union list
@@ -511,7 +511,6 @@ static pbn_status build_plan(const pbn_net& g, const std::vector<uint8_t>& inter
       tab_bytes += align16((inline_table(s) ? 0 : 32) + size_t(table_entries(s.members)));
     } else {
       fn_phi = std::max(fn_phi, max_phi(s.members[0]));
-      nfnrec += g.nfn(s.members[0]);
     }
   }
   ++nchoice;  // the default choice record of one-predictor FN slots and padded lanes
