@@ -333,14 +333,45 @@ def _to_device_bytes(obj):
     return torch.from_numpy(raw).to("cuda")
 
 
+# task queues of a batched launch (PBN_BATCH_QUEUES) and the words of its
+# control block: step0, nsteps, ntasks, reserved, one claim counter per queue
+BATCH_QUEUES = 8
+CTL_WORDS = 4 + BATCH_QUEUES
+
+
+def new_ctl(step0=0, nsteps=0):
+    """A batch control block on the device with the step window set."""
+    import torch
+    words = [int(step0), int(nsteps)] + [0] * (CTL_WORDS - 2)
+    return torch.tensor(words, dtype=torch.int32, device="cuda")
+
+
+def batch_schedule(plans_arr, ntraj, wpb, queues=BATCH_QUEUES):
+    """pbn_batch_tasks: (item of each task, its first trajectory, the
+    BATCH_QUEUES + 1 queue bounds), all uint32 host arrays."""
+    ntraj = np.ascontiguousarray(ntraj, dtype=np.uint32)
+    nt = C.c_uint32()
+    check(lib().pbn_batch_tasks(plans_arr, _ptr(ntraj, C.c_uint32), ntraj.size, int(wpb), int(queues),
+                                None, None, None, C.byref(nt)))
+    tasks = np.zeros(max(1, nt.value), dtype=np.uint32)
+    first = np.zeros(max(1, nt.value), dtype=np.uint32)
+    qfirst = np.zeros(BATCH_QUEUES + 1, dtype=np.uint32)
+    check(lib().pbn_batch_tasks(plans_arr, _ptr(ntraj, C.c_uint32), ntraj.size, int(wpb), int(queues),
+                                _ptr(tasks, C.c_uint32), _ptr(first, C.c_uint32), _ptr(qfirst, C.c_uint32),
+                                C.byref(nt)))
+    return tasks[:nt.value], first[:nt.value], qfirst
+
+
 class Batch:
     """Many networks advanced by one persistent launch (pbn_batch_launch).
 
     items: list of (plan, seed, ntraj, target_sets); every trajectory of every
     network shares the device step window held in the control block.
+    queues: how many of the launch's task queues (one per XCD) receive
+    networks; 1 puts every task in one queue.
     """
 
-    def __init__(self, items, count_from=0, waves_per_block=4):
+    def __init__(self, items, count_from=0, waves_per_block=4, queues=BATCH_QUEUES):
         import torch
         self.plans = [it[0] for it in items]
         self.wpb = int(waves_per_block)
@@ -364,17 +395,12 @@ class Batch:
         self._plan_arr = (C.c_void_p * len(items))(*[p.handle.value for p in self.plans])
         ntraj = np.asarray([it[2] for it in items], dtype=np.uint32)
         self._ntraj = ntraj
-        nt = C.c_uint32()
-        check(lib().pbn_batch_tasks(self._plan_arr, _ptr(ntraj, C.c_uint32), len(items), self.wpb,
-                                    None, None, C.byref(nt)))
-        tasks = np.zeros(max(1, nt.value), dtype=np.uint32)
-        first = np.zeros(max(1, nt.value), dtype=np.uint32)
-        check(lib().pbn_batch_tasks(self._plan_arr, _ptr(ntraj, C.c_uint32), len(items), self.wpb,
-                                    _ptr(tasks, C.c_uint32), _ptr(first, C.c_uint32), C.byref(nt)))
-        self.ntasks = nt.value
-        self.tasks_dev = torch.from_numpy(tasks.astype(np.int32)).to("cuda")
-        self.first_dev = torch.from_numpy(first.astype(np.int32)).to("cuda")
-        self.ctl = torch.zeros(4, dtype=torch.int32, device="cuda")
+        tasks, first, self.queue_first = batch_schedule(self._plan_arr, ntraj, self.wpb, queues)
+        self.ntasks = int(tasks.size)
+        pad = np.zeros(1, dtype=np.uint32)    # device arrays of at least one element
+        self.tasks_dev = torch.from_numpy((tasks if tasks.size else pad).astype(np.int32)).to("cuda")
+        self.first_dev = torch.from_numpy((first if first.size else pad).astype(np.int32)).to("cuda")
+        self.ctl = new_ctl()
 
     def init_states(self, stream=None):
         for plan, seed, state in zip(self.plans, self.seeds, self.states):
@@ -382,12 +408,16 @@ class Batch:
                                        _dptr(state), _stream(stream)))
 
     def set_window(self, step0, nsteps):
-        import torch
-        self.ctl.copy_(torch.tensor([0, int(step0), int(nsteps), 0], dtype=torch.int32))
+        self.ctl.copy_(new_ctl(step0, nsteps))
+
+    def step0(self):
+        """The device-held first step of the next launch's window."""
+        return int(self.ctl[0].item())
 
     def _args(self):
         return (self._plan_arr, len(self.plans), _dptr(self.items_dev), _dptr(self.tasks_dev),
-                _dptr(self.first_dev), self.ntasks, _dptr(self.ctl), self.wpb)
+                _dptr(self.first_dev), self.ntasks, _ptr(self.queue_first, C.c_uint32), _dptr(self.ctl),
+                self.wpb)
 
     def launch(self, stream=None):
         check(lib().pbn_batch_launch(*self._args(), _stream(stream)))

@@ -1602,20 +1602,32 @@ __global__ void __launch_bounds__(1024) k_simulate_bits(SimParams a) {
 
 // ---------------------------------------------------------------- batches
 // Many networks of uneven size in one persistent launch.  Work is cut into
-// tasks of `wpb` consecutive trajectories of one network, ordered by the host
-// (largest networks first); each workgroup repeatedly claims the next task with
-// one atomic increment and stops when none is left, so every wave reaches the
-// exit.  Plan images stay in global memory (the L2 serves them); each wave's
-// LDS holds its trajectory's state buffers and Philox ring.
+// tasks of `wpb` consecutive trajectories of one network, in PBN_BATCH_QUEUES
+// queues of whole networks, ordered by the host (largest networks first within
+// a queue).  The dispatcher hands workgroups to the eight XCDs in turn, so
+// workgroup b starts on queue b mod PBN_BATCH_QUEUES: the networks of a queue
+// run on one XCD and share its CUs' vector L1 caches, where one queue for the
+// whole chip would mix the images of every network in flight on each CU.  A
+// workgroup repeatedly claims the next task of its queue with one atomic
+// increment, moves on to the next queue when its own is empty (a queue found
+// empty stays empty: its counter only grows), and stops after the last one,
+// so every wave reaches the exit.  Plan images stay in global memory (the L2
+// serves them); each wave's LDS holds its trajectory's state buffers and
+// Philox ring.
+struct QueueBounds {
+  uint32_t first[PBN_BATCH_QUEUES + 1];   // queue k: tasks first[k] .. first[k + 1] - 1
+};
+
 struct BatchParams {
   const pbn_work* items;
   const uint32_t* tasks;           // item of task k
   const uint32_t* task_first;      // first trajectory (local index) of task k
-  uint32_t ntasks;
+  uint32_t ntasks;                 // PBN_NONE: one queue of ctl->ntasks tasks, written on the device
   uint32_t wpb;
   uint32_t wave_bytes;
   uint32_t gshift;                 // 1: the gather step's shift, passed at run time (see shl_or)
-  pbn_batch_ctl* ctl;              // device: task counter and the step window
+  pbn_batch_ctl* ctl;              // device: queue counters and the step window
+  QueueBounds q;
 };
 
 // PF: each pass's slot records are read while the previous pass evaluates
@@ -1628,14 +1640,28 @@ __global__ void __launch_bounds__(1024) k_batch(BatchParams a, const pbn_work* _
   uint32_t& claimed = *reinterpret_cast<uint32_t*>(smem);   // first 16 bytes: the claimed task
   const uint32_t wave = uniform(threadIdx.x >> 6);   // wave-uniform: keeps per-trajectory data scalar
   const uint32_t wstep0 = a.ctl->step0, nsteps = a.ctl->nsteps;
-  // PBN_NONE: the schedule was written on the device (allocation-free launch)
-  const uint32_t ntasks = a.ntasks != PBN_NONE ? a.ntasks : uniform(a.ctl->ntasks);
+  const uint32_t home = blockIdx.x % PBN_BATCH_QUEUES;
+  uint32_t tried = 0;   // queues found empty (thread 0's own count)
   for (;;) {
-    if (threadIdx.x == 0) claimed = atomicAdd(&a.ctl->next_task, 1u);
+    if (threadIdx.x == 0) {
+      uint32_t task = PBN_NONE;
+      for (; tried < PBN_BATCH_QUEUES; ++tried) {
+        const uint32_t k = (home + tried) % PBN_BATCH_QUEUES;
+        // PBN_NONE: the schedule was written on the device (allocation-free launch)
+        const uint32_t end = a.ntasks != PBN_NONE ? a.q.first[k + 1] : (k == 0 ? a.ctl->ntasks : 0u);
+        if (a.q.first[k] >= end) continue;   // an empty queue costs no atomic
+        const uint32_t t = atomicAdd(&a.ctl->next_task[k], 1u);
+        if (t < end) {
+          task = t;
+          break;
+        }
+      }
+      claimed = task;
+    }
     __syncthreads();
     const uint32_t task = uniform(claimed);   // the same for the workgroup: scalar loads of the task's item
     __syncthreads();
-    if (task >= ntasks) return;          // uniform across the workgroup
+    if (task == PBN_NONE) return;        // uniform across the workgroup
     // the task's work item, read into wave-uniform values (scalar registers)
     const pbn_work& it = items[uniform(a.tasks[task])];
     const uint32_t tl = uniform(a.task_first[task]) + wave;
@@ -1667,9 +1693,11 @@ __global__ void __launch_bounds__(1024) k_batch(BatchParams a, const pbn_work* _
   }
 }
 
-// Graph-friendly control updates (no memset nodes): reset the task counter
-// before a batch pass, advance the step window after it.
-__global__ void k_batch_begin(pbn_batch_ctl* ctl) { ctl->next_task = 0; }
+// Graph-friendly control updates (no memset nodes): set each queue's counter
+// to its first task before a batch pass, advance the step window after it.
+__global__ void k_batch_begin(pbn_batch_ctl* ctl, QueueBounds q) {
+  if (threadIdx.x < PBN_BATCH_QUEUES) ctl->next_task[threadIdx.x] = q.first[threadIdx.x];
+}
 __global__ void k_batch_end(pbn_batch_ctl* ctl) { ctl->step0 += ctl->nsteps; }
 
 // ------------------------------------------------ allocation-free batches
@@ -1717,7 +1745,7 @@ __global__ void __launch_bounds__(1024) k_noalloc_schedule(const pbn_work* items
   }
   if (t == 1023u) {
     pbn_batch_ctl* ctl = reinterpret_cast<pbn_batch_ctl*>(scr);
-    ctl->next_task = 0;
+    for (uint32_t k = 0; k < PBN_BATCH_QUEUES; ++k) ctl->next_task[k] = 0;
     ctl->step0 = step0;
     ctl->nsteps = nsteps;
     ctl->ntasks = min(part[1023], kNoAllocMaxTasks);
@@ -2208,7 +2236,7 @@ pbn_status launch_batch_t(const BatchParams& p, uint32_t lds, hipStream_t s, con
                        sched->nsteps, reinterpret_cast<uint32_t*>(p.ctl));
     hipLaunchKernelGGL(fn, dim3(blocks), dim3(64u * p.wpb), lds, s, p, p.items);
   } else {
-    hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(1), 0, s, p.ctl);
+    hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(64), 0, s, p.ctl, p.q);
     hipLaunchKernelGGL(fn, dim3(blocks), dim3(64u * p.wpb), lds, s, p, p.items);
     hipLaunchKernelGGL(k_batch_end, dim3(1), dim3(1), 0, s, p.ctl);
   }
@@ -2216,11 +2244,25 @@ pbn_status launch_batch_t(const BatchParams& p, uint32_t lds, hipStream_t s, con
 }
 
 pbn_status batch_enqueue(const pbn_plan* const* plans, uint32_t nitems, const pbn_work* d_items,
-                         const uint32_t* d_tasks, const uint32_t* d_task_first, uint32_t ntasks, pbn_batch_ctl* d_ctl,
-                         uint32_t wpb, hipStream_t s, const NoAllocSched* sched = nullptr) {
+                         const uint32_t* d_tasks, const uint32_t* d_task_first, uint32_t ntasks,
+                         const uint32_t* queue_first, pbn_batch_ctl* d_ctl, uint32_t wpb, hipStream_t s,
+                         const NoAllocSched* sched = nullptr) {
   if (!plans || !d_items || !d_tasks || !d_task_first || !d_ctl) return fail(PBN_EINVAL, "null argument");
   if (wpb < 1 || wpb > 16) return fail(PBN_EINVAL, "waves_per_block must be 1..16");
   if (nitems == 0 || ntasks == 0) return PBN_OK;
+  QueueBounds q{};
+  if (sched) {
+    // one queue, bounded on the device by the schedule's task count
+  } else if (queue_first) {
+    if (queue_first[0] != 0 || queue_first[PBN_BATCH_QUEUES] != ntasks)
+      return fail(PBN_EINVAL, "queue bounds must run from 0 to ntasks");
+    for (uint32_t k = 0; k <= PBN_BATCH_QUEUES; ++k) {
+      if (k > 0 && queue_first[k] < queue_first[k - 1]) return fail(PBN_EINVAL, "queue bounds must not decrease");
+      q.first[k] = queue_first[k];
+    }
+  } else {
+    for (uint32_t k = 1; k <= PBN_BATCH_QUEUES; ++k) q.first[k] = ntasks;
+  }
   BatchShape sh;
   pbn_status st = batch_shape(plans, nitems, sh);
   if (st != PBN_OK) return st;
@@ -2234,6 +2276,7 @@ pbn_status batch_enqueue(const pbn_plan* const* plans, uint32_t nitems, const pb
   p.wave_bytes = sh.wave_bytes;
   p.gshift = 1;
   p.ctl = d_ctl;
+  p.q = q;
   const uint32_t lds = 16u + wpb * sh.wave_bytes;
   if (sh.pm == 5) {
     if (sh.um == 0) return launch_batch_t<5, 0>(p, lds, s, sched);
@@ -2248,38 +2291,56 @@ pbn_status batch_enqueue(const pbn_plan* const* plans, uint32_t nitems, const pb
 }  // namespace
 
 extern "C" pbn_status pbn_batch_tasks(const pbn_plan* const* plans, const uint32_t* ntraj, uint32_t nitems,
-                                      uint32_t wpb, uint32_t* tasks, uint32_t* task_first, uint32_t* ntasks) {
+                                      uint32_t wpb, uint32_t nqueues, uint32_t* tasks, uint32_t* task_first,
+                                      uint32_t* queue_first, uint32_t* ntasks) {
   pbn::clear_error();
   if (!plans || !ntraj || !ntasks || wpb < 1 || wpb > 16) return fail(PBN_EINVAL, "bad argument");
-  // largest networks (most slots x passes) first, so the tail of the persistent
-  // launch is made of short tasks
+  if (nqueues < 1 || nqueues > PBN_BATCH_QUEUES) return fail(PBN_EINVAL, "nqueues must be 1..PBN_BATCH_QUEUES");
+  // per-step cost of one trajectory: lane passes and Philox jobs, then slots
+  std::vector<uint64_t> cost(nitems);
   std::vector<uint32_t> order(nitems);
   for (uint32_t k = 0; k < nitems; ++k) {
     if (!plans[k]) return fail(PBN_EINVAL, "null plan in batch");
     if (plans[k]->sampling) return fail(PBN_EINVAL, "alias-sampling plans are not supported by the batch entry points");
+    cost[k] = uint64_t(plans[k]->info.n_passes) * plans[k]->n_jobs + plans[k]->info.n_slots;
     order[k] = k;
   }
-  std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
-    return uint64_t(plans[a]->info.n_passes) * plans[a]->n_jobs + plans[a]->info.n_slots >
-           uint64_t(plans[b]->info.n_passes) * plans[b]->n_jobs + plans[b]->info.n_slots;
-  });
-  uint32_t count = 0;
+  // largest networks first, so the tail of each queue is made of short tasks
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return cost[a] > cost[b]; });
+  // each network, in that order, to the queue with the least work so far
+  // (ties: the lowest queue)
+  std::vector<uint32_t> queue_of(nitems, 0);
+  uint64_t load[PBN_BATCH_QUEUES] = {};
   for (uint32_t k : order) {
-    for (uint32_t f = 0; f < ntraj[k]; f += wpb) {
-      if (tasks) tasks[count] = k;
-      if (task_first) task_first[count] = f;
-      ++count;
+    uint32_t best = 0;
+    for (uint32_t j = 1; j < nqueues; ++j)
+      if (load[j] < load[best]) best = j;
+    queue_of[k] = best;
+    load[best] += cost[k] * ((uint64_t(ntraj[k]) + wpb - 1) / wpb);
+  }
+  uint32_t count = 0;
+  for (uint32_t j = 0; j < PBN_BATCH_QUEUES; ++j) {
+    if (queue_first) queue_first[j] = count;
+    for (uint32_t k : order) {
+      if (queue_of[k] != j) continue;
+      for (uint32_t f = 0; f < ntraj[k]; f += wpb) {
+        if (tasks) tasks[count] = k;
+        if (task_first) task_first[count] = f;
+        ++count;
+      }
     }
   }
+  if (queue_first) queue_first[PBN_BATCH_QUEUES] = count;
   *ntasks = count;
   return PBN_OK;
 }
 
 extern "C" pbn_status pbn_batch_launch(const pbn_plan* const* plans, uint32_t nitems, const pbn_work* d_items,
                                        const uint32_t* d_tasks, const uint32_t* d_task_first, uint32_t ntasks,
-                                       pbn_batch_ctl* d_ctl, uint32_t waves_per_block, void* stream) {
+                                       const uint32_t* queue_first, pbn_batch_ctl* d_ctl, uint32_t waves_per_block,
+                                       void* stream) {
   pbn::clear_error();
-  return batch_enqueue(plans, nitems, d_items, d_tasks, d_task_first, ntasks, d_ctl, waves_per_block,
+  return batch_enqueue(plans, nitems, d_items, d_tasks, d_task_first, ntasks, queue_first, d_ctl, waves_per_block,
                        static_cast<hipStream_t>(stream));
 }
 
@@ -2330,14 +2391,14 @@ extern "C" pbn_status pbn_batch_launch_noalloc(const pbn_plan* const* plans, con
   if (st != PBN_OK) return st;
   const NoAllocSched sched{nitems, step0, nsteps, uint32_t(total)};
   return batch_enqueue(plans, nitems, d_items, scr + kScratchCtlWords, scr + kScratchCtlWords + kNoAllocMaxTasks,
-                       PBN_NONE, reinterpret_cast<pbn_batch_ctl*>(scr), waves_per_block,
+                       PBN_NONE, nullptr, reinterpret_cast<pbn_batch_ctl*>(scr), waves_per_block,
                        static_cast<hipStream_t>(stream), &sched);
 }
 
 extern "C" pbn_status pbn_batch_graph_create(const pbn_plan* const* plans, uint32_t nitems, const pbn_work* d_items,
                                              const uint32_t* d_tasks, const uint32_t* d_task_first, uint32_t ntasks,
-                                             pbn_batch_ctl* d_ctl, uint32_t waves_per_block, uint32_t passes,
-                                             pbn_graph** out) {
+                                             const uint32_t* queue_first, pbn_batch_ctl* d_ctl,
+                                             uint32_t waves_per_block, uint32_t passes, pbn_graph** out) {
   pbn::clear_error();
   if (!out || passes == 0) return fail(PBN_EINVAL, "bad argument");
   *out = nullptr;
@@ -2347,7 +2408,8 @@ extern "C" pbn_status pbn_batch_graph_create(const pbn_plan* const* plans, uint3
   st = hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
   if (st == PBN_OK) {
     for (uint32_t k = 0; k < passes && st == PBN_OK; ++k)
-      st = batch_enqueue(plans, nitems, d_items, d_tasks, d_task_first, ntasks, d_ctl, waves_per_block, s);
+      st = batch_enqueue(plans, nitems, d_items, d_tasks, d_task_first, ntasks, queue_first, d_ctl,
+                         waves_per_block, s);
     hipGraph_t g = nullptr;
     const pbn_status end = hip_check(hipStreamEndCapture(s, &g), "hipStreamEndCapture");
     if (st == PBN_OK) st = end;

@@ -128,11 +128,12 @@ class _Lane:
         self.stream = torch.cuda.Stream()           # default priority
         with torch.cuda.stream(self.stream):
             self.res = _Resident(torch)
-            self.ctl = torch.tensor([0, 0, self.chunk, 0], dtype=torch.int32, device="cuda")
+            self.ctl = api.new_ctl(0, self.chunk)
         self.window = 0            # host mirror of the control block's step window
         self.dirty = True          # the lane's query set changed since its items were written
         self.active = []
         self.ntasks = 0
+        self.queue_first = None    # the launch's task-queue bounds (host)
         self.plans_arr = None
         self.inflight = None       # (queries, steps after the launch, pinned counts, event)
         self.launches = 0
@@ -140,7 +141,8 @@ class _Lane:
 
 class Server:
     def __init__(self, nets, net_seeds, *, plan_opts=None, traj_per_query=256, chunk=1000, burn_in=1000,
-                 min_counted=1000, max_steps=400000, waves_per_block=4, footprint=None, chunk_classes=3):
+                 min_counted=1000, max_steps=400000, waves_per_block=4, footprint=None, chunk_classes=3,
+                 task_queues=api.BATCH_QUEUES):
         import torch
         self.torch = torch
         self.nets = nets
@@ -153,6 +155,7 @@ class Server:
         self.min_counted = int(min_counted)
         self.max_steps = int(max_steps)
         self.wpb = int(waves_per_block)
+        self.task_queues = int(task_queues)   # per launch: networks dealt to the XCDs' task queues
         self.fp = footprint or Footprint()
         self.plans = {}
         self.base_interest = [non_sink_nodes(net) for net in nets]
@@ -253,17 +256,9 @@ class Server:
                                      q._counts.data_ptr(), q._seed, 0, self.ntraj, self.burn_in, off)
         lane.plans_arr = (api.C.c_void_p * len(act))(*[q._plan.handle.value for q in act])
         ntraj = np.full(len(act), self.ntraj, dtype=np.uint32)
-        nt = api.C.c_uint32()
-        L = _lib.lib()
-        _lib.check(L.pbn_batch_tasks(lane.plans_arr, api._ptr(ntraj, api.C.c_uint32), len(act), self.wpb, None,
-                                     None, api.C.byref(nt)))
-        tasks = np.zeros(nt.value, dtype=np.uint32)
-        first = np.zeros(nt.value, dtype=np.uint32)
-        _lib.check(L.pbn_batch_tasks(lane.plans_arr, api._ptr(ntraj, api.C.c_uint32), len(act), self.wpb,
-                                     api._ptr(tasks, api.C.c_uint32), api._ptr(first, api.C.c_uint32),
-                                     api.C.byref(nt)))
+        tasks, first, lane.queue_first = api.batch_schedule(lane.plans_arr, ntraj, self.wpb, self.task_queues)
         lane.res.upload(works, tasks, first)
-        lane.ntasks = nt.value
+        lane.ntasks = int(tasks.size)
         lane.dirty = False
 
     def _enqueue(self, lane):
@@ -278,7 +273,8 @@ class Server:
             L = _lib.lib()
             _lib.check(L.pbn_batch_launch(lane.plans_arr, len(act), api._dptr(lane.res.items),
                                           api._dptr(lane.res.tasks), api._dptr(lane.res.first), lane.ntasks,
-                                          api._dptr(lane.ctl), self.wpb, api._stream(lane.stream)))
+                                          api._ptr(lane.queue_first, api.C.c_uint32), api._dptr(lane.ctl),
+                                          self.wpb, api._stream(lane.stream)))
             lane.window = (lane.window + lane.chunk) & 0xFFFFFFFF
             for q in act:
                 q.steps += lane.chunk

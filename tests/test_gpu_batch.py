@@ -96,7 +96,7 @@ def test_batch_graph_replays_match_eager_launches():
         for k in range(len(items)):
             assert np.array_equal(b.states[k].cpu().numpy(), ref[k][0]), f"replay {replay} network {k}"
             assert np.array_equal(b.counts[k].cpu().numpy(), ref[k][1]), f"replay {replay} network {k}"
-    assert int(b.ctl.cpu()[1]) == 400
+    assert b.step0() == 400
 
 
 def test_batch_large_uneven_sampled():
@@ -266,3 +266,34 @@ def test_batch_launch_shape_probe_leaves_results_unchanged():
         runs.append(([s.cpu().numpy() for s in b.states], [c.cpu().numpy() for c in b.counts]))
     for k in range(len(items)):
         assert np.array_equal(runs[0][0][k], runs[1][0][k]) and np.array_equal(runs[0][1][k], runs[1][1][k]), k
+
+
+def test_task_queues_leave_results_unchanged():
+    """Networks dealt to one, three or all eight task queues (workgroups
+    steal from other queues once their own is empty): which workgroup runs a
+    trajectory changes nothing in its states or counters, also over a second
+    window and for an oracle-checked network."""
+    items, nets = make_items(13, 23, 20, 600, [64, 9, 130], True)
+    say("[gpu] batch task queues 1 / 3 / 8")
+    runs = []
+    for nq in (1, 3, api.BATCH_QUEUES):
+        b = api.Batch(items, count_from=20, waves_per_block=4, queues=nq)
+        assert b.queue_first[-1] == b.ntasks
+        b.init_states()
+        b.set_window(0, 90)
+        b.launch()
+        b.set_window(90, 60)
+        b.launch()
+        torch.cuda.synchronize()
+        runs.append(([s.cpu().numpy() for s in b.states], [c.cpu().numpy() for c in b.counts], b))
+    for r in runs[1:]:
+        for k in range(len(items)):
+            assert np.array_equal(runs[0][0][k], r[0][k]) and np.array_equal(runs[0][1][k], r[1][k]), k
+    plan, seed, ntraj, tgs = items[2]
+    ref = osim.run(nets[2], seed, np.arange(ntraj), 150, targets=tgs, count_from=20)
+    orig = api.unpack_bits(api.to_original(plan, runs[-1][2].states[2]).cpu().numpy(), plan.n)
+    kept = plan.node_pos() != NONE
+    assert np.array_equal(orig[:, kept], ref["state"][:, kept])
+    c = runs[-1][1][2]
+    assert np.array_equal(c[:, :, 0], ref["hits"]) and np.array_equal(c[:, :, 1], ref["n01"])
+    assert np.array_equal(c[:, :, 2], ref["n10"])

@@ -151,10 +151,10 @@ def test_batch_entry_points_reject_alias_plans():
     arr = (C.c_void_p * 1)(plan.handle.value)
     ntraj = (C.c_uint32 * 1)(4)
     nt = C.c_uint32()
-    assert lib().pbn_batch_tasks(arr, ntraj, 1, 4, None, None, C.byref(nt)) != 0
+    assert lib().pbn_batch_tasks(arr, ntraj, 1, 4, 1, None, None, None, C.byref(nt)) != 0
     keyed = api.Plan(NETS["tiny"], interest=[0])
     arr = (C.c_void_p * 1)(keyed.handle.value)
-    assert lib().pbn_batch_tasks(arr, ntraj, 1, 4, None, None, C.byref(nt)) == 0 and nt.value == 1
+    assert lib().pbn_batch_tasks(arr, ntraj, 1, 4, 1, None, None, None, C.byref(nt)) == 0 and nt.value == 1
 
 
 @pytest.mark.parametrize("opts", [dict(reduce=1, group=0), dict(reduce=1, group=1, lds_budget_bytes=0),
