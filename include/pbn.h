@@ -450,12 +450,15 @@ double pbn_normal_quantile(double p);
  * Many networks of uneven size advanced together by one persistent launch
  * (the step kernel of pbn_simulate, per trajectory, with a task loop on top).
  * A task is up to `waves_per_block` consecutive trajectories of one network.
- * The task list is cut into PBN_BATCH_QUEUES queues, each a run of whole
- * networks: workgroups are dispatched to the chip's eight XCDs in turn, and
- * workgroup b claims tasks from queue b mod PBN_BATCH_QUEUES with one atomic
- * increment of that queue's counter, then from the next queues in turn once
- * its own is empty, and exits when every queue is empty.  A queue's networks
- * thus share the vector L1 caches of one XCD's CUs.  Every item is simulated
+ * The task list is cut into `nqueues` queues (at most PBN_BATCH_QUEUES), each
+ * a run of whole networks.  Workgroup b claims tasks from queue b mod nqueues
+ * with one atomic increment of that queue's counter, then from the other
+ * queues once its own is empty, and exits when every queue is empty.  The
+ * dispatcher sends workgroup b to XCD b mod 8 and, within the XCD, to its 32
+ * CUs in turn; so with nqueues = 8 G the workgroups of a queue run on their
+ * own group of 32 / G CUs of one XCD, and the CUs of a group share the
+ * images of few networks in their vector L1 caches.  A workgroup whose queue
+ * is empty tries the other groups of its XCD before other XCDs.  Every item is simulated
  * over the device-held step window [d_ctl->step0, d_ctl->step0 + d_ctl->nsteps);
  * each launch resets the queue counters first and advances step0 by nsteps
  * last, with small kernels (no memset, no allocation, no host
@@ -471,15 +474,16 @@ double pbn_normal_quantile(double p);
  *              step0 + d_ctl->step0 .. + d_ctl->nsteps - 1 (callers must keep the
  *              sum below 2^32)
  * pbn_batch_tasks: host; the schedule.  Networks are dealt to `nqueues` queues
- *   (1..PBN_BATCH_QUEUES; the rest stay empty), largest first, each to the
- *   queue with the least work so far (work = tasks x a per-step cost from the
- *   plan's passes, Philox jobs and slots); within a queue, largest networks
- *   first.  tasks / task_first receive the item and first trajectory of each
- *   task in queue order, queue_first[PBN_BATCH_QUEUES + 1] the first task of
- *   each queue and the total (each may be NULL; all NULL to query *ntasks).
+ *   (1..PBN_BATCH_QUEUES), largest first, each to the queue with the least
+ *   work so far (work = tasks x a per-step cost from the plan's passes, Philox
+ *   jobs and slots); within a queue, largest networks first.  tasks /
+ *   task_first receive the item and first trajectory of each task in queue
+ *   order, queue_first[nqueues + 1] the first task of each queue and the
+ *   total (each may be NULL; all NULL to query *ntasks).
  * pbn_batch_launch: enqueue one pass on `stream`.  queue_first: host, the
- *   PBN_BATCH_QUEUES + 1 bounds from pbn_batch_tasks (non-decreasing, from 0
- *   to ntasks), copied into the launch; NULL: one queue of all tasks.
+ *   nqueues + 1 bounds from pbn_batch_tasks (non-decreasing, from 0 to
+ *   ntasks), copied into the launch; NULL: one queue of all tasks (nqueues
+ *   ignored).
  * pbn_batch_graph_create: capture `passes` consecutive launches into a graph,
  *   replayed by pbn_graph_launch (each replay advances by passes * nsteps).
  * Errors: PBN_EINVAL, PBN_ELDS (one workgroup's states exceed LDS), PBN_EHIP. */
@@ -494,7 +498,7 @@ typedef struct pbn_work {
   uint32_t step0;
 } pbn_work;
 
-#define PBN_BATCH_QUEUES 8
+#define PBN_BATCH_QUEUES 64
 
 typedef struct pbn_batch_ctl {
   uint32_t step0;
@@ -511,12 +515,12 @@ pbn_status pbn_batch_tasks(const pbn_plan* const* plans, const uint32_t* ntraj, 
                            uint32_t* queue_first, uint32_t* ntasks);
 pbn_status pbn_batch_launch(const pbn_plan* const* plans, uint32_t nitems, const pbn_work* d_items,
                             const uint32_t* d_tasks, const uint32_t* d_task_first, uint32_t ntasks,
-                            const uint32_t* queue_first, pbn_batch_ctl* d_ctl, uint32_t waves_per_block,
-                            void* stream);
+                            const uint32_t* queue_first, uint32_t nqueues, pbn_batch_ctl* d_ctl,
+                            uint32_t waves_per_block, void* stream);
 pbn_status pbn_batch_graph_create(const pbn_plan* const* plans, uint32_t nitems, const pbn_work* d_items,
                                   const uint32_t* d_tasks, const uint32_t* d_task_first, uint32_t ntasks,
-                                  const uint32_t* queue_first, pbn_batch_ctl* d_ctl, uint32_t waves_per_block,
-                                  uint32_t passes, pbn_graph** out);
+                                  const uint32_t* queue_first, uint32_t nqueues, pbn_batch_ctl* d_ctl,
+                                  uint32_t waves_per_block, uint32_t passes, pbn_graph** out);
 pbn_status pbn_graph_launch(pbn_graph* graph, void* stream);
 
 /* Allocation-free batch launch, for callers that cannot allocate device
@@ -529,7 +533,7 @@ pbn_status pbn_graph_launch(pbn_graph* graph, void* stream);
  *   ntraj[nitems]  host: the items' trajectory counts (must equal d_items[k].ntraj)
  *   d_items        device: the work items, as pbn_batch_launch
  * The control block and the task schedule live in a device array of the
- * library (512.25 KiB per GPU, held until the process ends) instead of caller
+ * library (512.5 KiB per GPU, held until the process ends) instead of caller
  * buffers: at most 4096 items and 65 536 tasks of waves_per_block trajectories
  * per call (PBN_ELIMIT beyond).  Items run in the caller's order, from one
  * queue (list the largest networks first, as pbn_batch_tasks orders them).  The call makes no

@@ -333,10 +333,14 @@ def _to_device_bytes(obj):
     return torch.from_numpy(raw).to("cuda")
 
 
-# task queues of a batched launch (PBN_BATCH_QUEUES) and the words of its
-# control block: step0, nsteps, ntasks, reserved, one claim counter per queue
-BATCH_QUEUES = 8
+# the most task queues of a batched launch (PBN_BATCH_QUEUES), the words of
+# its control block (step0, nsteps, ntasks, reserved, one claim counter per
+# queue) and the default queue count: 8 G queues give each group of 32 / G CUs
+# of an XCD its own queue; 64 (four CUs a queue) was the fastest of 1 to 256
+# on the 512-network batch
+BATCH_QUEUES = 64
 CTL_WORDS = 4 + BATCH_QUEUES
+DEFAULT_QUEUES = 64
 
 
 def new_ctl(step0=0, nsteps=0):
@@ -346,16 +350,16 @@ def new_ctl(step0=0, nsteps=0):
     return torch.tensor(words, dtype=torch.int32, device="cuda")
 
 
-def batch_schedule(plans_arr, ntraj, wpb, queues=BATCH_QUEUES):
+def batch_schedule(plans_arr, ntraj, wpb, queues=DEFAULT_QUEUES):
     """pbn_batch_tasks: (item of each task, its first trajectory, the
-    BATCH_QUEUES + 1 queue bounds), all uint32 host arrays."""
+    queues + 1 queue bounds), all uint32 host arrays."""
     ntraj = np.ascontiguousarray(ntraj, dtype=np.uint32)
     nt = C.c_uint32()
     check(lib().pbn_batch_tasks(plans_arr, _ptr(ntraj, C.c_uint32), ntraj.size, int(wpb), int(queues),
                                 None, None, None, C.byref(nt)))
     tasks = np.zeros(max(1, nt.value), dtype=np.uint32)
     first = np.zeros(max(1, nt.value), dtype=np.uint32)
-    qfirst = np.zeros(BATCH_QUEUES + 1, dtype=np.uint32)
+    qfirst = np.zeros(int(queues) + 1, dtype=np.uint32)
     check(lib().pbn_batch_tasks(plans_arr, _ptr(ntraj, C.c_uint32), ntraj.size, int(wpb), int(queues),
                                 _ptr(tasks, C.c_uint32), _ptr(first, C.c_uint32), _ptr(qfirst, C.c_uint32),
                                 C.byref(nt)))
@@ -367,11 +371,11 @@ class Batch:
 
     items: list of (plan, seed, ntraj, target_sets); every trajectory of every
     network shares the device step window held in the control block.
-    queues: how many of the launch's task queues (one per XCD) receive
-    networks; 1 puts every task in one queue.
+    queues: task queues of the launch (1 .. BATCH_QUEUES); 1 puts every task
+    in one queue.
     """
 
-    def __init__(self, items, count_from=0, waves_per_block=4, queues=BATCH_QUEUES):
+    def __init__(self, items, count_from=0, waves_per_block=4, queues=DEFAULT_QUEUES):
         import torch
         self.plans = [it[0] for it in items]
         self.wpb = int(waves_per_block)
@@ -395,7 +399,8 @@ class Batch:
         self._plan_arr = (C.c_void_p * len(items))(*[p.handle.value for p in self.plans])
         ntraj = np.asarray([it[2] for it in items], dtype=np.uint32)
         self._ntraj = ntraj
-        tasks, first, self.queue_first = batch_schedule(self._plan_arr, ntraj, self.wpb, queues)
+        self.nqueues = int(queues)
+        tasks, first, self.queue_first = batch_schedule(self._plan_arr, ntraj, self.wpb, self.nqueues)
         self.ntasks = int(tasks.size)
         pad = np.zeros(1, dtype=np.uint32)    # device arrays of at least one element
         self.tasks_dev = torch.from_numpy((tasks if tasks.size else pad).astype(np.int32)).to("cuda")
@@ -416,8 +421,8 @@ class Batch:
 
     def _args(self):
         return (self._plan_arr, len(self.plans), _dptr(self.items_dev), _dptr(self.tasks_dev),
-                _dptr(self.first_dev), self.ntasks, _ptr(self.queue_first, C.c_uint32), _dptr(self.ctl),
-                self.wpb)
+                _dptr(self.first_dev), self.ntasks, _ptr(self.queue_first, C.c_uint32), self.nqueues,
+                _dptr(self.ctl), self.wpb)
 
     def launch(self, stream=None):
         check(lib().pbn_batch_launch(*self._args(), _stream(stream)))

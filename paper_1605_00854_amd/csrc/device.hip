@@ -1602,17 +1602,21 @@ __global__ void __launch_bounds__(1024) k_simulate_bits(SimParams a) {
 
 // ---------------------------------------------------------------- batches
 // Many networks of uneven size in one persistent launch.  Work is cut into
-// tasks of `wpb` consecutive trajectories of one network, in PBN_BATCH_QUEUES
-// queues of whole networks, ordered by the host (largest networks first within
-// a queue).  The dispatcher hands workgroups to the eight XCDs in turn, so
-// workgroup b starts on queue b mod PBN_BATCH_QUEUES: the networks of a queue
-// run on one XCD and share its CUs' vector L1 caches, where one queue for the
-// whole chip would mix the images of every network in flight on each CU.  A
+// tasks of `wpb` consecutive trajectories of one network, in nq queues of
+// whole networks, ordered by the host (largest networks first within a
+// queue).  The dispatcher sends workgroup b to XCD b mod 8 and, within the
+// XCD, to its 32 CUs in turn, so the CU of a resident workgroup follows from
+// b mod 256; with nq = 8 G, workgroup b starts on queue b mod nq, and the
+// workgroups of a queue fill their own group of 32 / G CUs of one XCD, whose
+// vector L1 caches then hold the images of few networks (one queue for the
+// whole chip mixed the images of every network in flight on each CU).  A
 // workgroup repeatedly claims the next task of its queue with one atomic
-// increment, moves on to the next queue when its own is empty (a queue found
-// empty stays empty: its counter only grows), and stops after the last one,
-// so every wave reaches the exit.  Plan images stay in global memory (the L2
-// serves them); each wave's LDS holds its trajectory's state buffers and
+// increment; when its queue is empty it tries the other groups of its XCD,
+// then those of the next XCDs (a queue found empty stays empty: its counter
+// only grows), and it stops after the last one, so every wave reaches the
+// exit.  The placement only decides which caches a task shares; any other
+// placement gives the same results.  Plan images stay in global memory (the
+// L2 serves them); each wave's LDS holds its trajectory's state buffers and
 // Philox ring.
 struct QueueBounds {
   uint32_t first[PBN_BATCH_QUEUES + 1];   // queue k: tasks first[k] .. first[k + 1] - 1
@@ -1627,6 +1631,7 @@ struct BatchParams {
   uint32_t wave_bytes;
   uint32_t gshift;                 // 1: the gather step's shift, passed at run time (see shl_or)
   pbn_batch_ctl* ctl;              // device: queue counters and the step window
+  uint32_t nq;                     // queues, 1 .. PBN_BATCH_QUEUES
   QueueBounds q;
 };
 
@@ -1637,25 +1642,31 @@ struct BatchParams {
 template <int PM, int UM, bool PF>
 __global__ void __launch_bounds__(1024) k_batch(BatchParams a, const pbn_work* __restrict__ items) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-  uint32_t& claimed = *reinterpret_cast<uint32_t*>(smem);   // first 16 bytes: the claimed task
+  // first 16 bytes: the claimed task, and how many queues thread 0 has found
+  // empty (kept here, not in a register live across the trajectory body)
+  uint32_t& claimed = *reinterpret_cast<uint32_t*>(smem);
+  uint32_t& tried = *reinterpret_cast<uint32_t*>(smem + 4);
   const uint32_t wave = uniform(threadIdx.x >> 6);   // wave-uniform: keeps per-trajectory data scalar
   const uint32_t wstep0 = a.ctl->step0, nsteps = a.ctl->nsteps;
-  const uint32_t home = blockIdx.x % PBN_BATCH_QUEUES;
-  uint32_t tried = 0;   // queues found empty (thread 0's own count)
+  if (threadIdx.x == 0) tried = 0;
   for (;;) {
     if (threadIdx.x == 0) {
-      uint32_t task = PBN_NONE;
-      for (; tried < PBN_BATCH_QUEUES; ++tried) {
-        const uint32_t k = (home + tried) % PBN_BATCH_QUEUES;
+      const uint32_t nq = a.nq, home = blockIdx.x % nq;
+      const uint32_t groups = nq % 8u == 0 ? nq / 8u : 0u;   // CU groups per XCD
+      uint32_t task = PBN_NONE, t = tried;
+      for (; t < nq; ++t) {
+        // the groups of the home XCD first (8 a + c runs over 0 .. nq - 1 once)
+        const uint32_t k = groups ? (home + 8u * (t % groups) + t / groups) % nq : (home + t) % nq;
         // PBN_NONE: the schedule was written on the device (allocation-free launch)
         const uint32_t end = a.ntasks != PBN_NONE ? a.q.first[k + 1] : (k == 0 ? a.ctl->ntasks : 0u);
         if (a.q.first[k] >= end) continue;   // an empty queue costs no atomic
-        const uint32_t t = atomicAdd(&a.ctl->next_task[k], 1u);
-        if (t < end) {
-          task = t;
+        const uint32_t c = atomicAdd(&a.ctl->next_task[k], 1u);
+        if (c < end) {
+          task = c;
           break;
         }
       }
+      tried = t;
       claimed = task;
     }
     __syncthreads();
@@ -1695,8 +1706,8 @@ __global__ void __launch_bounds__(1024) k_batch(BatchParams a, const pbn_work* _
 
 // Graph-friendly control updates (no memset nodes): set each queue's counter
 // to its first task before a batch pass, advance the step window after it.
-__global__ void k_batch_begin(pbn_batch_ctl* ctl, QueueBounds q) {
-  if (threadIdx.x < PBN_BATCH_QUEUES) ctl->next_task[threadIdx.x] = q.first[threadIdx.x];
+__global__ void k_batch_begin(pbn_batch_ctl* ctl, QueueBounds q, uint32_t nq) {
+  if (threadIdx.x < nq) ctl->next_task[threadIdx.x] = q.first[threadIdx.x];
 }
 __global__ void k_batch_end(pbn_batch_ctl* ctl) { ctl->step0 += ctl->nsteps; }
 
@@ -1708,9 +1719,10 @@ __global__ void k_batch_end(pbn_batch_ctl* ctl) { ctl->step0 += ctl->nsteps; }
 // through the address hipGetSymbolAddress returns for the current device.
 constexpr uint32_t kNoAllocMaxItems = 4096u;    // work items per call
 constexpr uint32_t kNoAllocMaxTasks = 65536u;   // tasks (waves_per_block trajectories of one item) per call
-constexpr uint32_t kScratchCtlWords = 64u;      // the control block, alone in the first 256 bytes
+constexpr uint32_t kScratchCtlWords = 128u;     // the control block, alone in the first 512 bytes
+static_assert(sizeof(pbn_batch_ctl) <= 4u * kScratchCtlWords, "control block exceeds its scratch region");
 constexpr size_t kScratchWords = kScratchCtlWords + 2u * size_t(kNoAllocMaxTasks);
-static __device__ __align__(256) uint32_t scratch[kScratchWords];   // 512.25 KiB
+static __device__ __align__(256) uint32_t scratch[kScratchWords];   // 512.5 KiB
 
 // The schedule of one allocation-free launch, written by one workgroup of
 // 1024 threads: items in the caller's order, ceil(ntraj / wpb) tasks each
@@ -1745,7 +1757,7 @@ __global__ void __launch_bounds__(1024) k_noalloc_schedule(const pbn_work* items
   }
   if (t == 1023u) {
     pbn_batch_ctl* ctl = reinterpret_cast<pbn_batch_ctl*>(scr);
-    for (uint32_t k = 0; k < PBN_BATCH_QUEUES; ++k) ctl->next_task[k] = 0;
+    ctl->next_task[0] = 0;   // one queue
     ctl->step0 = step0;
     ctl->nsteps = nsteps;
     ctl->ntasks = min(part[1023], kNoAllocMaxTasks);
@@ -2236,7 +2248,7 @@ pbn_status launch_batch_t(const BatchParams& p, uint32_t lds, hipStream_t s, con
                        sched->nsteps, reinterpret_cast<uint32_t*>(p.ctl));
     hipLaunchKernelGGL(fn, dim3(blocks), dim3(64u * p.wpb), lds, s, p, p.items);
   } else {
-    hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(64), 0, s, p.ctl, p.q);
+    hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(PBN_BATCH_QUEUES), 0, s, p.ctl, p.q, p.nq);
     hipLaunchKernelGGL(fn, dim3(blocks), dim3(64u * p.wpb), lds, s, p, p.items);
     hipLaunchKernelGGL(k_batch_end, dim3(1), dim3(1), 0, s, p.ctl);
   }
@@ -2245,23 +2257,25 @@ pbn_status launch_batch_t(const BatchParams& p, uint32_t lds, hipStream_t s, con
 
 pbn_status batch_enqueue(const pbn_plan* const* plans, uint32_t nitems, const pbn_work* d_items,
                          const uint32_t* d_tasks, const uint32_t* d_task_first, uint32_t ntasks,
-                         const uint32_t* queue_first, pbn_batch_ctl* d_ctl, uint32_t wpb, hipStream_t s,
-                         const NoAllocSched* sched = nullptr) {
+                         const uint32_t* queue_first, uint32_t nq, pbn_batch_ctl* d_ctl, uint32_t wpb,
+                         hipStream_t s, const NoAllocSched* sched = nullptr) {
   if (!plans || !d_items || !d_tasks || !d_task_first || !d_ctl) return fail(PBN_EINVAL, "null argument");
   if (wpb < 1 || wpb > 16) return fail(PBN_EINVAL, "waves_per_block must be 1..16");
   if (nitems == 0 || ntasks == 0) return PBN_OK;
   QueueBounds q{};
-  if (sched) {
-    // one queue, bounded on the device by the schedule's task count
-  } else if (queue_first) {
-    if (queue_first[0] != 0 || queue_first[PBN_BATCH_QUEUES] != ntasks)
+  if (sched || !queue_first) {
+    // one queue (the allocation-free launch bounds it on the device by the
+    // schedule's task count)
+    nq = 1;
+    q.first[1] = ntasks;
+  } else {
+    if (nq < 1 || nq > PBN_BATCH_QUEUES) return fail(PBN_EINVAL, "nqueues must be 1..PBN_BATCH_QUEUES");
+    if (queue_first[0] != 0 || queue_first[nq] != ntasks)
       return fail(PBN_EINVAL, "queue bounds must run from 0 to ntasks");
-    for (uint32_t k = 0; k <= PBN_BATCH_QUEUES; ++k) {
+    for (uint32_t k = 0; k <= nq; ++k) {
       if (k > 0 && queue_first[k] < queue_first[k - 1]) return fail(PBN_EINVAL, "queue bounds must not decrease");
       q.first[k] = queue_first[k];
     }
-  } else {
-    for (uint32_t k = 1; k <= PBN_BATCH_QUEUES; ++k) q.first[k] = ntasks;
   }
   BatchShape sh;
   pbn_status st = batch_shape(plans, nitems, sh);
@@ -2276,6 +2290,7 @@ pbn_status batch_enqueue(const pbn_plan* const* plans, uint32_t nitems, const pb
   p.wave_bytes = sh.wave_bytes;
   p.gshift = 1;
   p.ctl = d_ctl;
+  p.nq = nq;
   p.q = q;
   const uint32_t lds = 16u + wpb * sh.wave_bytes;
   if (sh.pm == 5) {
@@ -2319,7 +2334,7 @@ extern "C" pbn_status pbn_batch_tasks(const pbn_plan* const* plans, const uint32
     load[best] += cost[k] * ((uint64_t(ntraj[k]) + wpb - 1) / wpb);
   }
   uint32_t count = 0;
-  for (uint32_t j = 0; j < PBN_BATCH_QUEUES; ++j) {
+  for (uint32_t j = 0; j < nqueues; ++j) {
     if (queue_first) queue_first[j] = count;
     for (uint32_t k : order) {
       if (queue_of[k] != j) continue;
@@ -2330,18 +2345,18 @@ extern "C" pbn_status pbn_batch_tasks(const pbn_plan* const* plans, const uint32
       }
     }
   }
-  if (queue_first) queue_first[PBN_BATCH_QUEUES] = count;
+  if (queue_first) queue_first[nqueues] = count;
   *ntasks = count;
   return PBN_OK;
 }
 
 extern "C" pbn_status pbn_batch_launch(const pbn_plan* const* plans, uint32_t nitems, const pbn_work* d_items,
                                        const uint32_t* d_tasks, const uint32_t* d_task_first, uint32_t ntasks,
-                                       const uint32_t* queue_first, pbn_batch_ctl* d_ctl, uint32_t waves_per_block,
-                                       void* stream) {
+                                       const uint32_t* queue_first, uint32_t nqueues, pbn_batch_ctl* d_ctl,
+                                       uint32_t waves_per_block, void* stream) {
   pbn::clear_error();
-  return batch_enqueue(plans, nitems, d_items, d_tasks, d_task_first, ntasks, queue_first, d_ctl, waves_per_block,
-                       static_cast<hipStream_t>(stream));
+  return batch_enqueue(plans, nitems, d_items, d_tasks, d_task_first, ntasks, queue_first, nqueues, d_ctl,
+                       waves_per_block, static_cast<hipStream_t>(stream));
 }
 
 namespace {
@@ -2391,13 +2406,13 @@ extern "C" pbn_status pbn_batch_launch_noalloc(const pbn_plan* const* plans, con
   if (st != PBN_OK) return st;
   const NoAllocSched sched{nitems, step0, nsteps, uint32_t(total)};
   return batch_enqueue(plans, nitems, d_items, scr + kScratchCtlWords, scr + kScratchCtlWords + kNoAllocMaxTasks,
-                       PBN_NONE, nullptr, reinterpret_cast<pbn_batch_ctl*>(scr), waves_per_block,
+                       PBN_NONE, nullptr, 1, reinterpret_cast<pbn_batch_ctl*>(scr), waves_per_block,
                        static_cast<hipStream_t>(stream), &sched);
 }
 
 extern "C" pbn_status pbn_batch_graph_create(const pbn_plan* const* plans, uint32_t nitems, const pbn_work* d_items,
                                              const uint32_t* d_tasks, const uint32_t* d_task_first, uint32_t ntasks,
-                                             const uint32_t* queue_first, pbn_batch_ctl* d_ctl,
+                                             const uint32_t* queue_first, uint32_t nqueues, pbn_batch_ctl* d_ctl,
                                              uint32_t waves_per_block, uint32_t passes, pbn_graph** out) {
   pbn::clear_error();
   if (!out || passes == 0) return fail(PBN_EINVAL, "bad argument");
@@ -2408,7 +2423,7 @@ extern "C" pbn_status pbn_batch_graph_create(const pbn_plan* const* plans, uint3
   st = hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
   if (st == PBN_OK) {
     for (uint32_t k = 0; k < passes && st == PBN_OK; ++k)
-      st = batch_enqueue(plans, nitems, d_items, d_tasks, d_task_first, ntasks, queue_first, d_ctl,
+      st = batch_enqueue(plans, nitems, d_items, d_tasks, d_task_first, ntasks, queue_first, nqueues, d_ctl,
                          waves_per_block, s);
     hipGraph_t g = nullptr;
     const pbn_status end = hip_check(hipStreamEndCapture(s, &g), "hipStreamEndCapture");

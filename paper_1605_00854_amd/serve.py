@@ -142,7 +142,7 @@ class _Lane:
 class Server:
     def __init__(self, nets, net_seeds, *, plan_opts=None, traj_per_query=256, chunk=1000, burn_in=1000,
                  min_counted=1000, max_steps=400000, waves_per_block=4, footprint=None, chunk_classes=3,
-                 task_queues=api.BATCH_QUEUES):
+                 task_queues=api.DEFAULT_QUEUES):
         import torch
         self.torch = torch
         self.nets = nets
@@ -155,7 +155,7 @@ class Server:
         self.min_counted = int(min_counted)
         self.max_steps = int(max_steps)
         self.wpb = int(waves_per_block)
-        self.task_queues = int(task_queues)   # per launch: networks dealt to the XCDs' task queues
+        self.task_queues = int(task_queues)   # per launch: networks dealt to the CU groups' task queues
         self.fp = footprint or Footprint()
         self.plans = {}
         self.base_interest = [non_sink_nodes(net) for net in nets]
@@ -273,8 +273,8 @@ class Server:
             L = _lib.lib()
             _lib.check(L.pbn_batch_launch(lane.plans_arr, len(act), api._dptr(lane.res.items),
                                           api._dptr(lane.res.tasks), api._dptr(lane.res.first), lane.ntasks,
-                                          api._ptr(lane.queue_first, api.C.c_uint32), api._dptr(lane.ctl),
-                                          self.wpb, api._stream(lane.stream)))
+                                          api._ptr(lane.queue_first, api.C.c_uint32), self.task_queues,
+                                          api._dptr(lane.ctl), self.wpb, api._stream(lane.stream)))
             lane.window = (lane.window + lane.chunk) & 0xFFFFFFFF
             for q in act:
                 q.steps += lane.chunk

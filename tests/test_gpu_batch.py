@@ -269,14 +269,15 @@ def test_batch_launch_shape_probe_leaves_results_unchanged():
 
 
 def test_task_queues_leave_results_unchanged():
-    """Networks dealt to one, three or all eight task queues (workgroups
-    steal from other queues once their own is empty): which workgroup runs a
-    trajectory changes nothing in its states or counters, also over a second
-    window and for an oracle-checked network."""
+    """Networks dealt to one, three, eight, 32 or 64 task queues (workgroups
+    steal from other queues once their own is empty, and most of the 64
+    queues hold no network): which workgroup runs a trajectory changes nothing
+    in its states or counters, also over a second window and for an
+    oracle-checked network."""
     items, nets = make_items(13, 23, 20, 600, [64, 9, 130], True)
-    say("[gpu] batch task queues 1 / 3 / 8")
+    say("[gpu] batch task queues 1 / 3 / 8 / 32 / 64")
     runs = []
-    for nq in (1, 3, api.BATCH_QUEUES):
+    for nq in (1, 3, 8, 32, api.BATCH_QUEUES):
         b = api.Batch(items, count_from=20, waves_per_block=4, queues=nq)
         assert b.queue_first[-1] == b.ntasks
         b.init_states()

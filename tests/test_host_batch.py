@@ -37,19 +37,19 @@ def test_header_constants_match_the_binding():
     assert f"#define PBN_BATCH_QUEUES {api.BATCH_QUEUES}" in text
     # control block: step0, nsteps, ntasks, reserved, one counter per queue
     assert api.CTL_WORDS == 4 + api.BATCH_QUEUES
+    assert 1 <= api.DEFAULT_QUEUES <= api.BATCH_QUEUES and api.DEFAULT_QUEUES % 8 == 0
 
 
-@pytest.mark.parametrize("nqueues", [1, 3, 8])
+@pytest.mark.parametrize("nqueues", [1, 3, 8, 32, 64])
 def test_schedule_deals_whole_networks_to_queues(batch, nqueues):
     plans, arr, ntraj = batch
     tasks, first, qf = api.batch_schedule(arr, ntraj, WPB, nqueues)
     ntasks = int(sum((int(t) + WPB - 1) // WPB for t in ntraj))
-    assert tasks.size == ntasks and qf[0] == 0 and qf[-1] == ntasks
+    assert tasks.size == ntasks and qf.size == nqueues + 1 and qf[0] == 0 and qf[-1] == ntasks
     assert np.all(np.diff(qf.astype(np.int64)) >= 0)
-    assert np.all(qf[nqueues:] == ntasks)              # queues beyond nqueues are empty
     queue_of = {}
-    load = np.zeros(api.BATCH_QUEUES, dtype=np.int64)
-    for j in range(api.BATCH_QUEUES):
+    load = np.zeros(nqueues, dtype=np.int64)
+    for j in range(nqueues):
         seg_items = tasks[qf[j]:qf[j + 1]]
         seg_first = first[qf[j]:qf[j + 1]]
         # each network's tasks are one contiguous run of one queue, covering its
@@ -72,7 +72,7 @@ def test_schedule_deals_whole_networks_to_queues(batch, nqueues):
     # dealt largest first to the least-loaded queue: no queue exceeds another
     # by more than the largest single network's work
     biggest = max(cost(p) * ((int(t) + WPB - 1) // WPB) for p, t in zip(plans, ntraj))
-    assert load[:nqueues].max() - load[:nqueues].min() <= biggest
+    assert load.max() - load.min() <= biggest
 
 
 def test_one_queue_keeps_the_global_largest_first_order(batch):
@@ -80,7 +80,7 @@ def test_one_queue_keeps_the_global_largest_first_order(batch):
     tasks, first, qf = api.batch_schedule(arr, ntraj, WPB, 1)
     costs = [cost(plans[k]) for k in tasks]
     assert costs == sorted(costs, reverse=True)
-    assert list(qf) == [0] + [tasks.size] * api.BATCH_QUEUES
+    assert list(qf) == [0, tasks.size]
 
 
 def test_schedule_rejects_bad_queue_counts(batch):
@@ -91,15 +91,17 @@ def test_schedule_rejects_bad_queue_counts(batch):
                                      C.byref(nt)) != 0
 
 
-@pytest.mark.parametrize("bounds", [
-    [1, 2, 3, 4, 5, 6, 7, 8, 10],        # does not start at 0
-    [0, 2, 3, 4, 5, 6, 7, 8, 9],         # does not end at ntasks
-    [0, 5, 3, 6, 7, 8, 9, 10, 10],       # decreasing
+@pytest.mark.parametrize("bounds,message", [
+    ([1, 2, 3, 4, 5, 6, 7, 8, 10], b"queue bounds"),        # does not start at 0
+    ([0, 2, 3, 4, 5, 6, 7, 8, 9], b"queue bounds"),         # does not end at ntasks
+    ([0, 5, 3, 6, 7, 8, 9, 10, 10], b"queue bounds"),       # decreasing
+    ([0] * (api.BATCH_QUEUES + 1) + [10], b"nqueues"),      # more queues than the launch holds
 ])
-def test_launch_rejects_bad_queue_bounds_before_any_device_work(batch, bounds):
+def test_launch_rejects_bad_queue_bounds_before_any_device_work(batch, bounds, message):
     plans, arr, _ = batch
     qf = np.asarray(bounds, dtype=np.uint32)
     fake = C.c_void_p(256)                # never dereferenced: the bounds are checked first
-    st = lib().pbn_batch_launch(arr, 1, fake, fake, fake, 10, api._ptr(qf, C.c_uint32), fake, WPB, None)
+    st = lib().pbn_batch_launch(arr, 1, fake, fake, fake, 10, api._ptr(qf, C.c_uint32), qf.size - 1, fake, WPB,
+                                None)
     assert st == EINVAL
-    assert b"queue bounds" in lib().pbn_last_error()
+    assert message in lib().pbn_last_error()
