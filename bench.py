@@ -34,17 +34,16 @@ PEAK_ALU = 256 * 64 * 2.4e9        # int32 VALU lane-operations per second (256 
 L1_PROBE_LOG2 = 14                 # 16 KiB global probe buffer: fits the vector L1 of a CU
 PHILOX_SLOTS = 60                  # 10 rounds x (2 full-rate 32x32->64 multiplies + 4 two-input xors)
 
-# HBM bytes per k_simulate launch of the C2 workload (reduction plan), from two
-# rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by
-# what the same counters read for a 256 MiB device copy (fetch x 2.0, write x
-# 1.0).  Measured on 20 000-step launches; the kernel touches HBM only at launch
+# HBM bytes per k_simulate launch of the C2 and C3 workloads (product plans),
+# from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per
+# dispatch) scaled by what the same counters read for a 256 MiB device copy
+# (fetch x 2.0, write x 1.0).  The kernel touches HBM only at launch
 # boundaries (states, counters, plan tables), so a launch of any length moves
 # the same bytes.  Valid only for the kernel source it was measured on, or a
 # later source whose device assembly for gfx950 is the same instruction for
 # instruction (only the per-build compilation-unit symbol differs).
 SAME_CODE_SOURCES = (
-    "79193dfed508c472ff4c1b2678b471834b729c31c2ab3c6db004ce17ca08851f",   # counters taken here
-    "06f8ea1188932d8afbfdaa38455ff71da688835ec6112bcff33f4a6f35d6a41f",   # unused locals removed
+    "aa6f152497d6e50cc4a92aeb4152bf30781304463cff7e9197211ea1ab888043",   # counters taken here
 )
 MEASURED_TRAFFIC = {
     # per launch of the product plan: FETCH_SIZE and WRITE_SIZE (KiB per
@@ -55,7 +54,7 @@ MEASURED_TRAFFIC = {
            "fetch_kib": 234.125, "fetch_factor": 2.0, "write_kib": 176.0, "write_factor": 1.0},
     "C3": {"kernel_source_sha256": SAME_CODE_SOURCES,
            "plan": {"group": 1, "max_group_nodes": 4, "max_parent_bits": 5, "reduce": 1},
-           "fetch_kib": 12135.69, "fetch_factor": 2.0, "write_kib": 22016.0, "write_factor": 1.0},
+           "fetch_kib": 12135.375, "fetch_factor": 2.0, "write_kib": 22016.0, "write_factor": 1.0},
 }
 
 
@@ -506,10 +505,11 @@ def bench_batch(args):
             items.append((plan, 1004000 + k, ntraj, tg))
         prep = time.perf_counter() - t0
         # the launch shape, timed on the batch itself (every leg alike)
-        wpb, wpb_trials = autotune.batch_waves_per_block(items, count_from=burn)
+        queues = args.queues or api.DEFAULT_QUEUES
+        wpb, wpb_trials = autotune.batch_waves_per_block(items, count_from=burn, queues=queues)
         if args.wpb:
             wpb = args.wpb
-        b = api.Batch(items, count_from=burn, waves_per_block=wpb)
+        b = api.Batch(items, count_from=burn, waves_per_block=wpb, queues=queues)
         b.init_states()
         b.set_window(0, chunk)
         g = b.graph(passes)
@@ -521,7 +521,7 @@ def bench_batch(args):
         work = sum(ntraj * total * net["n"] for net in nets)
         results[label] = {"node_updates_per_s": work / dt, "seconds": dt, "prep_seconds": prep,
                           "plan": opts, "waves_per_block": wpb, "wpb_trials": wpb_trials, "graph_passes": passes,
-                          "chunk": chunk}
+                          "chunk": chunk, "task_queues": queues}
         del g, b, items
     out = {"metric": "node-updates/sec on 1 MI355X (batched uneven networks, one graph replay)",
            "value": results["product"]["node_updates_per_s"], "unit": "node-updates/s", "n_gpus": 1,
@@ -701,6 +701,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="default run only: skip the C3 and C5 legs (grouped product at n = 2000, served queries)")
     ap.add_argument("--wpb", type=int, default=0)
+    ap.add_argument("--queues", type=int, default=0,
+                    help="C4: task queues of the batched launch (default: the library's)")
     ap.add_argument("--tpw", type=int, default=0, help="trajectories per wavefront (default: the autotuner's)")
     ap.add_argument("--quick-tune", action="store_true")
     ap.add_argument("--queries", type=int, default=2000, help="C5: number of served queries")

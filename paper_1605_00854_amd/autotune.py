@@ -85,7 +85,7 @@ def _probe(torch, plan, tg, seed, ntraj, steps, wpb, plain, tpw=1):
     return e0.elapsed_time(e1) * 1e-3
 
 
-def batch_waves_per_block(items, count_from=0, wpbs=(2, 4, 8), probe_steps=200):
+def batch_waves_per_block(items, count_from=0, wpbs=(2, 4, 8), probe_steps=200, queues=None):
     """Waves per workgroup of a batched persistent launch (api.Batch items),
     timed on the batch itself: how many networks share a CU, and its vector
     L1, depends on the workgroup size, which single-network probes cannot
@@ -93,7 +93,7 @@ def batch_waves_per_block(items, count_from=0, wpbs=(2, 4, 8), probe_steps=200):
     import torch
     trials = []
     for wpb in wpbs:
-        b = api.Batch(items, count_from=count_from, waves_per_block=wpb)
+        b = api.Batch(items, count_from=count_from, waves_per_block=wpb, queues=queues or api.DEFAULT_QUEUES)
         b.init_states()
         b.set_window(0, probe_steps)
         b.launch()                                  # warm-up: caches, first touch
