@@ -483,7 +483,12 @@ double pbn_normal_quantile(double p);
  * pbn_batch_launch: enqueue one pass on `stream`.  queue_first: host, the
  *   nqueues + 1 bounds from pbn_batch_tasks (non-decreasing, from 0 to
  *   ntasks), copied into the launch; NULL: one queue of all tasks (nqueues
- *   ignored).
+ *   ignored).  waves_per_block: trajectories per task, as given to
+ *   pbn_batch_tasks (one wave each).  waves_per_traj (1..16): with W > 1,
+ *   W waves of one workgroup advance each trajectory together, sharing its
+ *   state and draws in LDS and splitting each step's lane passes, for a
+ *   shorter step latency on networks of many passes; tasks must then hold one
+ *   trajectory (waves_per_block = 1).  Results do not depend on W.
  * pbn_batch_graph_create: capture `passes` consecutive launches into a graph,
  *   replayed by pbn_graph_launch (each replay advances by passes * nsteps).
  * Errors: PBN_EINVAL, PBN_ELDS (one workgroup's states exceed LDS), PBN_EHIP. */
@@ -516,11 +521,12 @@ pbn_status pbn_batch_tasks(const pbn_plan* const* plans, const uint32_t* ntraj, 
 pbn_status pbn_batch_launch(const pbn_plan* const* plans, uint32_t nitems, const pbn_work* d_items,
                             const uint32_t* d_tasks, const uint32_t* d_task_first, uint32_t ntasks,
                             const uint32_t* queue_first, uint32_t nqueues, pbn_batch_ctl* d_ctl,
-                            uint32_t waves_per_block, void* stream);
+                            uint32_t waves_per_block, uint32_t waves_per_traj, void* stream);
 pbn_status pbn_batch_graph_create(const pbn_plan* const* plans, uint32_t nitems, const pbn_work* d_items,
                                   const uint32_t* d_tasks, const uint32_t* d_task_first, uint32_t ntasks,
                                   const uint32_t* queue_first, uint32_t nqueues, pbn_batch_ctl* d_ctl,
-                                  uint32_t waves_per_block, uint32_t passes, pbn_graph** out);
+                                  uint32_t waves_per_block, uint32_t waves_per_traj, uint32_t passes,
+                                  pbn_graph** out);
 pbn_status pbn_graph_launch(pbn_graph* graph, void* stream);
 
 /* Allocation-free batch launch, for callers that cannot allocate device

@@ -107,12 +107,12 @@ SIGNATURES = {
                                        C.POINTER(pbn_targets), _P, _P, C.POINTER(pbn_launch_opts), _P]),
     "pbn_state_to_original": (C.c_int32, [_P, _P, _P, _U32, _P, _P]),
     "pbn_batch_tasks": (C.c_int32, [C.POINTER(_P), _pU32, _U32, _U32, _U32, _pU32, _pU32, _pU32, _pU32]),
-    "pbn_batch_launch": (C.c_int32, [C.POINTER(_P), _U32, _P, _P, _P, _U32, _pU32, _U32, _P, _U32, _P]),
+    "pbn_batch_launch": (C.c_int32, [C.POINTER(_P), _U32, _P, _P, _P, _U32, _pU32, _U32, _P, _U32, _U32, _P]),
     "pbn_batch_launch_noalloc": (C.c_int32, [C.POINTER(_P), _pU32, _U32, _P, _U32, _U32, _U32, _P]),
     "pbn_probe_lds_gather": (C.c_int32, [_U32, _U32, _U32, _U32, _U32, _P, _P]),
     "pbn_probe_vmem_gather": (C.c_int32, [_P, _U32, _U32, _U32, _U32, _U32, _P, _P]),
     "pbn_batch_graph_create": (C.c_int32, [C.POINTER(_P), _U32, _P, _P, _P, _U32, _pU32, _U32, _P, _U32, _U32,
-                                           C.POINTER(_P)]),
+                                           _U32, C.POINTER(_P)]),
     "pbn_graph_launch": (C.c_int32, [_P, _P]),
     "pbn_graph_destroy": (C.c_int32, [_P]),
     "pbn_estimate": (C.c_int32, [_pU64, _U32, _U64, C.c_double, C.c_double, C.POINTER(pbn_estimate_out)]),

@@ -372,13 +372,16 @@ class Batch:
     items: list of (plan, seed, ntraj, target_sets); every trajectory of every
     network shares the device step window held in the control block.
     queues: task queues of the launch (1 .. BATCH_QUEUES); 1 puts every task
-    in one queue.
+    in one queue.  waves_per_traj: W > 1 advances each trajectory with W
+    waves of one workgroup (one trajectory per task: waves_per_block is then
+    1); the results do not depend on it.
     """
 
-    def __init__(self, items, count_from=0, waves_per_block=4, queues=DEFAULT_QUEUES):
+    def __init__(self, items, count_from=0, waves_per_block=4, queues=DEFAULT_QUEUES, waves_per_traj=1):
         import torch
         self.plans = [it[0] for it in items]
-        self.wpb = int(waves_per_block)
+        self.wpt = int(waves_per_traj)
+        self.wpb = 1 if self.wpt > 1 else int(waves_per_block)
         self.targets, self.states, self.counts, self._tg_dev = [], [], [], []
         works = (_lib.pbn_work * len(items))()
         for k, (plan, seed, ntraj, target_sets) in enumerate(items):
@@ -422,7 +425,7 @@ class Batch:
     def _args(self):
         return (self._plan_arr, len(self.plans), _dptr(self.items_dev), _dptr(self.tasks_dev),
                 _dptr(self.first_dev), self.ntasks, _ptr(self.queue_first, C.c_uint32), self.nqueues,
-                _dptr(self.ctl), self.wpb)
+                _dptr(self.ctl), self.wpb, self.wpt)
 
     def launch(self, stream=None):
         check(lib().pbn_batch_launch(*self._args(), _stream(stream)))

@@ -563,13 +563,15 @@ __device__ __forceinline__ void store_slot(uint8_t* ns, uint32_t info, uint32_t 
 
 // The keyed draws of one step of a plan with more than 64 Philox jobs per
 // step, 64 at a time (job j: the first chain word for j = 0, else SEL block
-// blk[j - 1]).  Job 0 is in the first round, and a step whose first chain
-// word makes it perturbation-only (u >= Q[n]) reads no selection draw, so
-// the later rounds are left out for it.
+// blk[j - 1]); this wave takes the rounds from job j0 on, every jstep jobs
+// (several waves of one trajectory split the rounds).  Job 0 is in the first
+// round, and a step whose first chain word makes it perturbation-only
+// (u >= Q[n]) reads no selection draw, so the wave that computes it leaves
+// its later rounds out.
 __device__ __forceinline__ void fill_step_keyed(uint4* ring, const uint32_t* blk, uint32_t njobs, uint32_t traj,
                                                 uint32_t t, uint32_t lane, uint32_t k0, uint32_t k1, uint32_t qn_lo,
-                                                uint32_t qn_hi) {
-  for (uint32_t j = lane; j < njobs; j += 64u) {
+                                                uint32_t qn_hi, uint32_t j0 = 0u, uint32_t jstep = 64u) {
+  for (uint32_t j = j0 + lane; j < njobs; j += jstep) {
     const uint4 x = philox(traj, t, j ? blk[j - 1u] : 0u, j ? PBN_STREAM_SEL : PBN_STREAM_PERT, k0, k1);
     ring[j] = x;
     if (j < 64u) {   // the first round: every lane takes part (njobs > 64), lane 0 holds job 0
@@ -646,6 +648,7 @@ struct TrajArgs {
   uint32_t* record;                 // this trajectory's indicator bits (target 0), or null
   uint32_t record_words;
   uint32_t gshift;                  // 1 (see shl_or)
+  uint32_t wv, nw;                  // MODE bit 8: this wave's index among the trajectory's nw waves
 };
 
 // PM: parent bytes gathered per FN slot (>= the plan's largest predictor);
@@ -665,7 +668,14 @@ struct TrajArgs {
 // (one dependent global read less per pass for four more VGPRs); bit 7, with
 // NREG = 1 or 2 and FN-only keyed plans, the last register-held pass holds no
 // multi-predictor slot (no drawn word read, no threshold compare, and its
-// records stay in registers).
+// records stay in registers); bit 8, with NREG = 0 and keyed draws, a.nw waves
+// of one workgroup advance the trajectory together (this one is wave a.wv):
+// they share its state buffers and ring, split each fill's Philox calls and
+// each step's lane passes (wave w takes passes w, w + nw, ...), and meet at one
+// workgroup barrier per step; wave 0 alone walks the perturbation chain (in
+// place, between two barriers) and counts the targets.  Every wave takes the
+// same branch of every step (the step's drawn word is read from the shared
+// ring), so all reach the same barriers.
 template <int PM, int UM, int NREG, int MODE>
 __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   constexpr int XW = Shape<PM, UM>::XW, TTW = Shape<PM, UM>::TTW;
@@ -683,6 +693,17 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   constexpr bool kPre = kBallotTargets;
   constexpr bool kRegState = (MODE & 8) != 0;
   static_assert(!kRegState || (NREG == 1 && UM == 0 && !ALIAS), "register state: one-pass FN-only keyed plans");
+  constexpr bool kMW = (MODE & 256) != 0;
+  static_assert(!kMW || (NREG == 0 && !ALIAS), "several waves per trajectory: streaming keyed plans");
+  const uint32_t wv = kMW ? a.wv : 0u, nw = kMW ? a.nw : 1u;
+  const bool lead = !kMW || wv == 0u;   // counts targets and walks the chain
+  // orders the trajectory's LDS traffic: its own lanes, or all its waves
+  auto traj_sync = [&]() {
+    if constexpr (kMW)
+      __syncthreads();
+    else
+      wave_sync();
+  };
   using Regs = SlotRegs<XW, TTW>;
   const pbn_plan_header* H = reinterpret_cast<const pbn_plan_header*>(a.blob);
   const uint32_t lane = threadIdx.x & 63u;
@@ -713,7 +734,7 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   uint32_t* gst = a.state + size_t(a.tl) * W;
   unsigned long long rst = 0ull;   // register-held state (kRegState)
   if constexpr (kRegState) rst = uniform64((W > 1u ? (static_cast<unsigned long long>(gst[1]) << 32) : 0ull) | gst[0]);
-  for (uint32_t w = lane; w < (kRegState ? 0u : W); w += 64u) {
+  for (uint32_t w = lane + 64u * wv; w < (kRegState ? 0u : W); w += 64u * nw) {
     const uint32_t word = gst[w];
 #pragma unroll
     for (uint32_t i = 0; i < 8u; ++i) {
@@ -783,7 +804,7 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
       if (!placed && val) never = true;
     }
   }
-  wave_sync();
+  traj_sync();
 
   // fixed Philox job of this lane when one fill covers several steps
   // plans whose slot data stay in registers have at most 64 jobs per step
@@ -821,10 +842,10 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   auto target_reg = [&](unsigned long long b) -> bool {
     return !never && (masked_xor(uint32_t(b), care_lo[0], want_lo[0]) | masked_xor(uint32_t(b >> 32), care_hi[0], want_hi[0])) == 0u;
   };
-  uint32_t zlast;
+  uint32_t zlast = 0u;
   if constexpr (kRegState)
     zlast = target_reg(rst) ? 1u : 0u;
-  else
+  else if (lead)
     zlast = target_z(reinterpret_cast<const uint8_t*>(sbuf0)) ? 1u : 0u;
   uint32_t zacc = 0, nacc = 0;
   uint32_t hits = 0, n01 = 0, n10 = 0;
@@ -856,7 +877,7 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   };
   auto fold = [&]() {
     if (nacc == 0u) return;
-    if (a.record != nullptr && lane == 0u) record_bits();
+    if (a.record != nullptr && lead && lane == 0u) record_bits();
     const long long newest = (long long)tacc + nacc - 1;   // step of bit 0
     const uint32_t keep = low_bits(nacc);
     const uint32_t hm = low_bits(newest - (long long)a.count_from + 1) & keep;
@@ -878,14 +899,14 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
     if (small_jobs) {
 #pragma unroll
       for (int r = 0; r < kFillRounds; ++r)
-        if (lane + 64u * uint32_t(r) < scount * njobs)
+        if (lane + 64u * uint32_t(r) < scount * njobs && (!kMW || uint32_t(r) % nw == wv))
           ring[lane + 64u * uint32_t(r)] = philox(traj, t + my_s[r], my_c2[r], my_c3[r], k0, k1);
     } else if constexpr (ALIAS) {
       for (uint32_t j = lane; j < njobs; j += 64u) ring[j] = philox(traj, t, j, PBN_STREAM_ALIAS, k0, k1);
     } else {
-      fill_step_keyed(ring, blk, njobs, traj, t, lane, k0, k1, qn_lo, qn_hi);
+      fill_step_keyed(ring, blk, njobs, traj, t, lane, k0, k1, qn_lo, qn_hi, 64u * wv, 64u * nw);
     }
-    wave_sync();
+    traj_sync();
     if constexpr (ALIAS) {
       // Resolve the fill's perturbation draws ahead of the steps (they do not
       // depend on the state): word 1 of a step becomes its perturbed flag
@@ -958,12 +979,13 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
           ulo = uniform(pr.x);
           uhi = uniform(pr.y);
         }
-        walk_chain<(MODE & 2) != 0, kRegState>((static_cast<unsigned long long>(uhi) << 32) | ulo, n, stride0, Q, o2p,
-                                               traj, t, k0, k1, lane, csb, rst);
-        wave_sync();
+        if (lead)
+          walk_chain<(MODE & 2) != 0, kRegState>((static_cast<unsigned long long>(uhi) << 32) | ulo, n, stride0, Q,
+                                                 o2p, traj, t, k0, k1, lane, csb, rst);
+        traj_sync();
         if constexpr (kRegState)
           z = target_reg(rst);
-        else
+        else if (lead)
           z = target_z(csb);
       } else {
         uint8_t* nsb = reinterpret_cast<uint8_t*>(cur ? sbuf0 : sbuf1);
@@ -999,8 +1021,8 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
           }
         } else {
           constexpr bool G = (MODE & 2) != 0;
-          uint4 nrec = kPrefetch ? img_u4<G>(img + 16u * lane) : uint4{};
-          for (uint32_t p = 0; p < npass; ++p) {
+          uint4 nrec = kPrefetch && (!kMW || wv < npass) ? img_u4<G>(img + 16u * (wv * 64u + lane)) : uint4{};
+          for (uint32_t p = wv; p < npass; p += nw) {
             if constexpr (ALIAS) {
               Regs r;
               load_slot<PM, UM, MODE>(r, img, p * 64u + lane, fm);
@@ -1009,7 +1031,7 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
               uint4 rec;
               if constexpr (kPrefetch) {
                 rec = nrec;
-                if (p + 1u < npass) nrec = img_u4<G>(img + 16u * ((p + 1u) * 64u + lane));
+                if (p + nw < npass) nrec = img_u4<G>(img + 16u * ((p + nw) * 64u + lane));
               } else {
                 rec = img_u4<G>(img + 16u * (p * 64u + lane));
               }
@@ -1021,17 +1043,18 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
           }
         }
         cur ^= 1u;
-        if constexpr (!kRegState) wave_sync();
-        if constexpr (!kBallotTargets) z = target_z(nsb);
+        if constexpr (!kRegState) traj_sync();
+        if constexpr (!kBallotTargets)
+          if (lead) z = target_z(nsb);
       }
       zacc = zacc + zacc + (z ? 1u : 0u);
       ++nacc;
     }
-    wave_sync();
+    traj_sync();
   }
   fold();
 
-  if (lane < ntg) {
+  if (lead && lane < ntg) {
     unsigned long long* c = a.counts + (size_t(lane) * a.ntraj + a.tl) * 3u;
     c[0] += hits;
     c[1] += n01;
@@ -1042,7 +1065,7 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
     return;
   }
   const uint32_t* fs = cur ? sbuf1 : sbuf0;
-  for (uint32_t w = lane; w < W; w += 64u) {
+  for (uint32_t w = lane + 64u * wv; w < W; w += 64u * nw) {
     uint32_t word = 0;
 #pragma unroll
     for (uint32_t i = 0; i < 8u; ++i) {
@@ -1627,7 +1650,8 @@ struct BatchParams {
   const uint32_t* tasks;           // item of task k
   const uint32_t* task_first;      // first trajectory (local index) of task k
   uint32_t ntasks;                 // PBN_NONE: one queue of ctl->ntasks tasks, written on the device
-  uint32_t wpb;
+  uint32_t wpb;                    // trajectories per task
+  uint32_t wpt;                    // waves per trajectory (> 1: one trajectory per workgroup)
   uint32_t wave_bytes;
   uint32_t gshift;                 // 1: the gather step's shift, passed at run time (see shl_or)
   pbn_batch_ctl* ctl;              // device: queue counters and the step window
@@ -1638,8 +1662,10 @@ struct BatchParams {
 // PF: each pass's slot records are read while the previous pass evaluates
 // (run_traj MODE bit 5): launches too small to fill the chip at four waves
 // per SIMD, where its four VGPRs cost no occupancy and the step latency of
-// one trajectory is what counts (served queries).
-template <int PM, int UM, bool PF>
+// one trajectory is what counts (served queries).  MW: the workgroup's wpt
+// waves advance one trajectory together (run_traj MODE bit 8), for a shorter
+// step latency of the trajectories of large networks.
+template <int PM, int UM, bool PF, bool MW>
 __global__ void __launch_bounds__(1024) k_batch(BatchParams a, const pbn_work* __restrict__ items) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   // first 16 bytes: the claimed task, and how many queues thread 0 has found
@@ -1675,7 +1701,8 @@ __global__ void __launch_bounds__(1024) k_batch(BatchParams a, const pbn_work* _
     if (task == PBN_NONE) return;        // uniform across the workgroup
     // the task's work item, read into wave-uniform values (scalar registers)
     const pbn_work& it = items[uniform(a.tasks[task])];
-    const uint32_t tl = uniform(a.task_first[task]) + wave;
+    const uint32_t slot = MW ? 0u : wave;   // the wave's trajectory within the task
+    const uint32_t tl = uniform(a.task_first[task]) + slot;
     const uint32_t ntraj = uniform(it.ntraj);
     if (tl < ntraj) {
       const uint8_t* blob = static_cast<const uint8_t*>(it.d_plan);
@@ -1683,7 +1710,7 @@ __global__ void __launch_bounds__(1024) k_batch(BatchParams a, const pbn_work* _
       TrajArgs t;
       t.blob = blob;
       t.img = blob + H->image_off;
-      t.wb = smem + 16u + wave * a.wave_bytes;
+      t.wb = smem + 16u + slot * a.wave_bytes;
       t.seed = uniform64(it.seed);
       t.traj = uniform(it.traj0) + tl;
       t.tl = tl;
@@ -1697,9 +1724,11 @@ __global__ void __launch_bounds__(1024) k_batch(BatchParams a, const pbn_work* _
       t.record = nullptr;
       t.record_words = 0;
       t.gshift = a.gshift;
+      t.wv = MW ? wave : 0u;
+      t.nw = MW ? a.wpt : 1u;
       // large launches run without the prefetch: its four VGPRs would take
       // this kernel from five to four waves per SIMD
-      run_traj<PM, UM, 0, (PM == 7 ? 1 : 0) | 2 | (PF ? 32 : 0)>(t);
+      run_traj<PM, UM, 0, (PM == 7 ? 1 : 0) | 2 | (PF ? 32 : 0) | (MW ? 256 : 0)>(t);
     }
   }
 }
@@ -2235,21 +2264,23 @@ pbn_status launch_batch_t(const BatchParams& p, uint32_t lds, hipStream_t s, con
   if (e != hipSuccess) return hip_check(e, "batch device query");
   // the slot-record prefetch when every wave of the launch fits the chip at
   // four waves per SIMD (four SIMDs per CU)
-  const uint64_t waves = uint64_t(sched ? sched->ntasks : p.ntasks) * p.wpb;
-  auto* fn = waves <= uint64_t(ncu) * 16u ? k_batch<PM, UM, true> : k_batch<PM, UM, false>;
+  const uint64_t waves = uint64_t(sched ? sched->ntasks : p.ntasks) * p.wpb * p.wpt;
+  auto* fn = p.wpt > 1u                     ? k_batch<PM, UM, true, true>
+             : waves <= uint64_t(ncu) * 16u ? k_batch<PM, UM, true, false>
+                                            : k_batch<PM, UM, false, false>;
   if (e == hipSuccess)
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize, int(kLdsMax));
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, int(64u * p.wpb), lds);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, int(64u * p.wpb * p.wpt), lds);
   if (e != hipSuccess) return hip_check(e, "batch occupancy query");
   const uint32_t resident = uint32_t(std::max(1, per_cu) * std::max(1, ncu));
   const uint32_t blocks = std::max(1u, std::min(sched ? sched->ntasks : p.ntasks, resident));
   if (sched) {
     hipLaunchKernelGGL(k_noalloc_schedule, dim3(1), dim3(1024), 0, s, p.items, sched->nitems, p.wpb, sched->step0,
                        sched->nsteps, reinterpret_cast<uint32_t*>(p.ctl));
-    hipLaunchKernelGGL(fn, dim3(blocks), dim3(64u * p.wpb), lds, s, p, p.items);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(64u * p.wpb * p.wpt), lds, s, p, p.items);
   } else {
     hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(PBN_BATCH_QUEUES), 0, s, p.ctl, p.q, p.nq);
-    hipLaunchKernelGGL(fn, dim3(blocks), dim3(64u * p.wpb), lds, s, p, p.items);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(64u * p.wpb * p.wpt), lds, s, p, p.items);
     hipLaunchKernelGGL(k_batch_end, dim3(1), dim3(1), 0, s, p.ctl);
   }
   return hip_check(hipGetLastError(), "k_batch launch");
@@ -2258,9 +2289,11 @@ pbn_status launch_batch_t(const BatchParams& p, uint32_t lds, hipStream_t s, con
 pbn_status batch_enqueue(const pbn_plan* const* plans, uint32_t nitems, const pbn_work* d_items,
                          const uint32_t* d_tasks, const uint32_t* d_task_first, uint32_t ntasks,
                          const uint32_t* queue_first, uint32_t nq, pbn_batch_ctl* d_ctl, uint32_t wpb,
-                         hipStream_t s, const NoAllocSched* sched = nullptr) {
+                         uint32_t wpt, hipStream_t s, const NoAllocSched* sched = nullptr) {
   if (!plans || !d_items || !d_tasks || !d_task_first || !d_ctl) return fail(PBN_EINVAL, "null argument");
   if (wpb < 1 || wpb > 16) return fail(PBN_EINVAL, "waves_per_block must be 1..16");
+  if (wpt < 1 || wpt > 16 || (wpt > 1 && wpb != 1))
+    return fail(PBN_EINVAL, "waves_per_traj must be 1..16, with one trajectory per task when above 1");
   if (nitems == 0 || ntasks == 0) return PBN_OK;
   QueueBounds q{};
   if (sched || !queue_first) {
@@ -2287,6 +2320,7 @@ pbn_status batch_enqueue(const pbn_plan* const* plans, uint32_t nitems, const pb
   p.task_first = d_task_first;
   p.ntasks = ntasks;
   p.wpb = wpb;
+  p.wpt = wpt;
   p.wave_bytes = sh.wave_bytes;
   p.gshift = 1;
   p.ctl = d_ctl;
@@ -2353,10 +2387,10 @@ extern "C" pbn_status pbn_batch_tasks(const pbn_plan* const* plans, const uint32
 extern "C" pbn_status pbn_batch_launch(const pbn_plan* const* plans, uint32_t nitems, const pbn_work* d_items,
                                        const uint32_t* d_tasks, const uint32_t* d_task_first, uint32_t ntasks,
                                        const uint32_t* queue_first, uint32_t nqueues, pbn_batch_ctl* d_ctl,
-                                       uint32_t waves_per_block, void* stream) {
+                                       uint32_t waves_per_block, uint32_t waves_per_traj, void* stream) {
   pbn::clear_error();
   return batch_enqueue(plans, nitems, d_items, d_tasks, d_task_first, ntasks, queue_first, nqueues, d_ctl,
-                       waves_per_block, static_cast<hipStream_t>(stream));
+                       waves_per_block, waves_per_traj, static_cast<hipStream_t>(stream));
 }
 
 namespace {
@@ -2406,14 +2440,15 @@ extern "C" pbn_status pbn_batch_launch_noalloc(const pbn_plan* const* plans, con
   if (st != PBN_OK) return st;
   const NoAllocSched sched{nitems, step0, nsteps, uint32_t(total)};
   return batch_enqueue(plans, nitems, d_items, scr + kScratchCtlWords, scr + kScratchCtlWords + kNoAllocMaxTasks,
-                       PBN_NONE, nullptr, 1, reinterpret_cast<pbn_batch_ctl*>(scr), waves_per_block,
+                       PBN_NONE, nullptr, 1, reinterpret_cast<pbn_batch_ctl*>(scr), waves_per_block, 1,
                        static_cast<hipStream_t>(stream), &sched);
 }
 
 extern "C" pbn_status pbn_batch_graph_create(const pbn_plan* const* plans, uint32_t nitems, const pbn_work* d_items,
                                              const uint32_t* d_tasks, const uint32_t* d_task_first, uint32_t ntasks,
                                              const uint32_t* queue_first, uint32_t nqueues, pbn_batch_ctl* d_ctl,
-                                             uint32_t waves_per_block, uint32_t passes, pbn_graph** out) {
+                                             uint32_t waves_per_block, uint32_t waves_per_traj, uint32_t passes,
+                                             pbn_graph** out) {
   pbn::clear_error();
   if (!out || passes == 0) return fail(PBN_EINVAL, "bad argument");
   *out = nullptr;
@@ -2424,7 +2459,7 @@ extern "C" pbn_status pbn_batch_graph_create(const pbn_plan* const* plans, uint3
   if (st == PBN_OK) {
     for (uint32_t k = 0; k < passes && st == PBN_OK; ++k)
       st = batch_enqueue(plans, nitems, d_items, d_tasks, d_task_first, ntasks, queue_first, nqueues, d_ctl,
-                         waves_per_block, s);
+                         waves_per_block, waves_per_traj, s);
     hipGraph_t g = nullptr;
     const pbn_status end = hip_check(hipStreamEndCapture(s, &g), "hipStreamEndCapture");
     if (st == PBN_OK) st = end;

@@ -17,7 +17,10 @@ query on a small network never waits for the step latency of a large one.  A
 query's chunk is fixed by its own plan: the base chunk times the power of two
 (up to 2^(chunk_classes - 1)) that brings its estimated step cost closest to,
 without exceeding, that of the costliest resident network, so lanes take
-about equally long per launch.  Queries that arrive while others are on the
+about equally long per launch.  In the lanes of the costlier networks several
+waves advance each trajectory together (four in the two costliest chunk
+classes, two in the next), which shortens the step latency that a query's
+latency is made of; the results do not depend on it.  Queries that arrive while others are on the
 device join their lane at its next launch as soon as their footprint
 (resident waves, LDS bytes, HBM bytes) fits, and leave when their precision
 is met.  A lane's work items, task list and control block stay on the device
@@ -134,15 +137,20 @@ class _Lane:
         self.active = []
         self.ntasks = 0
         self.queue_first = None    # the launch's task-queue bounds (host)
+        self.wpt = 1               # waves per trajectory of the lane's launches
         self.plans_arr = None
         self.inflight = None       # (queries, steps after the launch, pinned counts, event)
         self.launches = 0
+
+    def wpb(self, wpb):
+        """Trajectories per task: one when several waves share a trajectory."""
+        return 1 if self.wpt > 1 else wpb
 
 
 class Server:
     def __init__(self, nets, net_seeds, *, plan_opts=None, traj_per_query=256, chunk=1000, burn_in=1000,
                  min_counted=1000, max_steps=400000, waves_per_block=4, footprint=None, chunk_classes=3,
-                 task_queues=api.DEFAULT_QUEUES):
+                 task_queues=api.DEFAULT_QUEUES, waves_per_traj=(4, 4, 2)):
         import torch
         self.torch = torch
         self.nets = nets
@@ -156,6 +164,13 @@ class Server:
         self.max_steps = int(max_steps)
         self.wpb = int(waves_per_block)
         self.task_queues = int(task_queues)   # per launch: networks dealt to the CU groups' task queues
+        # waves per trajectory of the lane of chunk base x 2^j: entry j (the
+        # last one for larger j); the costliest networks run in the base lane.
+        # (4, 4, 2) served the 2000-query Poisson stream fastest of those
+        # measured: one wave per trajectory gave p50 12.6 / p99 34.4 ms, this
+        # 8.2 / 23.4 ms, (8, 4, 2) 9.4 / 30.9 ms
+        self.wpt = tuple(int(w) for w in (waves_per_traj if isinstance(waves_per_traj, (tuple, list))
+                                          else (waves_per_traj,)))
         self.fp = footprint or Footprint()
         self.plans = {}
         self.base_interest = [non_sink_nodes(net) for net in nets]
@@ -200,12 +215,19 @@ class Server:
             m *= 2
         return self.chunk * m
 
-    def footprint(self, plan):
+    def footprint(self, plan, wpt=1):
+        """(waves, LDS bytes, HBM bytes) of one query: wpt waves per trajectory
+        share its LDS state and ring."""
         ring = plan.info["n_jobs"]
         fill = min(32, plan.fill_steps) if ring <= 64 else 1
-        wave_lds = 2 * plan.info["state_bytes"] + 16 * (fill * ring if ring <= 64 else ring)
+        traj_lds = 2 * plan.info["state_bytes"] + 16 * (fill * ring if ring <= 64 else ring)
         hbm = self.ntraj * (4 * plan.info["state_words"] + 24)
-        return np.array([self.ntraj, self.ntraj * wave_lds, hbm], dtype=np.float64)
+        return np.array([self.ntraj * wpt, self.ntraj * traj_lds, hbm], dtype=np.float64)
+
+    def wpt_of(self, chunk):
+        """Waves per trajectory of the lane of this chunk length."""
+        j = max(0, (chunk // self.chunk).bit_length() - 1)
+        return self.wpt[min(j, len(self.wpt) - 1)]
 
     # -- queue management
     def submit(self, q, now):
@@ -215,18 +237,21 @@ class Server:
             q.status, q.error, q.finished = "rejected", str(e), now
             self.done.append(q)
             return
-        need = self.footprint(plan)
+        chunk = self.chunk_of(q.net, plan)
+        need = self.footprint(plan, self.wpt_of(chunk))
         if self.fp.exceeds_device(need):
             q.status, q.error, q.finished = "rejected", "footprint exceeds the device budget", now
             self.done.append(q)
             return
         q._plan, q._tg, q._need = plan, tg, need
-        q._chunk = self.chunk_of(q.net, plan)
+        q._chunk = chunk
         self.queue.append(q)
 
     def _lane(self, chunk):
         if chunk not in self.lanes:
-            self.lanes[chunk] = _Lane(self.torch, chunk)
+            lane = _Lane(self.torch, chunk)
+            lane.wpt = self.wpt_of(chunk)
+            self.lanes[chunk] = lane
         return self.lanes[chunk]
 
     def _admit(self, now):
@@ -256,7 +281,8 @@ class Server:
                                      q._counts.data_ptr(), q._seed, 0, self.ntraj, self.burn_in, off)
         lane.plans_arr = (api.C.c_void_p * len(act))(*[q._plan.handle.value for q in act])
         ntraj = np.full(len(act), self.ntraj, dtype=np.uint32)
-        tasks, first, lane.queue_first = api.batch_schedule(lane.plans_arr, ntraj, self.wpb, self.task_queues)
+        tasks, first, lane.queue_first = api.batch_schedule(lane.plans_arr, ntraj, lane.wpb(self.wpb),
+                                                            self.task_queues)
         lane.res.upload(works, tasks, first)
         lane.ntasks = int(tasks.size)
         lane.dirty = False
@@ -274,7 +300,8 @@ class Server:
             _lib.check(L.pbn_batch_launch(lane.plans_arr, len(act), api._dptr(lane.res.items),
                                           api._dptr(lane.res.tasks), api._dptr(lane.res.first), lane.ntasks,
                                           api._ptr(lane.queue_first, api.C.c_uint32), self.task_queues,
-                                          api._dptr(lane.ctl), self.wpb, api._stream(lane.stream)))
+                                          api._dptr(lane.ctl), lane.wpb(self.wpb), lane.wpt,
+                                          api._stream(lane.stream)))
             lane.window = (lane.window + lane.chunk) & 0xFFFFFFFF
             for q in act:
                 q.steps += lane.chunk

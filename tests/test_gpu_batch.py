@@ -298,3 +298,47 @@ def test_task_queues_leave_results_unchanged():
     c = runs[-1][1][2]
     assert np.array_equal(c[:, :, 0], ref["hits"]) and np.array_equal(c[:, :, 1], ref["n01"])
     assert np.array_equal(c[:, :, 2], ref["n10"])
+
+
+def test_waves_per_trajectory_leave_results_unchanged():
+    """Two, three or four waves advancing each trajectory together (shared
+    state and draws in LDS, the lane passes split between them, one barrier
+    per step) give the states and counters of one wave per trajectory: plans
+    of one to 24 passes, with and without table slots, one with more than 64
+    Philox jobs per step (single-step fills split between the waves), and a
+    perturbation-heavy one (most steps walk the chain); two windows, and an
+    oracle check of the largest network."""
+    items, nets = make_items(6, 29, 20, 400, [7, 3], True)
+    big = ps.medium_c2(n=1500, p=1e-3, seed=2931)
+    hot = ps.medium_c2(n=300, p=1e-2, seed=2932)
+    for k, net in enumerate((big, hot)):
+        tgs = [ps.non_leaf_targets(net, 2)]
+        plan = api.Plan(net, interest=[a for a, _ in tgs[0]], reduce=1, group=k)
+        items.append((plan, 4000 + k, 5, tgs))
+        nets.append(net)
+    assert max(it[0].info["n_jobs"] for it in items) > 64
+    assert max(it[0].info["n_passes"] for it in items) >= 20
+    say("[gpu] batch waves per trajectory 1 / 2 / 3 / 4")
+    runs = []
+    for wpt in (1, 2, 3, 4):
+        b = api.Batch(items, count_from=15, waves_per_block=4, waves_per_traj=wpt)
+        b.init_states()
+        b.set_window(0, 70)
+        b.launch()
+        b.set_window(70, 50)
+        b.launch()
+        torch.cuda.synchronize()
+        runs.append(([s.cpu().numpy() for s in b.states], [c.cpu().numpy() for c in b.counts], b))
+    for wpt, r in zip((2, 3, 4), runs[1:]):
+        for k in range(len(items)):
+            assert np.array_equal(runs[0][0][k], r[0][k]), (wpt, k)
+            assert np.array_equal(runs[0][1][k], r[1][k]), (wpt, k)
+    k = len(items) - 2
+    plan, seed, ntraj, tgs = items[k]
+    ref = osim.run(nets[k], seed, np.arange(ntraj), 120, targets=tgs, count_from=15)
+    orig = api.unpack_bits(api.to_original(plan, runs[-1][2].states[k]).cpu().numpy(), plan.n)
+    kept = plan.node_pos() != NONE
+    assert np.array_equal(orig[:, kept], ref["state"][:, kept])
+    c = runs[-1][1][k]
+    assert np.array_equal(c[:, :, 0], ref["hits"]) and np.array_equal(c[:, :, 1], ref["n01"])
+    assert np.array_equal(c[:, :, 2], ref["n10"])

@@ -87,6 +87,27 @@ def test_chunk_lanes_results_identical_alone_and_in_mix():
         assert a.result["p_hat"] == b.result["p_hat"], q.qid
 
 
+def test_multi_wave_lanes_give_the_results_of_single_wave_lanes():
+    """Lanes whose trajectories are advanced by several waves each (four in
+    the base lane of the costliest network, two in the next) serve every
+    query with the same steps and counters as one wave per trajectory."""
+    nets = small_nets() + [ps.medium_c2(n=1500, p=1e-4, seed=5)]
+    runs = []
+    for wpt in ((1,), (4, 2, 1)):
+        srv = make_server(nets, waves_per_traj=wpt)
+        qs = serve.poisson_queries(nets, 10, rate=1000.0, seed=13, precisions=(0.04, 0.06))
+        say(f"[gpu] serving 10 queries, waves per trajectory {wpt}")
+        m = srv.run(qs, realtime=False)
+        assert m["done"] + m["max_steps"] == 10, m
+        if wpt[0] > 1:
+            assert any(lane.wpt > 1 for lane in srv.lanes.values())
+        runs.append({q.qid: q for q in srv.done})
+    for qid, a in runs[0].items():
+        b = runs[1][qid]
+        assert a._chunk == b._chunk and a.steps == b.steps, qid
+        assert np.array_equal(a.result["counts"], b.result["counts"]), qid
+
+
 def test_resident_plans_follow_the_network_not_generator_metadata():
     """The resident plan's interest set is every node some predictor reads, so
     Definition 1 removes the sinks whether or not the network carries the

@@ -101,7 +101,16 @@ def test_launch_rejects_bad_queue_bounds_before_any_device_work(batch, bounds, m
     plans, arr, _ = batch
     qf = np.asarray(bounds, dtype=np.uint32)
     fake = C.c_void_p(256)                # never dereferenced: the bounds are checked first
-    st = lib().pbn_batch_launch(arr, 1, fake, fake, fake, 10, api._ptr(qf, C.c_uint32), qf.size - 1, fake, WPB,
+    st = lib().pbn_batch_launch(arr, 1, fake, fake, fake, 10, api._ptr(qf, C.c_uint32), qf.size - 1, fake, WPB, 1,
                                 None)
     assert st == EINVAL
     assert message in lib().pbn_last_error()
+
+
+@pytest.mark.parametrize("wpb,wpt", [(4, 2), (1, 0), (1, 17)])
+def test_launch_rejects_bad_waves_per_trajectory(batch, wpb, wpt):
+    plans, arr, _ = batch
+    fake = C.c_void_p(256)                # never dereferenced: the shape is checked first
+    st = lib().pbn_batch_launch(arr, 1, fake, fake, fake, 10, None, 1, fake, wpb, wpt, None)
+    assert st == EINVAL
+    assert b"waves_per_traj" in lib().pbn_last_error()
