@@ -40,10 +40,12 @@ PHILOX_SLOTS = 60                  # 10 rounds x (2 full-rate 32x32->64 multipli
 # (fetch x 2.0, write x 1.0).  The kernel touches HBM only at launch
 # boundaries (states, counters, plan tables), so a launch of any length moves
 # the same bytes.  Valid only for the kernel source it was measured on, or a
-# later source whose device assembly for gfx950 is the same instruction for
-# instruction (only the per-build compilation-unit symbol differs).
+# later source whose k_simulate instances compile to the same gfx950
+# instructions (their assembly compared instance by instance, labels aside)
+# with the same host plan builder.
 SAME_CODE_SOURCES = (
     "aa6f152497d6e50cc4a92aeb4152bf30781304463cff7e9197211ea1ab888043",   # counters taken here
+    "8af1d8b60e604c5e17092e9b7ffaf2e6f83dafba80b77d3fbc766f017954f561",   # several waves per trajectory in k_batch
 )
 MEASURED_TRAFFIC = {
     # per launch of the product plan: FETCH_SIZE and WRITE_SIZE (KiB per
