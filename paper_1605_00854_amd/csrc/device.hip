@@ -563,15 +563,13 @@ __device__ __forceinline__ void store_slot(uint8_t* ns, uint32_t info, uint32_t 
 
 // The keyed draws of one step of a plan with more than 64 Philox jobs per
 // step, 64 at a time (job j: the first chain word for j = 0, else SEL block
-// blk[j - 1]); this wave takes the rounds from job j0 on, every jstep jobs
-// (several waves of one trajectory split the rounds).  Job 0 is in the first
-// round, and a step whose first chain word makes it perturbation-only
-// (u >= Q[n]) reads no selection draw, so the wave that computes it leaves
-// its later rounds out.
+// blk[j - 1]).  Job 0 is in the first round, and a step whose first chain
+// word makes it perturbation-only (u >= Q[n]) reads no selection draw, so
+// the later rounds are left out for it.
 __device__ __forceinline__ void fill_step_keyed(uint4* ring, const uint32_t* blk, uint32_t njobs, uint32_t traj,
                                                 uint32_t t, uint32_t lane, uint32_t k0, uint32_t k1, uint32_t qn_lo,
-                                                uint32_t qn_hi, uint32_t j0 = 0u, uint32_t jstep = 64u) {
-  for (uint32_t j = j0 + lane; j < njobs; j += jstep) {
+                                                uint32_t qn_hi) {
+  for (uint32_t j = lane; j < njobs; j += 64u) {
     const uint4 x = philox(traj, t, j ? blk[j - 1u] : 0u, j ? PBN_STREAM_SEL : PBN_STREAM_PERT, k0, k1);
     ring[j] = x;
     if (j < 64u) {   // the first round: every lane takes part (njobs > 64), lane 0 holds job 0
@@ -588,12 +586,14 @@ __device__ __forceinline__ void fill_step_keyed(uint4* ring, const uint32_t* blk
 // perturbed one with ballots over Q (radix 64).  The chain's later draws are
 // computed 64 at a time, one per lane (indices sbase .. sbase + 63), when the
 // walk goes past them; a walk that flips again within them reads its next
-// word with one lane read.  All lanes of the wave take part.
-template <bool G, bool REG, bool LBITS = false>
+// word with one lane read.  All lanes of the wave take part.  TOPREG: the
+// top level's 64 entries of Q (entry stride0 (lane + 1), 0 past n) are held
+// by the lanes in `qtop`, which saves a dependent read per draw.
+template <bool G, bool REG, bool LBITS = false, bool TOPREG = false>
 __device__ __forceinline__ void walk_chain(unsigned long long u, uint32_t n, uint32_t stride0,
                                            const unsigned long long* Q, const uint32_t* o2p, uint32_t traj, uint32_t t,
                                            uint32_t k0, uint32_t k1, uint32_t lane, uint8_t* csb,
-                                           unsigned long long& rst) {
+                                           unsigned long long& rst, unsigned long long qtop = 0ull) {
   uint32_t j0 = 0;
   uint32_t sbase = 0u, spec_lo = 0u, spec_hi = 0u;
   bool have = false;
@@ -601,7 +601,7 @@ __device__ __forceinline__ void walk_chain(unsigned long long u, uint32_t n, uin
     uint32_t base = 0;
     for (uint32_t st = stride0;; st /= 64u) {
       const uint32_t h = base + st * (lane + 1u);
-      const bool gt = h <= n && blob_u64<G>(Q + h) > u;
+      const bool gt = TOPREG && st == stride0 ? qtop > u : h <= n && blob_u64<G>(Q + h) > u;
       base += st * uint32_t(__popcll(__ballot(gt)));
       if (st == 1u) break;
     }
@@ -632,6 +632,12 @@ __device__ __forceinline__ void walk_chain(unsigned long long u, uint32_t n, uin
   }
 }
 
+// LDS copy of a plan's chain tables (several waves per trajectory): Q[0..n]
+// (8 bytes each), then the original-to-position map o2p[0..n-1] (4 bytes
+// each), each padded to 16 bytes.
+__host__ __device__ constexpr uint32_t chain_q_bytes(uint32_t n) { return (8u * (n + 1u) + 15u) & ~15u; }
+__host__ __device__ constexpr uint32_t chain_lds_bytes(uint32_t n) { return chain_q_bytes(n) + ((4u * n + 15u) & ~15u); }
+
 // Everything one wavefront needs to advance one trajectory.
 struct TrajArgs {
   const uint8_t* blob;              // plan blob (global memory)
@@ -649,6 +655,7 @@ struct TrajArgs {
   uint32_t record_words;
   uint32_t gshift;                  // 1 (see shl_or)
   uint32_t wv, nw;                  // MODE bit 8: this wave's index among the trajectory's nw waves
+  uint8_t* qo;                      // MODE bit 8: the workgroup's LDS for the chain tables (chain_lds_bytes)
 };
 
 // PM: parent bytes gathered per FN slot (>= the plan's largest predictor);
@@ -720,9 +727,20 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   const uint32_t sdp = (sd + 3u) & ~3u;   // state buffer, padded to 16 bytes
   const uint32_t* blk = reinterpret_cast<const uint32_t*>(a.blob + H->blk_off);
   const uint8_t* img = a.img;
-  // the chain's tables are read from the image (LDS when the image is staged there)
+  // the chain's tables are read from the image (LDS when the image is staged
+  // there); several waves per trajectory (a latency-bound walk) copy them into
+  // the workgroup's LDS first (ordered by the barrier after the state unpack)
   const unsigned long long* Q = reinterpret_cast<const unsigned long long*>(img + H->q_img);
   const uint32_t* o2p = reinterpret_cast<const uint32_t*>(img + H->o2p_img);
+  constexpr bool kChainG = (MODE & 2) != 0 && !kMW;   // chain tables in global memory
+  if constexpr (kMW) {
+    auto* ql = reinterpret_cast<unsigned long long*>(a.qo);
+    auto* ol = reinterpret_cast<uint32_t*>(a.qo + chain_q_bytes(H->n));
+    for (uint32_t i = 64u * wv + lane; i <= H->n; i += 64u * nw) ql[i] = blob_u64<true>(Q + i);
+    for (uint32_t i = 64u * wv + lane; i < H->n; i += 64u * nw) ol[i] = blob_u32<true>(o2p + i);
+    Q = ql;
+    o2p = ol;
+  }
   uint32_t* sbuf0 = reinterpret_cast<uint32_t*>(a.wb);
   uint32_t* sbuf1 = kSingle ? sbuf0 : reinterpret_cast<uint32_t*>(a.wb + 4u * sdp);
   uint4* ring = reinterpret_cast<uint4*>(a.wb + (kSingle ? 4u : 8u) * sdp);   // after the state buffer(s)
@@ -830,6 +848,13 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   const uint32_t* kpos = reinterpret_cast<const uint32_t*>(a.blob + (ALIAS ? H->kpos_off : 0u));
   uint32_t stride0 = 1;
   while (stride0 * 64u < n) stride0 *= 64u;
+  // several waves per trajectory (served queries, latency-bound chains): the
+  // chain's top search level held in registers
+  unsigned long long qtop = 0ull;
+  if constexpr (kMW) {
+    const uint32_t h = stride0 * (lane + 1u);
+    qtop = h <= n ? blob_u64<kChainG>(Q + h) : 0ull;
+  }
   const unsigned long long Qn = Q[n];
   const uint32_t qn_lo = uint32_t(Qn), qn_hi = uint32_t(Qn >> 32);
 
@@ -903,8 +928,21 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
           ring[lane + 64u * uint32_t(r)] = philox(traj, t + my_s[r], my_c2[r], my_c3[r], k0, k1);
     } else if constexpr (ALIAS) {
       for (uint32_t j = lane; j < njobs; j += 64u) ring[j] = philox(traj, t, j, PBN_STREAM_ALIAS, k0, k1);
+    } else if constexpr (kMW) {
+      // several waves: wave 0 draws the first round (job 0, the step's first
+      // chain word, among them); after a barrier every wave reads that word,
+      // and the later rounds, split between the waves, are drawn only for a
+      // step that is not perturbation-only
+      if (wv == 0u) ring[lane] = philox(traj, t, lane ? blk[lane - 1u] : 0u, lane ? PBN_STREAM_SEL : PBN_STREAM_PERT,
+                                        k0, k1);
+      traj_sync();
+      const uint2 pr = *reinterpret_cast<const uint2*>(ring);
+      const uint32_t plo = uniform(pr.x), phi = uniform(pr.y);
+      if (!(phi > qn_hi || (phi == qn_hi && plo >= qn_lo)))
+        for (uint32_t j = 64u * (wv + 1u) + lane; j < njobs; j += 64u * nw)
+          ring[j] = philox(traj, t, blk[j - 1u], PBN_STREAM_SEL, k0, k1);
     } else {
-      fill_step_keyed(ring, blk, njobs, traj, t, lane, k0, k1, qn_lo, qn_hi, 64u * wv, 64u * nw);
+      fill_step_keyed(ring, blk, njobs, traj, t, lane, k0, k1, qn_lo, qn_hi);
     }
     traj_sync();
     if constexpr (ALIAS) {
@@ -980,8 +1018,8 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
           uhi = uniform(pr.y);
         }
         if (lead)
-          walk_chain<(MODE & 2) != 0, kRegState>((static_cast<unsigned long long>(uhi) << 32) | ulo, n, stride0, Q,
-                                                 o2p, traj, t, k0, k1, lane, csb, rst);
+          walk_chain<kChainG, kRegState, false, kMW>((static_cast<unsigned long long>(uhi) << 32) | ulo, n, stride0,
+                                                     Q, o2p, traj, t, k0, k1, lane, csb, rst, qtop);
         traj_sync();
         if constexpr (kRegState)
           z = target_reg(rst);
@@ -1652,7 +1690,8 @@ struct BatchParams {
   uint32_t ntasks;                 // PBN_NONE: one queue of ctl->ntasks tasks, written on the device
   uint32_t wpb;                    // trajectories per task
   uint32_t wpt;                    // waves per trajectory (> 1: one trajectory per workgroup)
-  uint32_t wave_bytes;
+  uint32_t wave_bytes;             // LDS per trajectory: state buffers and ring; with wpt > 1 the chain
+                                   // tables follow them (chain_lds_bytes of the largest network)
   uint32_t gshift;                 // 1: the gather step's shift, passed at run time (see shl_or)
   pbn_batch_ctl* ctl;              // device: queue counters and the step window
   uint32_t nq;                     // queues, 1 .. PBN_BATCH_QUEUES
@@ -1726,6 +1765,7 @@ __global__ void __launch_bounds__(1024) k_batch(BatchParams a, const pbn_work* _
       t.gshift = a.gshift;
       t.wv = MW ? wave : 0u;
       t.nw = MW ? a.wpt : 1u;
+      t.qo = MW ? smem + 16u + a.wave_bytes : nullptr;
       // large launches run without the prefetch: its four VGPRs would take
       // this kernel from five to four waves per SIMD
       run_traj<PM, UM, 0, (PM == 7 ? 1 : 0) | 2 | (PF ? 32 : 0) | (MW ? 256 : 0)>(t);
@@ -2231,6 +2271,7 @@ namespace {
 
 struct BatchShape {
   uint32_t pm = 5, um = 0, wave_bytes = 0;
+  uint32_t chain_bytes = 0;   // LDS copy of the largest network's chain tables
 };
 
 pbn_status batch_shape(const pbn_plan* const* plans, uint32_t nitems, BatchShape& sh) {
@@ -2245,6 +2286,7 @@ pbn_status batch_shape(const pbn_plan* const* plans, uint32_t nitems, BatchShape
     if (p->info.max_fn_parents > 5) sh.pm = 7;
     sh.um = std::max(sh.um, p->info.max_union_bits);
     sh.wave_bytes = std::max(sh.wave_bytes, wave_lds_bytes(p, false));
+    sh.chain_bytes = std::max(sh.chain_bytes, chain_lds_bytes(reinterpret_cast<const pbn_plan_header*>(p->blob.data())->n));
   }
   sh.um = sh.um == 0 ? 0 : sh.um <= 8 ? 8 : 16;
   return PBN_OK;
@@ -2313,7 +2355,8 @@ pbn_status batch_enqueue(const pbn_plan* const* plans, uint32_t nitems, const pb
   BatchShape sh;
   pbn_status st = batch_shape(plans, nitems, sh);
   if (st != PBN_OK) return st;
-  if (16u + wpb * sh.wave_bytes > kLdsMax) return fail(PBN_ELDS, "states and rings of one workgroup exceed LDS");
+  const uint32_t lds = 16u + wpb * sh.wave_bytes + (wpt > 1u ? sh.chain_bytes : 0u);
+  if (lds > kLdsMax) return fail(PBN_ELDS, "states, rings and chain tables of one workgroup exceed LDS");
   BatchParams p{};
   p.items = d_items;
   p.tasks = d_tasks;
@@ -2326,7 +2369,6 @@ pbn_status batch_enqueue(const pbn_plan* const* plans, uint32_t nitems, const pb
   p.ctl = d_ctl;
   p.nq = nq;
   p.q = q;
-  const uint32_t lds = 16u + wpb * sh.wave_bytes;
   if (sh.pm == 5) {
     if (sh.um == 0) return launch_batch_t<5, 0>(p, lds, s, sched);
     if (sh.um == 8) return launch_batch_t<5, 8>(p, lds, s, sched);

@@ -217,10 +217,14 @@ class Server:
 
     def footprint(self, plan, wpt=1):
         """(waves, LDS bytes, HBM bytes) of one query: wpt waves per trajectory
-        share its LDS state and ring."""
+        share its LDS state and ring, and with wpt > 1 a copy of the chain
+        tables (Q and the position map, 12 bytes a node)."""
         ring = plan.info["n_jobs"]
         fill = min(32, plan.fill_steps) if ring <= 64 else 1
         traj_lds = 2 * plan.info["state_bytes"] + 16 * (fill * ring if ring <= 64 else ring)
+        if wpt > 1:
+            n = plan.info["n"]
+            traj_lds += ((8 * (n + 1) + 15) & ~15) + ((4 * n + 15) & ~15)
         hbm = self.ntraj * (4 * plan.info["state_words"] + 24)
         return np.array([self.ntraj * wpt, self.ntraj * traj_lds, hbm], dtype=np.float64)
 
