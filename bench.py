@@ -46,6 +46,7 @@ PHILOX_SLOTS = 60                  # 10 rounds x (2 full-rate 32x32->64 multipli
 SAME_CODE_SOURCES = (
     "aa6f152497d6e50cc4a92aeb4152bf30781304463cff7e9197211ea1ab888043",   # counters taken here
     "8af1d8b60e604c5e17092e9b7ffaf2e6f83dafba80b77d3fbc766f017954f561",   # several waves per trajectory in k_batch
+    "11113b1b956c9c8b93568c092fe0c3cfcd7ae047f79a90474a6289bde28f37c0",   # served multi-wave lanes: split fill, chain tables in LDS
 )
 MEASURED_TRAFFIC = {
     # per launch of the product plan: FETCH_SIZE and WRITE_SIZE (KiB per
