@@ -342,3 +342,29 @@ def test_waves_per_trajectory_leave_results_unchanged():
     c = runs[-1][1][k]
     assert np.array_equal(c[:, :, 0], ref["hits"]) and np.array_equal(c[:, :, 1], ref["n01"])
     assert np.array_equal(c[:, :, 2], ref["n10"])
+
+
+def test_waves_per_trajectory_with_a_three_level_chain_search():
+    """A network of more than 4096 nodes: the chain's search runs three
+    radix-64 levels (the top one from registers, the others from the LDS copy
+    of Q), with about five flips per step at p = 1e-3; four waves per
+    trajectory give the one-wave results, and the oracle's."""
+    net = ps.medium_c2(n=5000, p=1e-3, seed=2941)
+    tgs = [ps.non_leaf_targets(net, 2)]
+    plan = api.Plan(net, interest=[a for a, _ in tgs[0]], reduce=1, group=0)
+    items = [(plan, 4100, 3, tgs)]
+    say("[gpu] batch waves per trajectory, n = 5000")
+    runs = []
+    for wpt in (1, 4):
+        b = api.Batch(items, count_from=5, waves_per_block=4, waves_per_traj=wpt)
+        b.init_states()
+        b.set_window(0, 40)
+        b.launch()
+        torch.cuda.synchronize()
+        runs.append((b.states[0].cpu().numpy(), b.counts[0].cpu().numpy(), b))
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+    ref = osim.run(net, 4100, np.arange(3), 40, targets=tgs, count_from=5)
+    orig = api.unpack_bits(api.to_original(plan, runs[1][2].states[0]).cpu().numpy(), plan.n)
+    kept = plan.node_pos() != NONE
+    assert np.array_equal(orig[:, kept], ref["state"][:, kept])
+    assert np.array_equal(runs[1][1][:, :, 0], ref["hits"])
