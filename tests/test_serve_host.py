@@ -66,3 +66,24 @@ def test_footprint_budget_takes_and_gives_back():
     fp.give(need)
     assert fp.fits(need) and np.allclose(fp.used, need)
     assert fp.exceeds_device(np.array([2000, 1, 1], dtype=np.float64))
+
+
+def test_lane_waves_per_trajectory_follow_the_chunk_class():
+    srv, _ = bare_server([{"n": 100, "p": 1e-4}], [2], chunk=500, chunk_classes=3)
+    srv.wpt = (4, 4, 2)
+    assert [srv.wpt_of(c) for c in (500, 1000, 2000, 4000)] == [4, 4, 2, 2]
+    srv.wpt = (1,)
+    assert [srv.wpt_of(c) for c in (500, 1000, 2000)] == [1, 1, 1]
+
+
+def test_footprint_counts_waves_and_chain_tables_of_multi_wave_lanes():
+    srv = serve.Server.__new__(serve.Server)
+    srv.ntraj = 256
+    plan = types.SimpleNamespace(info={"n_jobs": 100, "state_bytes": 3008, "state_words": 94, "n": 3000},
+                                 fill_steps=1)
+    one = srv.footprint(plan, 1)
+    four = srv.footprint(plan, 4)
+    assert one[0] == 256 and four[0] == 1024                 # waves
+    chain = (8 * 3001 + 15) // 16 * 16 + (4 * 3000 + 15) // 16 * 16
+    assert four[1] - one[1] == 256 * chain                   # LDS: the chain tables of each trajectory
+    assert four[2] == one[2]                                 # HBM: states and counters only
