@@ -75,14 +75,18 @@ def single_launch_states(items, steps):
     return out
 
 
-def test_batch_graph_replays_match_eager_launches():
+@pytest.mark.parametrize("wpt", [1, 2])
+def test_batch_graph_replays_match_eager_launches(wpt):
+    """Graph replays (two captured passes of 100 steps each) give the states
+    and counters of single-network launches, with one or two waves per
+    trajectory; eager work runs between the replays."""
     items, _ = make_items(24, 7, 20, 700, [16, 7, 33], True)
     ref_a = single_launch_states(items, 200)
     ref_b = single_launch_states(items, 400)
-    b = api.Batch(items, waves_per_block=4)
+    b = api.Batch(items, waves_per_block=4, waves_per_traj=wpt)
     b.init_states()
     b.set_window(0, 100)
-    say("[gpu] capture batch graph (2 passes x 100 steps)")
+    say(f"[gpu] capture batch graph (2 passes x 100 steps, {wpt} waves per trajectory)")
     g = b.graph(2)
     torch.cuda.synchronize()
     for replay, ref in ((0, ref_a), (1, ref_b)):
