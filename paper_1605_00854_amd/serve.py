@@ -412,6 +412,7 @@ class Server:
             "wall_s": wall,
             "ticks": self.ticks,
             "lanes": {str(c): lane.launches for c, lane in sorted(self.lanes.items())},
+            "waves_per_traj": {str(c): lane.wpt for c, lane in sorted(self.lanes.items())},
         }
 
 
