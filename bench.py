@@ -588,11 +588,12 @@ def bench_planner_fit(args):
     rows = {}
     for label, nets in (("fit", ps.planner_population(args.planner_fit, 2007)),
                         ("held_out", ps.planner_population(max(3, args.planner_fit // 3), 2008))):
-        xs1, xs2, ys = [], [], []
+        xs1, xs2, ys, rs = [], [], [], []
         for k, net in enumerate(nets):
             tg = [ps.non_leaf_targets(net, 3)]
             interest = [a for a, _ in tg[0]]
             x1, x2, _ = planner.features(net, interest)
+            rs.append(planner.lane_pass_ratio(net, interest))
             plain = api.Plan(net, interest=interest, reduce=0, group=0)
             dt = autotune._probe(torch, plain, plain.targets(tg), 7, ntraj, probe, 4, True)
             r_plain = ntraj * probe * net["n"] / dt
@@ -604,19 +605,26 @@ def bench_planner_fit(args):
             ys.append(max(r_best, r_plain) / r_plain)
             print(f"[planner] {label} {k} n={net['n']} leaf={x1:.3f} D={x2:.2f} speedup={ys[-1]:.3f}",
                   file=sys.stderr, flush=True)
-        rows[label] = (np.array(xs1), np.array(xs2), np.array(ys))
-    x1, x2, y = rows["fit"]
+        rows[label] = (np.array(xs1), np.array(xs2), np.array(ys), np.array(rs))
+    x1, x2, y, r = rows["fit"]
     coeffs, r2 = planner.fit(x1, x2, y)
     cv = planner.cross_validated_r2(x1, x2, y)
-    h1, h2, hy = rows["held_out"]
+    h1, h2, hy, hr = rows["held_out"]
     hp = planner.predict(h1, h2, coeffs)
     hr2 = 1.0 - float(((hy - hp) ** 2).sum()) / float(((hy - hy.mean()) ** 2).sum())
+    # the same form per lane-pass ratio (the device's work comes in 64-lane passes)
+    pcoeffs, pr2 = planner.fit_per_pass(x1, x2, r, y)
+    pcv = planner.cross_validated_r2(x1, x2, y, ratio=r)
+    pp = hr * planner.predict(h1, h2, pcoeffs)
+    phr2 = 1.0 - float(((hy - pp) ** 2).sum()) / float(((hy - hy.mean()) ** 2).sum())
     out = {"metric": "planner speedup model (Equation 7 form) refit on MI355X", "value": r2, "unit": "R^2",
            "n_gpus": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"{args.planner_fit} + {h1.size} synthetic networks, {ntraj} trajectories, "
                                   f"{probe}-step probes"},
            "coeffs": coeffs, "r2": r2, "cv10_r2": cv, "held_out_r2": hr2,
            "held_out_mean_abs_error": float(np.abs(hy - hp).mean()),
+           "per_pass": {"coeffs": pcoeffs, "r2": pr2, "cv10_r2": pcv, "held_out_r2": phr2,
+                        "held_out_mean_abs_error": float(np.abs(hy - pp).mean())},
            "speedup_range": [float(y.min()), float(y.max())],
            "rows": {k: [list(map(float, v)) for v in r] for k, r in rows.items()}}
     print(json.dumps(out))

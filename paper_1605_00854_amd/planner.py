@@ -19,10 +19,10 @@ import numpy as np
 from . import api, autotune
 
 # Equation 7's form refit on MI355X: 72 synthetic networks (n 100-1500, leaf
-# fraction 0-0.9, density 1.0-8.8), speedup of the autotuned plan over the plain
-# kernel at 2048 trajectories (bench.py --planner-fit 72): R^2 0.63,
-# 10-fold cross-validated 0.57, 24 held-out networks 0.72.
-COEFFS = (0.489354, 1.255258, 0.866232, 0.237944, -0.019611)
+# fraction 0.06-0.94, density 1.0-8.8), speedup of the autotuned plan over the
+# plain kernel at 2048 trajectories (bench.py --planner-fit 72): R^2 0.56,
+# 10-fold cross-validated 0.49, 24 held-out networks 0.68.
+COEFFS = (0.589427, 0.991735, 0.975340, 0.220935, -0.018722)
 
 
 def density(net):
@@ -36,6 +36,15 @@ def features(net, interest):
     plan = api.Plan(net, interest=interest, reduce=1, group=0)
     prep = time.perf_counter() - t0
     return 1.0 - plan.info["n_kept"] / int(net["n"]), density(net), prep
+
+
+def lane_pass_ratio(net, interest):
+    """Lane passes of the plain plan over those of the leaf-reduced plan: the
+    step kernel's work comes in whole 64-lane passes, so a reduction pays in
+    steps of ceil(n / 64) / ceil(n' / 64), which x1 alone cannot show."""
+    plain = api.Plan(net, interest=interest, reduce=0, group=0)
+    red = api.Plan(net, interest=interest, reduce=1, group=0)
+    return plain.info["n_passes"] / max(1, red.info["n_passes"])
 
 
 def design(x1, x2):
@@ -60,16 +69,31 @@ def fit(x1, x2, y):
     return tuple(float(v) for v in b), r2
 
 
-def cross_validated_r2(x1, x2, y, folds=10, seed=0):
+def fit_per_pass(x1, x2, ratio, y):
+    """Equation 7's form fit to the speedup per lane-pass ratio (y / ratio),
+    the prediction being ratio times the form; returns the coefficients and
+    the R^2 of that prediction on y itself."""
+    ratio = np.asarray(ratio, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    b, _ = fit(x1, x2, y / ratio)
+    res = y - ratio * predict(x1, x2, b)
+    tot = y - y.mean()
+    return b, 1.0 - float(res @ res) / float(tot @ tot) if float(tot @ tot) > 0 else 1.0
+
+
+def cross_validated_r2(x1, x2, y, folds=10, seed=0, ratio=None):
+    """R^2 of out-of-fold predictions (the paper validates its fit with 10
+    folds); with `ratio`, of the per-lane-pass form (fit_per_pass)."""
     """R^2 of out-of-fold predictions (the paper validates its fit with 10 folds)."""
     x1, x2, y = (np.asarray(v, dtype=np.float64) for v in (x1, x2, y))
+    r = np.ones_like(y) if ratio is None else np.asarray(ratio, dtype=np.float64)
     idx = np.random.default_rng(seed).permutation(y.size)
     pred = np.empty_like(y)
     for f in range(folds):
         test = idx[f::folds]
         train = np.setdiff1d(idx, test)
-        b, _ = fit(x1[train], x2[train], y[train])
-        pred[test] = predict(x1[test], x2[test], b)
+        b, _ = fit(x1[train], x2[train], y[train] / r[train])
+        pred[test] = r[test] * predict(x1[test], x2[test], b)
     res, tot = y - pred, y - y.mean()
     return 1.0 - float(res @ res) / float(tot @ tot)
 

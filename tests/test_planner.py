@@ -22,6 +22,27 @@ def test_fit_recovers_known_coefficients():
     assert planner.predict(0.5, 3.0, b) == pytest.approx(2.89 + 2.71 * 0.5 + 2.40 * 0.25 - 1.65 * 3 + 0.71 * 9)
 
 
+def test_per_pass_fit_recovers_known_coefficients():
+    rng = np.random.default_rng(4)
+    x1 = rng.uniform(0, 0.9, 40)
+    x2 = rng.uniform(1, 8, 40)
+    ratio = rng.choice([1.0, 1.5, 2.0, 3.0], 40)
+    b = (1.1, 0.3, -0.2, 0.05, -0.004)
+    y = ratio * (b[0] + b[1] * x1 + b[2] * x1 ** 2 + b[3] * x2 + b[4] * x2 ** 2)
+    got, r2 = planner.fit_per_pass(x1, x2, ratio, y)
+    assert np.allclose(got, b, rtol=1e-9, atol=1e-9) and r2 == pytest.approx(1.0)
+    assert planner.cross_validated_r2(x1, x2, y, ratio=ratio) == pytest.approx(1.0)
+    # the plain form cannot follow the ratio's steps
+    assert planner.fit(x1, x2, y)[1] < 0.99
+
+
+def test_lane_pass_ratio_counts_64_lane_passes():
+    net = ps.medium_c2(n=200, seed=6, leaf_frac=0.5)
+    interest = [a for a, _ in ps.non_leaf_targets(net, 3)]
+    kept = 200 - len(structure.leaf_nodes(net, interest))
+    assert planner.lane_pass_ratio(net, interest) == pytest.approx(math.ceil(200 / 64) / math.ceil(kept / 64))
+
+
 def test_features_are_leaf_fraction_and_density():
     net = ps.medium_c2(n=120, seed=5)
     interest = [a for a, _ in ps.non_leaf_targets(net, 3)]
