@@ -822,6 +822,25 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
       if (!placed && val) never = true;
     }
   }
+  // one target (the common case): each lane's own care and want bits of
+  // target 0 per register-held pass (0 or 1), so that a step's indicator is
+  // one ballot of the lanes' mismatches, (out ^ want) & care, instead of a
+  // masked compare of every pass's ballot on the target's lane
+  const bool one_target = kBallotTargets && ntg == 1u;
+  uint32_t care_l[NR], want_l[NR];
+  bool never0 = false;
+#pragma unroll
+  for (int p = 0; p < NR; ++p) care_l[p] = want_l[p] = 0u;
+  if constexpr (kBallotTargets) {
+#pragma unroll
+    for (int p = 0; p < NR; ++p) {
+      const uint32_t c = lane < 32u ? uniform(care_lo[p]) >> lane : uniform(care_hi[p]) >> (lane - 32u);
+      const uint32_t w = lane < 32u ? uniform(want_lo[p]) >> lane : uniform(want_hi[p]) >> (lane - 32u);
+      care_l[p] = c & 1u;
+      want_l[p] = w & 1u;
+    }
+    never0 = (__ballot(never) & 1ull) != 0ull;
+  }
   traj_sync();
 
   // fixed Philox job of this lane when one fill covers several steps
@@ -1049,13 +1068,20 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
             for (int p = 0; p < NREG; ++p) store_slot<UM>(nsb, cached[p].info, cached[p].spos, out[p]);
           }
           if constexpr (kBallotTargets) {
-            uint32_t mism = 0u;
+            if (one_target) {
+              uint32_t m = 0u;
 #pragma unroll
-            for (int p = 0; p < NREG; ++p) {
-              const unsigned long long b = __ballot(out[p] != 0u);
-              mism |= masked_xor(uint32_t(b), care_lo[p], want_lo[p]) | masked_xor(uint32_t(b >> 32), care_hi[p], want_hi[p]);
+              for (int p = 0; p < NREG; ++p) m |= (out[p] ^ want_l[p]) & care_l[p];
+              z = !never0 && __ballot(m != 0u) == 0ull;
+            } else {
+              uint32_t mism = 0u;
+#pragma unroll
+              for (int p = 0; p < NREG; ++p) {
+                const unsigned long long b = __ballot(out[p] != 0u);
+                mism |= masked_xor(uint32_t(b), care_lo[p], want_lo[p]) | masked_xor(uint32_t(b >> 32), care_hi[p], want_hi[p]);
+              }
+              z = !never && mism == 0u;
             }
-            z = !never && mism == 0u;
           }
         } else {
           constexpr bool G = (MODE & 2) != 0;

@@ -170,3 +170,29 @@ def test_single_step_launches_count_the_new_state(name):
         prev = hits
     assert np.array_equal(api.unpack_bits(api.to_original(plan, st).cpu().numpy(), plan.n)[:, plan.node_pos() != NONE],
                           s[:, plan.node_pos() != NONE])
+
+
+@pytest.mark.parametrize("n,seed", [(10, 51), (37, 52), (100, 53)])
+def test_one_target_counts_equal_those_of_a_target_among_several(n, seed):
+    """Plans whose slot data stay in registers count one target with a ballot
+    of the lanes' own mismatches, and several targets with a masked compare of
+    each pass's ballot per target lane: the same target counted alone and
+    beside another gets the same hits and changes, which match the oracle's."""
+    net = ps.medium_c2(n=n, p=2e-2, seed=seed)
+    t1 = ps.non_leaf_targets(net, 3)
+    t2 = [(t1[0][0], 0)]
+    interest = sorted({a for a, _ in t1})
+    plan = api.Plan(net, interest=interest, reduce=1, group=0)
+    assert plan.info["n_passes"] <= 2
+    runs = []
+    for tgs in ([t1], [t1, t2]):
+        tg = plan.targets(tgs)
+        st = api.state_init(plan, 9, 48)
+        cn = api.new_counts(len(tgs), 48)
+        api.simulate(plan, 9, st, cn, tg, 0, 300, count_from=20)
+        runs.append(cn.cpu().numpy())
+    assert np.array_equal(runs[0][0], runs[1][0])
+    ref = osim.run(net, 9, np.arange(48), 300, targets=[t1, t2], count_from=20)
+    for k in range(2):
+        assert np.array_equal(runs[1][k][:, 0], ref["hits"][k]) and np.array_equal(runs[1][k][:, 1], ref["n01"][k])
+        assert np.array_equal(runs[1][k][:, 2], ref["n10"][k])
