@@ -44,9 +44,7 @@ PHILOX_SLOTS = 60                  # 10 rounds x (2 full-rate 32x32->64 multipli
 # instructions (their assembly compared instance by instance, labels aside)
 # with the same host plan builder.
 SAME_CODE_SOURCES = (
-    "aa6f152497d6e50cc4a92aeb4152bf30781304463cff7e9197211ea1ab888043",   # counters taken here
-    "8af1d8b60e604c5e17092e9b7ffaf2e6f83dafba80b77d3fbc766f017954f561",   # several waves per trajectory in k_batch
-    "11113b1b956c9c8b93568c092fe0c3cfcd7ae047f79a90474a6289bde28f37c0",   # served multi-wave lanes: split fill, chain tables in LDS
+    "96b5f63677dfb4de9a7cbe99aea9c6b59f49724fce4ae7323b25bb8d01d33968",   # counters taken here
 )
 MEASURED_TRAFFIC = {
     # per launch of the product plan: FETCH_SIZE and WRITE_SIZE (KiB per
@@ -54,10 +52,10 @@ MEASURED_TRAFFIC = {
     # device copy reads for them (fetch 131 088 KiB, write 262 144 KiB)
     "C2": {"kernel_source_sha256": SAME_CODE_SOURCES,
            "plan": {"group": 0, "reduce": 1},
-           "fetch_kib": 234.125, "fetch_factor": 2.0, "write_kib": 176.0, "write_factor": 1.0},
+           "fetch_kib": 233.0, "fetch_factor": 2.0, "write_kib": 176.0, "write_factor": 1.0},
     "C3": {"kernel_source_sha256": SAME_CODE_SOURCES,
            "plan": {"group": 1, "max_group_nodes": 4, "max_parent_bits": 5, "reduce": 1},
-           "fetch_kib": 12135.375, "fetch_factor": 2.0, "write_kib": 22016.0, "write_factor": 1.0},
+           "fetch_kib": 12132.25, "fetch_factor": 2.0, "write_kib": 22016.0, "write_factor": 1.0},
 }
 
 
