@@ -45,6 +45,7 @@ PHILOX_SLOTS = 60                  # 10 rounds x (2 full-rate 32x32->64 multipli
 # with the same host plan builder.
 SAME_CODE_SOURCES = (
     "96b5f63677dfb4de9a7cbe99aea9c6b59f49724fce4ae7323b25bb8d01d33968",   # counters taken here
+    "d0a1234e9adf49cd7c8fe3c0b6ddf868809dba4a5b8f3c73b475d4a800cd960c",   # a compile-time check added; every kernel's code unchanged
 )
 MEASURED_TRAFFIC = {
     # per launch of the product plan: FETCH_SIZE and WRITE_SIZE (KiB per

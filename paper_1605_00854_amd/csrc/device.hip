@@ -701,7 +701,8 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   constexpr bool kRegState = (MODE & 8) != 0;
   static_assert(!kRegState || (NREG == 1 && UM == 0 && !ALIAS), "register state: one-pass FN-only keyed plans");
   constexpr bool kMW = (MODE & 256) != 0;
-  static_assert(!kMW || (NREG == 0 && !ALIAS), "several waves per trajectory: streaming keyed plans");
+  static_assert(!kMW || (NREG == 0 && !ALIAS && (MODE & 2) != 0),
+                "several waves per trajectory: streaming keyed plans with the image in global memory");
   const uint32_t wv = kMW ? a.wv : 0u, nw = kMW ? a.nw : 1u;
   const bool lead = !kMW || wv == 0u;   // counts targets and walks the chain
   // orders the trajectory's LDS traffic: its own lanes, or all its waves
