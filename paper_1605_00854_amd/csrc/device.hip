@@ -826,13 +826,16 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
   // one target (the common case): each lane's own care and want bits of
   // target 0 per register-held pass (0 or 1), so that a step's indicator is
   // one ballot of the lanes' mismatches, (out ^ want) & care, instead of a
-  // masked compare of every pass's ballot on the target's lane
-  const bool one_target = kBallotTargets && ntg == 1u;
+  // masked compare of every pass's ballot on the target's lane; fewer vector
+  // instructions for many waves, but one more branch in the step, so not for
+  // the register-held state (one latency-bound trajectory)
+  constexpr bool kOneTargetForm = kBallotTargets && !kRegState;
+  const bool one_target = kOneTargetForm && ntg == 1u;
   uint32_t care_l[NR], want_l[NR];
   bool never0 = false;
 #pragma unroll
   for (int p = 0; p < NR; ++p) care_l[p] = want_l[p] = 0u;
-  if constexpr (kBallotTargets) {
+  if constexpr (kOneTargetForm) {
 #pragma unroll
     for (int p = 0; p < NR; ++p) {
       const uint32_t c = lane < 32u ? uniform(care_lo[p]) >> lane : uniform(care_hi[p]) >> (lane - 32u);
@@ -1069,7 +1072,7 @@ __device__ __forceinline__ void run_traj(const TrajArgs& a) {
             for (int p = 0; p < NREG; ++p) store_slot<UM>(nsb, cached[p].info, cached[p].spos, out[p]);
           }
           if constexpr (kBallotTargets) {
-            if (one_target) {
+            if (kOneTargetForm && one_target) {
               uint32_t m = 0u;
 #pragma unroll
               for (int p = 0; p < NREG; ++p) m |= (out[p] ^ want_l[p]) & care_l[p];
