@@ -47,6 +47,7 @@ SAME_CODE_SOURCES = (
     "96b5f63677dfb4de9a7cbe99aea9c6b59f49724fce4ae7323b25bb8d01d33968",   # counters taken here
     "d0a1234e9adf49cd7c8fe3c0b6ddf868809dba4a5b8f3c73b475d4a800cd960c",   # a compile-time check added; every kernel's code unchanged
     "97ee4dcda3638f74a8698679d3dd1de24e569094665c0907c1019a20966b3538",   # register-state kernels back to their previous form; the others unchanged
+    "3af68a17e4e0cf6b992298558252103a962552b83cfa04b94025f4c4e5673817",   # host fallback for chain tables beyond LDS; kernels unchanged
 )
 MEASURED_TRAFFIC = {
     # per launch of the product plan: FETCH_SIZE and WRITE_SIZE (KiB per

@@ -488,7 +488,10 @@ double pbn_normal_quantile(double p);
  *   W waves of one workgroup advance each trajectory together, sharing its
  *   state and draws in LDS and splitting each step's lane passes, for a
  *   shorter step latency on networks of many passes; tasks must then hold one
- *   trajectory (waves_per_block = 1).  Results do not depend on W.
+ *   trajectory (waves_per_block = 1).  The W waves keep a copy of the chain
+ *   tables (12 bytes a node) in LDS; a launch whose largest network's tables
+ *   do not fit beside its states runs one wave per trajectory instead.
+ *   Results do not depend on W.
  * pbn_batch_graph_create: capture `passes` consecutive launches into a graph,
  *   replayed by pbn_graph_launch (each replay advances by passes * nsteps).
  * Errors: PBN_EINVAL, PBN_ELDS (one workgroup's states exceed LDS), PBN_EHIP. */

@@ -2385,8 +2385,12 @@ pbn_status batch_enqueue(const pbn_plan* const* plans, uint32_t nitems, const pb
   BatchShape sh;
   pbn_status st = batch_shape(plans, nitems, sh);
   if (st != PBN_OK) return st;
+  // several waves per trajectory copy the chain tables into LDS; when those of
+  // the batch's largest network do not fit beside its states and ring, the
+  // launch runs one wave per trajectory (the same results)
+  if (wpt > 1u && 16u + wpb * sh.wave_bytes + sh.chain_bytes > kLdsMax) wpt = 1u;
   const uint32_t lds = 16u + wpb * sh.wave_bytes + (wpt > 1u ? sh.chain_bytes : 0u);
-  if (lds > kLdsMax) return fail(PBN_ELDS, "states, rings and chain tables of one workgroup exceed LDS");
+  if (lds > kLdsMax) return fail(PBN_ELDS, "states and rings of one workgroup exceed LDS");
   BatchParams p{};
   p.items = d_items;
   p.tasks = d_tasks;

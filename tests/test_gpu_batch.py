@@ -372,3 +372,22 @@ def test_waves_per_trajectory_with_a_three_level_chain_search():
     kept = plan.node_pos() != NONE
     assert np.array_equal(orig[:, kept], ref["state"][:, kept])
     assert np.array_equal(runs[1][1][:, :, 0], ref["hits"])
+
+
+def test_waves_per_trajectory_fall_back_when_the_chain_tables_do_not_fit():
+    """A 13 000-node network: its chain tables (12 bytes a node) do not fit in
+    LDS beside its states and ring, so a launch asked for four waves per
+    trajectory runs one; the results equal those of one wave."""
+    net = ps.medium_c2(n=13000, p=1e-4, seed=2951)
+    tgs = [ps.non_leaf_targets(net, 2)]
+    plan = api.Plan(net, interest=[a for a, _ in tgs[0]], reduce=1, group=0)
+    say("[gpu] batch waves per trajectory, n = 13000 (chain tables beyond LDS)")
+    runs = []
+    for wpt in (1, 4):
+        b = api.Batch([(plan, 4200, 2, tgs)], count_from=3, waves_per_block=1, waves_per_traj=wpt)
+        b.init_states()
+        b.set_window(0, 30)
+        b.launch()
+        torch.cuda.synchronize()
+        runs.append((b.states[0].cpu().numpy(), b.counts[0].cpu().numpy()))
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
