@@ -114,3 +114,31 @@ def test_launch_rejects_bad_waves_per_trajectory(batch, wpb, wpt):
     st = lib().pbn_batch_launch(arr, 1, fake, fake, fake, 10, None, 1, fake, wpb, wpt, None)
     assert st == EINVAL
     assert b"waves_per_traj" in lib().pbn_last_error()
+
+
+@pytest.mark.parametrize("nqueues", [5, 64])
+def test_schedule_equals_a_longest_processing_time_deal(batch, nqueues):
+    """The queue of every network, recomputed: networks in order of per-step
+    cost (largest first, stable on ties), each dealt to the queue with the
+    least work so far (work = cost x tasks; ties: the lowest queue)."""
+    plans, arr, ntraj = batch
+    tasks, first, qf = api.batch_schedule(arr, ntraj, WPB, nqueues)
+    order = sorted(range(len(plans)), key=lambda k: -cost(plans[k]))
+    load = [0] * nqueues
+    want = {}
+    for k in order:
+        j = min(range(nqueues), key=lambda q: (load[q], q))
+        want[k] = j
+        load[j] += cost(plans[k]) * ((int(ntraj[k]) + WPB - 1) // WPB)
+    got = {}
+    for j in range(nqueues):
+        for k in tasks[qf[j]:qf[j + 1]]:
+            got[int(k)] = j
+    assert got == want
+    # within a queue, networks appear in the deal's order
+    for j in range(nqueues):
+        seen = []
+        for k in tasks[qf[j]:qf[j + 1]]:
+            if not seen or seen[-1] != int(k):
+                seen.append(int(k))
+        assert seen == [k for k in order if want[k] == j]
