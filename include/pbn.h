@@ -508,11 +508,13 @@ typedef struct pbn_work {
 
 #define PBN_BATCH_QUEUES 64
 
+/* Control block of batched launches (device memory, caller-owned; the caller
+ * sets step0 and nsteps, the library the rest). */
 typedef struct pbn_batch_ctl {
-  uint32_t step0;
-  uint32_t nsteps;
+  uint32_t step0;    /* first step of the next launch's window (advanced by each launch) */
+  uint32_t nsteps;   /* steps per launch */
   uint32_t ntasks;   /* written by pbn_batch_launch_noalloc's own schedule; unused otherwise */
-  uint32_t reserved;
+  uint32_t reserved; /* unused (keeps the counters 16-byte aligned) */
   uint32_t next_task[PBN_BATCH_QUEUES];   /* claim counters of the queues, reset by each launch */
 } pbn_batch_ctl;
 
